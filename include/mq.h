@@ -1,0 +1,243 @@
+/*
+ * mq.h -- C ABI of the batched eddy-current UQ library (libmq.so, HIP, gfx950).
+ *
+ * Operations (Hahn and Schoeps, "Multi-Level Monte Carlo sampling with
+ * Parallel-in-Time Integration for Uncertainty Quantification in Electric
+ * Machine Simulation"):
+ *   fem_setup       Section II-A, Eqs. (1)-(5): 2-D A-formulation, P1 elements
+ *                   (w_i = N_i e_z), M_sigma, K_nu and r(t) on a structured mesh.
+ *   mlmc_level_run  Section II-A, Eqs. (6)-(7) (implicit Euler) for every sample
+ *                   of one MLMC level, on the level's time grid and on the next
+ *                   coarser one with the same input (Section II-B, coupled
+ *                   differences), and the mean Joule loss of Eq. (26).
+ *   parareal_run    Section II-C, Eq. (12): Parareal for samples of the finest
+ *                   level, batched over samples and time slices.
+ *   mlmc_estimate   Section II-B, Eq. (9): the MLMC estimator (with level means
+ *                   and level variances).
+ *
+ * Conventions
+ *  - Every function returns an int status: MQ_OK (0); a positive warning
+ *    (results valid, see the per-instance flags in mq_run_stats); or a negative
+ *    error (outputs unspecified).  mq_last_error() returns a message for the
+ *    last non-zero status of the calling thread.  No C++ exception crosses the
+ *    boundary.
+ *  - Array arguments marked "device" are HIP device pointers on the device that
+ *    was current at fem_setup / mq_server_create; arrays marked "host" are host
+ *    pointers.  The caller owns every array; the library owns its handles and
+ *    the device memory it allocates, and frees both in the *_destroy calls.
+ *  - `stream` arguments are hipStream_t passed as void* (NULL: default stream).
+ *    Compute calls run on the problem's stream and return after the stream
+ *    has finished (results are ready on return).
+ *  - Inputs are validated before any launch; invalid sizes return
+ *    MQ_ERR_INVALID_ARG, non-finite xi MQ_ERR_NONFINITE.
+ *  - Handles are not thread-safe; a server accepts mq_submit from any thread.
+ *  - Times: t_k = k dt from the integer step index, a(t_0) = 0, the source is
+ *    evaluated at t_{k+1}.  The state is solved in increment form
+ *    (M/dt + K) d_k = r(t_{k+1}) - K a_k, a_{k+1} = a_k + d_k, which is
+ *    algebraically Eq. (7); Q = (1/T) sum_k d_k^T M d_k / dt (Eq. (26)).
+ */
+#ifndef MQ_H
+#define MQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MQ_OK = 0,
+  MQ_WARN_NOT_CONVERGED = 1, /* some instance hit an iteration cap (flags in stats) */
+  MQ_ERR_INVALID_ARG = -1,
+  MQ_ERR_NO_DEVICE = -2,
+  MQ_ERR_OUT_OF_MEMORY = -3,
+  MQ_ERR_DEVICE = -4,
+  MQ_ERR_NONFINITE = -5,
+  MQ_ERR_BUSY = -6,
+  MQ_ERR_CANCELLED = -7
+};
+
+enum { MQ_MAT_LOGNORMAL_SCALAR = 0, MQ_MAT_KL = 1, MQ_MAT_NONLINEAR = 2 };
+enum { MQ_PREC_FP64 = 0, MQ_PREC_MIXED = 1 };
+enum { MQ_APPLY_A = 0, MQ_APPLY_M = 1, MQ_APPLY_K = 2 };
+/* kernel path selection (mq_problem_desc.path) */
+enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2 };
+
+/* Problem description (Section II-A; materials per the workload).
+ * Unit square, n_nodes x n_nodes nodes, each cell split along "/" into two P1
+ * triangles; A = 0 on the boundary.  Elements whose centroid lies in
+ * `conductor` (inclusive) are conducting; elsewhere sigma = 0, nu = nu_air.
+ * The source J(t) = J0 sin(2 pi freq t) acts on elements whose centroid x lies
+ * in [strip[0], strip[1]].  Conductor materials by kind:
+ *  LOGNORMAL_SCALAR: sigma = sigma0 exp(s_sigma xi_0), nu = nu_cond exp(s_nu xi_1)
+ *  KL:  ln sigma_e = ln sigma0 + s_kl sum_k sqrt(lam_k) phi_k(c_e) xi_k, nu = nu_cond,
+ *       separable exponential covariance exp(-|dx|/corr_len - |dy|/corr_len)
+ *       on the conductor rectangle, n_modes largest modes, c_e = centroid.
+ *  NONLINEAR: sigma = sigma0, nu(|B|) = k1' exp(k2' |B|^2) + k3',
+ *       k_i' = k_i exp(s_k xi_i), solved per step by Picard iteration
+ *       (||a^(i+1) - a^(i)|| <= picard_tol ||a^(i+1)||, at most picard_max).
+ * Linear solves: Jacobi-preconditioned CG inside iterative refinement; a step
+ * is converged when ||b - (M/dt + K) d||_2 <= tol ||b||_2 in FP64.  The inner
+ * CG runs in FP64 (MQ_PREC_FP64) or FP32 (MQ_PREC_MIXED) to inner_rtol
+ * relative to its own initial residual, at most max_iter iterations per
+ * solve and max_sweeps refinement sweeps per step. */
+typedef struct mq_problem_desc {
+  int32_t n_nodes;
+  int32_t material;
+  int32_t precision;
+  int32_t path;
+  double conductor[4]; /* x0, x1, y0, y1 */
+  double strip[2];     /* x0, x1 */
+  double J0, freq;
+  double sigma0, nu_cond, nu_air;
+  double s_sigma, s_nu;
+  int32_t n_modes, picard_max;
+  double corr_len, s_kl;
+  double k1, k2, k3, s_k, picard_tol;
+  double tol, inner_rtol;
+  int32_t max_iter, max_sweeps;
+} mq_problem_desc;
+
+typedef struct mq_problem mq_problem;
+
+typedef struct mq_problem_info {
+  int32_t n_nodes, n_dof, pitch, n_xi;
+  int32_t box[4];        /* interior-node box [x0, x1) x [y0, y1) of sample-dependent rows */
+  int32_t resident_ok;   /* 1 if the register/LDS-resident path fits this mesh/precision */
+  int32_t lds_bytes;     /* LDS per workgroup of the resident path */
+  int32_t n_modes_used;
+  double kl_lambda[16];  /* 2-D KL eigenvalues in use (KL material) */
+} mq_problem_info;
+
+/* Per-call statistics (host struct, nullable). */
+typedef struct mq_run_stats {
+  int64_t n_instances;
+  int64_t sample_steps;        /* implicit Euler steps executed (all instances) */
+  int64_t inner_iters;         /* CG iterations summed over instances */
+  int64_t sweeps;              /* refinement sweeps summed over instances */
+  int64_t picard_iters;        /* Picard iterations summed (nonlinear) */
+  int32_t max_inner_per_step;  /* largest inner-iteration count of any step */
+  int32_t n_not_converged;     /* instances that hit a cap */
+  int32_t n_failed;            /* instances with a non-finite residual */
+  int32_t path;                /* MQ_PATH_RESIDENT or MQ_PATH_STREAMING */
+  int32_t grid, block;         /* launch shape of the time-stepping kernel */
+  double kernel_ms;            /* device time of the time-stepping launches */
+  double total_ms;             /* wall time of the call */
+} mq_run_stats;
+
+/* One MLMC level (Section II-B): every sample runs steps_per_period *
+ * n_periods implicit Euler steps of dt = 1/(freq steps_per_period) and, if
+ * coarse_steps_per_period > 0, the coupled coarse run with the same xi. */
+typedef struct mq_level_desc {
+  int32_t steps_per_period;
+  int32_t coarse_steps_per_period; /* 0 at level 0 (Q_{-1} = 0) */
+  int32_t n_periods;
+  int32_t reserved;
+} mq_level_desc;
+
+/* Parareal (Section II-C): [0, n_periods/freq] split into n_slices slices;
+ * fine F = fine_steps_per_slice IE steps per slice, coarse C =
+ * coarse_steps_per_slice IE steps per slice.  Iterate until the largest
+ * relative interface jump ||F_n - U_n|| / ||F_n|| <= tol or k_max iterations
+ * (fixed_k > 0: exactly fixed_k iterations, no tolerance test). */
+typedef struct mq_parareal_desc {
+  int32_t n_periods, n_slices, fine_steps_per_slice, coarse_steps_per_slice;
+  int32_t k_max, fixed_k;
+  double tol;
+} mq_parareal_desc;
+
+const char* mq_last_error(void);
+int mq_version(void);
+
+/* Build the mesh, masks, KL basis, load shape and device tables.
+ * d: host; stream: hipStream_t or NULL; *out receives the handle.
+ * Errors: MQ_ERR_INVALID_ARG (n_nodes < 3, bad boxes, tolerances), MQ_ERR_NO_DEVICE,
+ * MQ_ERR_OUT_OF_MEMORY. */
+int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out);
+int mq_problem_destroy(mq_problem* p);
+int mq_ndof(const mq_problem* p, int64_t* nd);
+int mq_problem_info_get(const mq_problem* p, mq_problem_info* info);
+
+/* One MLMC level for n_samples samples.
+ * xi: device [n_samples][n_xi] FP64.  q_fine: device [n_samples] (Q on the
+ * level's grid).  q_coarse: device [n_samples] or NULL; required when
+ * lv->coarse_steps_per_period > 0.  final_state: device [n_samples][n_dof] or
+ * NULL (fine-run end state, interior DoF order (j-1)(N-2)+(i-1)).  st: host or NULL.
+ * Returns MQ_WARN_NOT_CONVERGED if any instance hit a cap. */
+int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                   double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st);
+
+/* Several levels in ONE persistent launch (instances of all levels share the
+ * device work queue, longest first).  lv, n_samples, xi, q_fine, q_coarse are
+ * host arrays of n_levels entries; the pointers inside are device pointers as
+ * in mlmc_level_run (q_coarse[l] may be NULL only where lv[l] has no coarse run). */
+int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
+                        const int32_t* n_samples, const double* const* xi,
+                        double* const* q_fine, double* const* q_coarse, mq_run_stats* st);
+
+/* Parareal for n_samples samples at once (samples x slices batched).
+ * xi: device [n_samples][n_xi]; q: device [n_samples] (Q from the final
+ * per-slice fine sums); iters: device int32 [n_samples] (K per sample);
+ * final_state: device [n_samples][n_dof] or NULL; st: host or NULL.
+ * Returns MQ_WARN_NOT_CONVERGED if some sample reached k_max above tol. */
+int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
+                 double* q, int32_t* iters, double* final_state, mq_run_stats* st);
+
+/* Eq. (9) in FP64 on the device with a fixed summation order.
+ * n_per_level: host [n_levels]; q_fine, q_coarse: host arrays of device
+ * pointers (q_coarse[0] ignored, Q_{-1} = 0).  out: device [1 + 2 n_levels] =
+ * {E, Y_0..Y_L, V_0..V_L} (V_l with N_l - 1; 0 when N_l = 1).  stream: hipStream_t or NULL. */
+int mlmc_estimate(int32_t n_levels, const int32_t* n_per_level, const double* const* q_fine,
+                  const double* const* q_coarse, double* out, void* stream);
+
+/* Test hook: y = which(xi) x with which in {A = M/dt + K, M, K} for n samples.
+ * xi device [n][n_xi]; x, y device [n][n_dof] FP64 (interior DoF order). */
+int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const double* xi,
+                   const double* x, double* y);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of independent sample solves (linear materials, mixed
+ * meshes).  A request names its mesh (n_nodes), time grid and KL input.  The
+ * server admits requests in arrival order while their device footprint fits
+ * hbm_budget_bytes and fewer than max_inflight are running; admitted requests
+ * are launched at once on one of its streams and overlap with those already
+ * on the device; finished ones are reported by mq_poll. */
+typedef struct mq_server_desc {
+  mq_problem_desc base;      /* material/precision/tolerances; n_nodes ignored */
+  int64_t hbm_budget_bytes;
+  int32_t max_inflight;
+  int32_t n_streams;
+  int32_t max_batch;         /* requests fused into one launch at most */
+  int32_t reserved;
+} mq_server_desc;
+
+typedef struct mq_request {
+  int32_t n_nodes, steps_per_period, n_periods, n_xi;
+  double xi[16];
+  uint64_t user_id;
+} mq_request;
+
+typedef struct mq_result {
+  uint64_t ticket, user_id;
+  double q;
+  int32_t status;            /* MQ_OK, MQ_WARN_NOT_CONVERGED or a negative error */
+  int32_t inner_iters;
+  int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock ns */
+} mq_result;
+
+typedef struct mq_server mq_server;
+int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out);
+/* Queue a request (host struct); *ticket identifies it in mq_poll.
+ * MQ_ERR_BUSY if the request alone exceeds the HBM budget. */
+int mq_submit(mq_server* s, const mq_request* rq, uint64_t* ticket);
+/* Launch what can be admitted, then copy up to cap finished results to out
+ * (host) and set *n_out.  Non-blocking. */
+int mq_poll(mq_server* s, mq_result* out, int32_t cap, int32_t* n_out);
+/* Number of requests queued or running. */
+int mq_server_pending(const mq_server* s, int32_t* n);
+int mq_server_destroy(mq_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MQ_H */

@@ -1,0 +1,11 @@
+"""Batched MLMC + Parareal eddy-current UQ on MI355X (Python binding of libmq).
+
+The binding only marshals arguments: torch CUDA/HIP tensors provide device
+memory and streams; every step of the hot path (assembly, implicit Euler with
+CG, Joule-loss accumulation, Parareal, MLMC sums) runs in the HIP library.
+"""
+from .api import (  # noqa: F401
+    Problem, default_desc, mlmc_estimate, mlmc_level_run, mlmc_multilevel_run, parareal_run,
+    debug_apply, Server,
+)
+from ._lib import MQError, load  # noqa: F401

@@ -1,0 +1,217 @@
+"""Thin torch-facing wrappers of the libmq C ABI (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+# Solver defaults per precision: (outer FP64 tolerance on ||b - A d|| / ||b||,
+# inner CG relative tolerance, inner iteration cap, refinement sweep cap).
+SOLVER_DEFAULTS = {
+    L.MQ_PREC_FP64: dict(tol=1e-12, inner_rtol=1e-9, max_iter=20000, max_sweeps=10),
+    L.MQ_PREC_MIXED: dict(tol=1e-10, inner_rtol=1e-5, max_iter=20000, max_sweeps=10),
+}
+
+
+def default_desc(problem, precision: int, path: int = L.MQ_PATH_AUTO, **solver) -> L.ProblemDesc:
+    """Fill the C problem description from a `workloads.Problem`."""
+    m = problem.material
+    d = L.ProblemDesc()
+    d.n_nodes = problem.n_nodes
+    d.material = m.kind
+    d.precision = precision
+    d.path = path
+    for i, v in enumerate(problem.conductor):
+        d.conductor[i] = v
+    d.strip[0], d.strip[1] = problem.strip
+    d.J0, d.freq = problem.J0, problem.freq
+    d.sigma0, d.nu_cond, d.nu_air = m.sigma0, m.nu_cond, m.nu_air
+    d.s_sigma, d.s_nu = m.s_sigma, m.s_nu
+    d.n_modes, d.corr_len, d.s_kl = m.n_modes, m.corr_len, m.s_kl
+    d.k1, d.k2, d.k3, d.s_k = m.k1, m.k2, m.k3, m.s_k
+    d.picard_tol, d.picard_max = m.picard_tol, m.picard_max
+    sv = dict(SOLVER_DEFAULTS[precision])
+    sv.update(solver)
+    d.tol, d.inner_rtol = sv["tol"], sv["inner_rtol"]
+    d.max_iter, d.max_sweeps = sv["max_iter"], sv["max_sweeps"]
+    return d
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(x, shape=None) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if shape is not None:
+        t = t.reshape(shape)
+    return t.to("cuda").contiguous()
+
+
+class Problem:
+    """Handle of one mesh/material/solver set-up (fem_setup)."""
+
+    def __init__(self, problem, precision: int, path: int = L.MQ_PATH_AUTO, **solver):
+        self.lib = L.load()
+        self.spec = problem
+        self.desc = default_desc(problem, precision, path, **solver)
+        h = C.c_void_p()
+        L.check(self.lib.fem_setup(C.byref(self.desc), _stream(), C.byref(h)))
+        self.h = h
+        info = L.ProblemInfo()
+        L.check(self.lib.mq_problem_info_get(self.h, C.byref(info)))
+        self.info = info
+        self.n_dof = info.n_dof
+        self.n_xi = info.n_xi
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mq_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def path(self) -> int:
+        return L.MQ_PATH_RESIDENT if (self.desc.path != L.MQ_PATH_STREAMING and self.info.resident_ok) else L.MQ_PATH_STREAMING
+
+
+def mlmc_level_run(prob: Problem, steps_per_period: int, coarse_steps_per_period: int, n_periods: int,
+                   xi, want_state: bool = False):
+    """Returns (q_fine, q_coarse or None, final_state or None, status, stats dict)."""
+    xi_d = _dev_f64(xi).reshape(-1, prob.n_xi).contiguous()
+    n = xi_d.shape[0]
+    qf = torch.empty(n, dtype=torch.float64, device="cuda")
+    qc = torch.empty(n, dtype=torch.float64, device="cuda") if coarse_steps_per_period > 0 else None
+    fs = torch.empty((n, prob.n_dof), dtype=torch.float64, device="cuda") if want_state else None
+    lv = L.LevelDesc(steps_per_period, coarse_steps_per_period, n_periods, 0)
+    st = L.RunStats()
+    rc = L.check(prob.lib.mlmc_level_run(prob.h, C.byref(lv), n, _ptr(xi_d), _ptr(qf), _ptr(qc),
+                                         _ptr(fs), C.byref(st)))
+    return qf, qc, fs, rc, st.as_dict()
+
+
+def mlmc_multilevel_run(prob: Problem, levels: Sequence, xis: Sequence):
+    """All levels in one persistent launch.  levels: (spp, coarse_spp, n_periods) tuples.
+    Returns (list of q_fine, list of q_coarse or None, status, stats)."""
+    nl = len(levels)
+    lvs = (L.LevelDesc * nl)()
+    ns = (C.c_int32 * nl)()
+    xs, qfs, qcs = [], [], []
+    for l, (spp, cspp, nper) in enumerate(levels):
+        lvs[l] = L.LevelDesc(spp, cspp, nper, 0)
+        x = _dev_f64(xis[l]).reshape(-1, prob.n_xi).contiguous()
+        ns[l] = x.shape[0]
+        xs.append(x)
+        qfs.append(torch.empty(x.shape[0], dtype=torch.float64, device="cuda"))
+        qcs.append(torch.empty(x.shape[0], dtype=torch.float64, device="cuda") if cspp > 0 else None)
+    px = (C.c_void_p * nl)(*[x.data_ptr() for x in xs])
+    pf = (C.c_void_p * nl)(*[q.data_ptr() for q in qfs])
+    pc = (C.c_void_p * nl)(*[(q.data_ptr() if q is not None else None) for q in qcs])
+    st = L.RunStats()
+    rc = L.check(prob.lib.mlmc_multilevel_run(prob.h, nl, lvs, ns, px, pf, pc, C.byref(st)))
+    return qfs, qcs, rc, st.as_dict()
+
+
+def parareal_run(prob: Problem, n_periods: int, n_slices: int, fine_steps_per_slice: int,
+                 coarse_steps_per_slice: int, k_max: int, tol: float, xi, fixed_k: int = 0,
+                 want_state: bool = False):
+    """Returns (q, iters, final_state or None, status, stats)."""
+    xi_d = _dev_f64(xi).reshape(-1, prob.n_xi).contiguous()
+    n = xi_d.shape[0]
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    it = torch.empty(n, dtype=torch.int32, device="cuda")
+    fs = torch.empty((n, prob.n_dof), dtype=torch.float64, device="cuda") if want_state else None
+    pd = L.PararealDesc(n_periods, n_slices, fine_steps_per_slice, coarse_steps_per_slice, k_max,
+                        fixed_k, tol)
+    st = L.RunStats()
+    rc = L.check(prob.lib.parareal_run(prob.h, C.byref(pd), n, _ptr(xi_d), _ptr(q), _ptr(it),
+                                       _ptr(fs), C.byref(st)))
+    return q, it, fs, rc, st.as_dict()
+
+
+def mlmc_estimate(q_fine: Sequence[torch.Tensor], q_coarse: Sequence[Optional[torch.Tensor]]):
+    """Eq. (9) on the device: returns (E, level means, level variances) as a float64 tensor split."""
+    lib = L.load()
+    nl = len(q_fine)
+    ns = (C.c_int32 * nl)(*[int(q.numel()) for q in q_fine])
+    pf = (C.c_void_p * nl)(*[q.data_ptr() for q in q_fine])
+    pc = (C.c_void_p * nl)(*[(q.data_ptr() if q is not None else None) for q in q_coarse])
+    out = torch.empty(1 + 2 * nl, dtype=torch.float64, device="cuda")
+    L.check(lib.mlmc_estimate(nl, ns, pf, pc, _ptr(out), _stream()))
+    return out[0], out[1:1 + nl], out[1 + nl:]
+
+
+def debug_apply(prob: Problem, which: int, dt: float, xi, x) -> torch.Tensor:
+    xi_d = _dev_f64(xi).reshape(-1, prob.n_xi).contiguous()
+    n = xi_d.shape[0]
+    x_d = _dev_f64(x).reshape(n, prob.n_dof).contiguous()
+    y = torch.empty_like(x_d)
+    L.check(prob.lib.mq_debug_apply(prob.h, which, dt, n, _ptr(xi_d), _ptr(x_d), _ptr(y)))
+    return y
+
+
+class Server:
+    """Continuous-batching request server (mq_server_*)."""
+
+    def __init__(self, base_problem, precision: int, hbm_budget_bytes: int, max_inflight: int = 1024,
+                 n_streams: int = 4, max_batch: int = 64, **solver):
+        self.lib = L.load()
+        sd = L.ServerDesc()
+        sd.base = default_desc(base_problem, precision, **solver)
+        sd.hbm_budget_bytes = int(hbm_budget_bytes)
+        sd.max_inflight = max_inflight
+        sd.n_streams = n_streams
+        sd.max_batch = max_batch
+        self.desc = sd
+        h = C.c_void_p()
+        L.check(self.lib.mq_server_create(C.byref(sd), _stream(), C.byref(h)))
+        self.h = h
+
+    def submit(self, n_nodes: int, steps_per_period: int, n_periods: int, xi, user_id: int = 0) -> int:
+        rq = L.Request()
+        rq.n_nodes, rq.steps_per_period, rq.n_periods = n_nodes, steps_per_period, n_periods
+        rq.n_xi = len(xi)
+        for i, v in enumerate(xi):
+            rq.xi[i] = float(v)
+        rq.user_id = user_id
+        t = C.c_uint64()
+        L.check(self.lib.mq_submit(self.h, C.byref(rq), C.byref(t)))
+        return t.value
+
+    def poll(self, cap: int = 256):
+        buf = (L.Result * cap)()
+        n = C.c_int32()
+        L.check(self.lib.mq_poll(self.h, buf, cap, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def pending(self) -> int:
+        n = C.c_int32()
+        L.check(self.lib.mq_server_pending(self.h, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mq_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,662 @@
+// C ABI of libmq: argument validation, device memory, instance tables and
+// launch orchestration for MLMC level runs (Section II-B), Parareal
+// (Section II-C) and the MLMC estimator (Eq. (9)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mq_internal.h"
+#include "setup.h"
+
+using namespace mq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e__ = (expr);                                                       \
+    if (e__ != hipSuccess)                                                         \
+      return fail(e__ == hipErrorOutOfMemory ? MQ_ERR_OUT_OF_MEMORY : MQ_ERR_DEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(e__));             \
+  } while (0)
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation owned by a unique_ptr.
+struct DevFree {
+  void operator()(void* p) const {
+    if (p) (void)hipFree(p);
+  }
+};
+template <class T>
+using DevPtr = std::unique_ptr<T, DevFree>;
+
+template <class T>
+hipError_t dev_alloc(DevPtr<T>& out, size_t count) {
+  T* p = nullptr;
+  hipError_t e = hipMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T));
+  if (e == hipSuccess) out.reset(p);
+  return e;
+}
+
+}  // namespace
+
+struct mq_problem {
+  mq_problem_desc d;
+  HostMesh hm;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  int lds_limit = 0;
+  int n_xi = 0;
+  int resident_ok = 0;
+  int lds_bytes = 0;
+  int path = MQ_PATH_STREAMING;
+  double mat[10];
+  DevPtr<double> dS;
+  DevPtr<uint8_t> dcond;
+  DevPtr<double> dkl;
+  DevPtr<int> dcounter;
+  DevPtr<int> dflag;
+  // per-slot work buffers (grown on demand, zeroed when allocated)
+  DevPtr<double> work;
+  size_t work_slots = 0;
+};
+
+namespace {
+
+int n_xi_of(const mq_problem_desc& d) {
+  if (d.material == MQ_MAT_LOGNORMAL_SCALAR) return 2;
+  if (d.material == MQ_MAT_KL) return d.n_modes;
+  return 3;
+}
+
+int validate_desc(const mq_problem_desc* d) {
+  if (!d) return fail(MQ_ERR_INVALID_ARG, "null problem description");
+  if (d->n_nodes < 3 || d->n_nodes > 8193) return fail(MQ_ERR_INVALID_ARG, "n_nodes must be in [3, 8193]");
+  if (d->material < 0 || d->material > 2) return fail(MQ_ERR_INVALID_ARG, "unknown material kind");
+  if (d->precision != MQ_PREC_FP64 && d->precision != MQ_PREC_MIXED)
+    return fail(MQ_ERR_INVALID_ARG, "unknown precision");
+  if (d->path < 0 || d->path > 2) return fail(MQ_ERR_INVALID_ARG, "unknown path");
+  if (!(d->conductor[0] < d->conductor[1]) || !(d->conductor[2] < d->conductor[3]))
+    return fail(MQ_ERR_INVALID_ARG, "empty conductor box");
+  if (!(d->strip[0] <= d->strip[1])) return fail(MQ_ERR_INVALID_ARG, "bad strip");
+  if (!(d->freq > 0) || !std::isfinite(d->J0)) return fail(MQ_ERR_INVALID_ARG, "bad source");
+  if (!(d->sigma0 >= 0) || !(d->nu_cond > 0) || !(d->nu_air > 0))
+    return fail(MQ_ERR_INVALID_ARG, "bad material constants");
+  if (d->material == MQ_MAT_KL && (d->n_modes < 1 || d->n_modes > 16 || !(d->corr_len > 0)))
+    return fail(MQ_ERR_INVALID_ARG, "KL needs 1..16 modes and corr_len > 0");
+  if (!(d->tol > 0) || !(d->inner_rtol > 0) || !(d->inner_rtol < 1))
+    return fail(MQ_ERR_INVALID_ARG, "tolerances must be positive (inner_rtol < 1)");
+  if (d->max_iter < 1 || d->max_sweeps < 1) return fail(MQ_ERR_INVALID_ARG, "max_iter and max_sweeps must be >= 1");
+  if (d->material == MQ_MAT_NONLINEAR && (d->picard_max < 1 || !(d->picard_tol > 0)))
+    return fail(MQ_ERR_INVALID_ARG, "bad Picard parameters");
+  return MQ_OK;
+}
+
+Solver solver_of(const mq_problem* p) {
+  Solver sv;
+  sv.precision = p->d.precision;
+  sv.tol = p->d.tol;
+  sv.inner_rtol = p->d.inner_rtol;
+  sv.max_iter = p->d.max_iter;
+  sv.max_sweeps = p->d.max_sweeps;
+  sv.nonlinear = p->d.material == MQ_MAT_NONLINEAR;
+  sv.picard_tol = p->d.picard_tol;
+  sv.picard_max = p->d.picard_max;
+  return sv;
+}
+
+int check_finite(mq_problem* p, const double* x, size_t n) {
+  HIP_TRY(launch_fill_zero_i(p->dflag.get(), 1, p->stream));
+  HIP_TRY(launch_check_finite(x, n, p->dflag.get(), p->stream));
+  int bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, p->dflag.get(), sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (bad) return fail(MQ_ERR_NONFINITE, "xi contains NaN or Inf");
+  return MQ_OK;
+}
+
+size_t slot_doubles(const Geom& g) {
+  // FP64 state (3 full grids) + the streaming path's vector workspace (8-byte upper bound)
+  return ie_work_doubles(g) + stream_vwork_elems(g);
+}
+
+int ensure_work(mq_problem* p, size_t slots) {
+  if (p->work_slots >= slots) return MQ_OK;
+  p->work.reset();
+  p->work_slots = 0;
+  const size_t nd = slots * slot_doubles(p->hm.g);
+  HIP_TRY(dev_alloc(p->work, nd));
+  HIP_TRY(launch_fill_zero(p->work.get(), nd, p->stream));
+  p->work_slots = slots;
+  return MQ_OK;
+}
+
+// J(t_k) = J0 sin(2 pi f k dt), k = 0..n_total (FP64 on the host).
+std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_total) {
+  std::vector<double> s(n_total + 1);
+  for (int k = 0; k <= n_total; ++k) s[k] = d.J0 * std::sin(2.0 * M_PI * d.freq * (k * dt));
+  return s;
+}
+
+struct RunOut {
+  int status = MQ_OK;
+  double kernel_ms = 0;
+  int grid = 0, block = 0;
+};
+
+// Launch one persistent time-stepping kernel over `insts` (host copy).
+int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, RunOut* ro,
+                  std::vector<int>* stat_host) {
+  const int n = (int)insts.size();
+  if (n == 0) return MQ_OK;
+  DevPtr<int> dstat;
+  HIP_TRY(dev_alloc(dstat, (size_t)n * 4));
+  for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + 4 * i;
+  DevPtr<Inst> dinst;
+  HIP_TRY(dev_alloc(dinst, n));
+  HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
+  const Geom& g = p->hm.g;
+  const int per_cu = ie_slots_per_cu(g, p->path, p->d.precision);
+  const size_t slots = std::min<size_t>((size_t)n, (size_t)p->num_cu * per_cu);
+  int rc = ensure_work(p, slots);
+  if (rc) return rc;
+  HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  Solver sv = solver_of(p);
+  HIP_TRY(hipEventRecord(e0, p->stream));
+  // the slot layout of the work buffer is fixed by its allocation (work_slots);
+  // the grid is the occupancy-limited slot count
+  hipError_t le = launch_ie(g, sv, dinst.get(), n, p->dcounter.get(), p->work.get(), (int)p->work_slots, (int)slots,
+                            p->dS.get(), p->path, p->d.precision, p->hm.cr, p->dcond.get(), p->mat,
+                            &ro->grid, &ro->block, p->stream);
+  if (le != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return fail(MQ_ERR_DEVICE, std::string("time-stepping launch: ") + hipGetErrorString(le));
+  }
+  HIP_TRY(hipEventRecord(e1, p->stream));
+  std::vector<int> sh((size_t)n * 4);
+  HIP_TRY(hipMemcpyAsync(sh.data(), dstat.get(), sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ro->kernel_ms += ms;
+  for (int i = 0; i < n; ++i) {
+    const int* s4 = &sh[4 * i];
+    if (st) {
+      st->n_instances += 1;
+      st->sample_steps += (int64_t)insts[i].n_steps * std::max(1, insts[i].n_chain);
+      st->inner_iters += s4[0];
+      st->sweeps += s4[1];
+      st->max_inner_per_step = std::max(st->max_inner_per_step, s4[2]);
+      if (s4[3] & FLAG_NOT_CONVERGED) st->n_not_converged++;
+      if (s4[3] & FLAG_FAILED) st->n_failed++;
+    }
+    if (s4[3] & (FLAG_NOT_CONVERGED | FLAG_FAILED)) ro->status = MQ_WARN_NOT_CONVERGED;
+  }
+  if (st) {
+    st->path = p->path;
+    st->grid = ro->grid;
+    st->block = ro->block;
+    st->kernel_ms += ms;
+  }
+  if (stat_host) *stat_host = std::move(sh);
+  return MQ_OK;
+}
+
+int assemble(mq_problem* p, const double* xi, int n, DevPtr<double>& tables) {
+  const Geom& g = p->hm.g;
+  HIP_TRY(dev_alloc(tables, (size_t)n * T_NPLANES * g.RW * g.RH));
+  HIP_TRY(launch_assemble(g, p->hm.cr, p->dcond.get(), p->dkl.get(), p->hm.n_modes, p->d.material, xi,
+                          p->n_xi, n, p->mat, tables.get(), p->stream));
+  return MQ_OK;
+}
+
+struct LevelBufs {
+  DevPtr<double> tables, src_f, src_c, afull;
+  std::vector<double*> afull_ptr;
+};
+
+// Append the instances of one level (fine first) and allocate their inputs.
+int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* xi, double* qf,
+                  double* qc, bool want_state, LevelBufs& lb, std::vector<Inst>& fine,
+                  std::vector<Inst>& coarse) {
+  if (!lv) return fail(MQ_ERR_INVALID_ARG, "null level description");
+  if (n < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  if (lv->steps_per_period < 1 || lv->n_periods < 1 || lv->coarse_steps_per_period < 0)
+    return fail(MQ_ERR_INVALID_ARG, "steps_per_period, n_periods >= 1 and coarse_steps_per_period >= 0 required");
+  if (!xi || !qf) return fail(MQ_ERR_INVALID_ARG, "xi and q_fine are required");
+  if (lv->coarse_steps_per_period > 0 && !qc) return fail(MQ_ERR_INVALID_ARG, "q_coarse required for a coupled level");
+  const int64_t nf = (int64_t)lv->steps_per_period * lv->n_periods;
+  const int64_t nc = (int64_t)lv->coarse_steps_per_period * lv->n_periods;
+  if (nf > (1 << 24) || nc > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
+  int rc = check_finite(p, xi, (size_t)n * p->n_xi);
+  if (rc) return rc;
+  rc = assemble(p, xi, n, lb.tables);
+  if (rc) return rc;
+  const Geom& g = p->hm.g;
+  const double T = lv->n_periods / p->d.freq;
+  const double dtf = 1.0 / (p->d.freq * lv->steps_per_period);
+  auto sf = source_table(p->d, dtf, (int)nf);
+  HIP_TRY(dev_alloc(lb.src_f, sf.size()));
+  HIP_TRY(hipMemcpyAsync(lb.src_f.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  double dtc = 0;
+  if (nc > 0) {
+    dtc = 1.0 / (p->d.freq * lv->coarse_steps_per_period);
+    auto sc = source_table(p->d, dtc, (int)nc);
+    HIP_TRY(dev_alloc(lb.src_c, sc.size()));
+    HIP_TRY(hipMemcpyAsync(lb.src_c.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    // the copy's host vector must outlive the async copy
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const size_t FS = (size_t)g.N * g.P;
+  if (want_state) {
+    HIP_TRY(dev_alloc(lb.afull, FS * n));
+    lb.afull_ptr.resize(n);
+    for (int s = 0; s < n; ++s) lb.afull_ptr[s] = lb.afull.get() + FS * s;
+  }
+  const size_t RHW = (size_t)g.RW * g.RH;
+  for (int s = 0; s < n; ++s) {
+    Inst in{};
+    in.tab = lb.tables.get() + (size_t)s * T_NPLANES * RHW;
+    in.src = lb.src_f.get();
+    in.a_out = want_state ? lb.afull_ptr[s] : nullptr;
+    in.q_out = qf + s;
+    in.q_scale = 1.0 / T;
+    in.dt = dtf;
+    in.n_steps = (int)nf;
+    in.sample = s;
+    fine.push_back(in);
+    if (nc > 0) {
+      Inst ic = in;
+      ic.src = lb.src_c.get();
+      ic.a_out = nullptr;
+      ic.q_out = qc + s;
+      ic.dt = dtc;
+      ic.n_steps = (int)nc;
+      coarse.push_back(ic);
+    }
+  }
+  return MQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mq_last_error(void) { return g_err.c_str(); }
+
+int mq_version(void) { return 1; }
+
+int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
+  if (!out) return fail(MQ_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MQ_ERR_NO_DEVICE, "no HIP device");
+  std::unique_ptr<mq_problem> p(new mq_problem());
+  p->d = *d;
+  try {
+    p->hm = build_host_mesh(*d);
+  } catch (const std::exception& ex) {
+    return fail(MQ_ERR_INVALID_ARG, std::string("mesh set-up: ") + ex.what());
+  }
+  HIP_TRY(hipGetDevice(&p->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, p->device));
+  p->num_cu = prop.multiProcessorCount;
+  p->lds_limit = (int)prop.sharedMemPerBlock;
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, p->device) == hipSuccess && optin > p->lds_limit)
+    p->lds_limit = optin;
+  p->stream = (hipStream_t)stream;
+  p->n_xi = n_xi_of(*d);
+  p->resident_ok = resident_supported(p->hm.g, d->precision, p->lds_limit, &p->lds_bytes);
+  if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
+    return fail(MQ_ERR_INVALID_ARG, "the resident path does not fit this mesh/precision");
+  p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
+  const double m[10] = {d->sigma0, d->nu_cond, d->nu_air, d->s_sigma, d->s_nu, d->s_kl, d->k1, d->k2, d->k3, d->s_k};
+  std::memcpy(p->mat, m, sizeof(m));
+  const Geom& g = p->hm.g;
+  HIP_TRY(dev_alloc(p->dS, p->hm.S.size()));
+  HIP_TRY(hipMemcpy(p->dS.get(), p->hm.S.data(), p->hm.S.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(dev_alloc(p->dcond, p->hm.cond.size()));
+  HIP_TRY(hipMemcpy(p->dcond.get(), p->hm.cond.data(), p->hm.cond.size(), hipMemcpyHostToDevice));
+  if (!p->hm.kl.empty()) {
+    HIP_TRY(dev_alloc(p->dkl, p->hm.kl.size()));
+    HIP_TRY(hipMemcpy(p->dkl.get(), p->hm.kl.data(), p->hm.kl.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(dev_alloc(p->dcounter, 1));
+  HIP_TRY(dev_alloc(p->dflag, 1));
+  (void)g;
+  *out = p.release();
+  return MQ_OK;
+}
+
+int mq_problem_destroy(mq_problem* p) {
+  if (!p) return MQ_OK;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  delete p;
+  return MQ_OK;
+}
+
+int mq_ndof(const mq_problem* p, int64_t* nd) {
+  if (!p || !nd) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  *nd = (int64_t)p->hm.g.n * p->hm.g.n;
+  return MQ_OK;
+}
+
+int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
+  if (!p || !info) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  const Geom& g = p->hm.g;
+  info->n_nodes = g.N;
+  info->n_dof = g.n * g.n;
+  info->pitch = g.P;
+  info->n_xi = p->n_xi;
+  info->box[0] = g.bx0;
+  info->box[1] = g.bx1;
+  info->box[2] = g.by0;
+  info->box[3] = g.by1;
+  info->resident_ok = p->resident_ok;
+  info->lds_bytes = p->lds_bytes;
+  info->n_modes_used = p->hm.n_modes;
+  for (int k = 0; k < p->hm.n_modes && k < 16; ++k) info->kl_lambda[k] = p->hm.kl_lambda[k];
+  return MQ_OK;
+}
+
+int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                   double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+  if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
+  const double t0 = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  LevelBufs lb;
+  std::vector<Inst> fine, coarse;
+  int rc = prepare_level(p, lv, n_samples, xi, q_fine, q_coarse, final_state != nullptr, lb, fine, coarse);
+  if (rc) return rc;
+  std::vector<Inst> all = fine;
+  all.insert(all.end(), coarse.begin(), coarse.end());
+  RunOut ro;
+  rc = run_instances(p, all, st, &ro, nullptr);
+  if (rc) return rc;
+  if (final_state) {
+    DevPtr<double*> dptr;
+    HIP_TRY(dev_alloc(dptr, lb.afull_ptr.size()));
+    HIP_TRY(hipMemcpyAsync(dptr.get(), lb.afull_ptr.data(), lb.afull_ptr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(launch_to_interior(p->hm.g, n_samples, dptr.get(), final_state, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  if (st) st->total_ms = now_ms() - t0;
+  return ro.status;
+}
+
+int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
+                        const int32_t* n_samples, const double* const* xi, double* const* q_fine,
+                        double* const* q_coarse, mq_run_stats* st) {
+  if (!p || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
+  const double t0 = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  std::vector<LevelBufs> lbs(n_levels);
+  std::vector<Inst> all;
+  std::vector<std::pair<int64_t, Inst>> keyed;
+  for (int l = 0; l < n_levels; ++l) {
+    std::vector<Inst> f, c;
+    int rc = prepare_level(p, &lv[l], n_samples[l], xi[l], q_fine[l], q_coarse[l], false, lbs[l], f, c);
+    if (rc) return rc;
+    for (auto& i : f) keyed.push_back({i.n_steps, i});
+    for (auto& i : c) keyed.push_back({i.n_steps, i});
+  }
+  // longest instances first; stable so that equal lengths keep their order
+  std::stable_sort(keyed.begin(), keyed.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  for (auto& k : keyed) all.push_back(k.second);
+  RunOut ro;
+  int rc = run_instances(p, all, st, &ro, nullptr);
+  if (rc) return rc;
+  if (st) st->total_ms = now_ms() - t0;
+  return ro.status;
+}
+
+int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
+                 double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
+  if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
+  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  const int M = pd->n_slices, fs = pd->fine_steps_per_slice, cs = pd->coarse_steps_per_slice;
+  if (M < 1 || fs < 1 || cs < 1 || pd->n_periods < 1 || pd->k_max < 1 || pd->fixed_k < 0 || !(pd->tol >= 0))
+    return fail(MQ_ERR_INVALID_ARG, "invalid Parareal description");
+  if ((int64_t)M * fs > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
+  const double t_start = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  int rc = check_finite(p, xi, (size_t)n_samples * p->n_xi);
+  if (rc) return rc;
+  const Geom& g = p->hm.g;
+  const size_t FS = (size_t)g.N * g.P, RHW = (size_t)g.RW * g.RH;
+  DevPtr<double> tables;
+  rc = assemble(p, xi, n_samples, tables);
+  if (rc) return rc;
+  const double T = pd->n_periods / p->d.freq;
+  const double dtf = T / ((double)M * fs), dtc = T / ((double)M * cs);
+  auto sf = source_table(p->d, dtf, M * fs);
+  auto sc = source_table(p->d, dtc, M * cs);
+  DevPtr<double> dsf, dsc;
+  HIP_TRY(dev_alloc(dsf, sf.size()));
+  HIP_TRY(dev_alloc(dsc, sc.size()));
+  HIP_TRY(hipMemcpy(dsf.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dsc.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice));
+  // states: U_0..U_{M-1} (U_0 = 0), F_1..F_M, C_old_1..C_old_{M-1}, per sample
+  const int S = n_samples;
+  const size_t per = (size_t)(M + M + M) * FS;
+  DevPtr<double> states, qn;
+  HIP_TRY(dev_alloc(states, per * S));
+  HIP_TRY(launch_fill_zero(states.get(), per * S, p->stream));
+  HIP_TRY(dev_alloc(qn, (size_t)S * M));
+  HIP_TRY(launch_fill_zero(qn.get(), (size_t)S * M, p->stream));
+  auto U = [&](int s, int nn) { return states.get() + per * s + (size_t)nn * FS; };             // nn = 0..M-1
+  auto F = [&](int s, int nn) { return states.get() + per * s + (size_t)(M + nn - 1) * FS; };   // nn = 1..M
+  auto C = [&](int s, int nn) { return states.get() + per * s + (size_t)(2 * M + nn - 1) * FS; };  // nn = 1..M-1
+  const int kcap = std::min(pd->fixed_k > 0 ? pd->fixed_k : pd->k_max, M);
+  RunOut ro;
+  std::vector<int> active(S);
+  for (int s = 0; s < S; ++s) active[s] = s;
+  std::vector<int> Kout(S, 0);
+  bool warn = false;
+
+  auto launch_chain = [&](const std::vector<int>& smp, int first, bool initial) -> int {
+    if (first > M - 1 || smp.empty()) return MQ_OK;
+    const int nseg = M - first;
+    const size_t L = (size_t)smp.size() * nseg;
+    std::vector<double*> arr(3 * L);
+    for (size_t a = 0; a < smp.size(); ++a)
+      for (int k = 0; k < nseg; ++k) {
+        const int nn = first + k;
+        arr[a * nseg + k] = U(smp[a], nn);
+        arr[L + a * nseg + k] = initial ? nullptr : F(smp[a], nn);
+        arr[2 * L + a * nseg + k] = C(smp[a], nn);
+      }
+    DevPtr<double*> darr;
+    HIP_TRY(dev_alloc(darr, arr.size()));
+    HIP_TRY(hipMemcpy(darr.get(), arr.data(), arr.size() * sizeof(double*), hipMemcpyHostToDevice));
+    std::vector<Inst> insts;
+    for (size_t a = 0; a < smp.size(); ++a) {
+      Inst in{};
+      in.tab = tables.get() + (size_t)smp[a] * T_NPLANES * RHW;
+      in.src = dsc.get();
+      in.a_init = U(smp[a], first - 1);
+      in.dt = dtc;
+      in.n_steps = cs;
+      in.k0 = (first - 1) * cs;
+      in.n_chain = nseg;
+      in.chain_u = darr.get() + a * nseg;
+      in.chain_f = darr.get() + L + a * nseg;
+      in.chain_c = darr.get() + 2 * L + a * nseg;
+      in.sample = smp[a];
+      insts.push_back(in);
+    }
+    return run_instances(p, insts, st, &ro, nullptr);
+  };
+
+  // initial coarse pass U_n = C(U_{n-1}), n = 1..M-1
+  rc = launch_chain(active, 1, true);
+  if (rc) return rc;
+  std::vector<double> jump_host;
+  for (int j = 1; j <= kcap && !active.empty(); ++j) {
+    // fine sweep over slices j..M of the active samples
+    std::vector<Inst> insts;
+    for (int s : active)
+      for (int nn = j; nn <= M; ++nn) {
+        Inst in{};
+        in.tab = tables.get() + (size_t)s * T_NPLANES * RHW;
+        in.src = dsf.get();
+        in.a_init = U(s, nn - 1);
+        in.a_out = F(s, nn);
+        in.q_out = qn.get() + (size_t)s * M + (nn - 1);
+        in.q_scale = 1.0;
+        in.dt = dtf;
+        in.n_steps = fs;
+        in.k0 = (nn - 1) * fs;
+        in.sample = s;
+        insts.push_back(in);
+      }
+    rc = run_instances(p, insts, st, &ro, nullptr);
+    if (rc) return rc;
+    // interface jumps over n = j..M-1
+    std::vector<int> still;
+    if (j < M) {
+      const int npair = (int)active.size() * (M - j);
+      std::vector<const double*> fp(npair), up(npair);
+      int k = 0;
+      for (int s : active)
+        for (int nn = j; nn < M; ++nn, ++k) {
+          fp[k] = F(s, nn);
+          up[k] = U(s, nn);
+        }
+      DevPtr<const double*> dfp, dup;
+      DevPtr<double> dj;
+      HIP_TRY(dev_alloc(dfp, npair));
+      HIP_TRY(dev_alloc(dup, npair));
+      HIP_TRY(dev_alloc(dj, 2 * (size_t)npair));
+      HIP_TRY(hipMemcpy(dfp.get(), fp.data(), npair * sizeof(double*), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(dup.get(), up.data(), npair * sizeof(double*), hipMemcpyHostToDevice));
+      HIP_TRY(launch_jumps(g, npair, dfp.get(), dup.get(), dj.get(), p->stream));
+      jump_host.assign(2 * (size_t)npair, 0.0);
+      HIP_TRY(hipMemcpyAsync(jump_host.data(), dj.get(), jump_host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      k = 0;
+      for (int s : active) {
+        double J = 0.0;
+        for (int nn = j; nn < M; ++nn, ++k) {
+          const double r = jump_host[2 * k + 1] > 0 ? std::sqrt(jump_host[2 * k] / jump_host[2 * k + 1]) : std::sqrt(jump_host[2 * k]);
+          J = std::max(J, r);
+        }
+        const bool done = (pd->fixed_k == 0 && J <= pd->tol) || j == kcap;
+        if (done) {
+          Kout[s] = j;
+          if (pd->fixed_k == 0 && J > pd->tol) warn = true;
+        } else {
+          still.push_back(s);
+        }
+      }
+    } else {
+      for (int s : active) Kout[s] = j;
+    }
+    active = still;
+    if (active.empty()) break;
+    // correction: U_j = F_j, then the coarse chain over j+1..M-1
+    for (int s : active)
+      HIP_TRY(hipMemcpyAsync(U(s, j), F(s, j), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    rc = launch_chain(active, j + 1, false);
+    if (rc) return rc;
+  }
+  // Q = sum_n q_n / T in slice order (FP64, host)
+  std::vector<double> qh((size_t)S * M);
+  HIP_TRY(hipMemcpy(qh.data(), qn.get(), qh.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> Q(S);
+  for (int s = 0; s < S; ++s) {
+    double acc = 0.0;
+    for (int nn = 0; nn < M; ++nn) acc += qh[(size_t)s * M + nn];
+    Q[s] = acc / T;
+  }
+  HIP_TRY(hipMemcpy(q, Q.data(), S * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(iters, Kout.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (final_state) {
+    std::vector<const double*> fp(S);
+    for (int s = 0; s < S; ++s) fp[s] = F(s, M);
+    DevPtr<const double*> dfp;
+    HIP_TRY(dev_alloc(dfp, S));
+    HIP_TRY(hipMemcpy(dfp.get(), fp.data(), S * sizeof(double*), hipMemcpyHostToDevice));
+    HIP_TRY(launch_to_interior(g, S, dfp.get(), final_state, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  if (st) st->total_ms = now_ms() - t_start;
+  if (warn) {
+    g_err = "Parareal reached k_max above the tolerance for some samples";
+    return MQ_WARN_NOT_CONVERGED;
+  }
+  return ro.status;
+}
+
+int mlmc_estimate(int32_t n_levels, const int32_t* n_per_level, const double* const* q_fine,
+                  const double* const* q_coarse, double* out, void* stream) {
+  if (n_levels < 1 || n_levels > 64 || !n_per_level || !q_fine || !out)
+    return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
+  for (int l = 0; l < n_levels; ++l) {
+    if (n_per_level[l] < 1) return fail(MQ_ERR_INVALID_ARG, "every level needs >= 1 sample");
+    if (!q_fine[l]) return fail(MQ_ERR_INVALID_ARG, "null q_fine entry");
+    if (l > 0 && (!q_coarse || !q_coarse[l])) return fail(MQ_ERR_INVALID_ARG, "null q_coarse entry for a level > 0");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<const double*> qc(n_levels, nullptr);
+  for (int l = 1; l < n_levels; ++l) qc[l] = q_coarse[l];
+  DevPtr<int> dn;
+  DevPtr<const double*> dqf, dqc;
+  HIP_TRY(dev_alloc(dn, n_levels));
+  HIP_TRY(dev_alloc(dqf, n_levels));
+  HIP_TRY(dev_alloc(dqc, n_levels));
+  HIP_TRY(hipMemcpyAsync(dn.get(), n_per_level, n_levels * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dqf.get(), q_fine, n_levels * sizeof(double*), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dqc.get(), qc.data(), n_levels * sizeof(double*), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_level_stats(n_levels, dn.get(), dqf.get(), dqc.get(), out, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MQ_OK;
+}
+
+int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const double* xi,
+                   const double* x, double* y) {
+  if (!p || !xi || !x || !y) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (which < 0 || which > 2 || n < 1 || !(dt > 0)) return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
+  int rc = check_finite(p, xi, (size_t)n * p->n_xi);
+  if (rc) return rc;
+  DevPtr<double> tables;
+  rc = assemble(p, xi, n, tables);
+  if (rc) return rc;
+  HIP_TRY(launch_apply(p->hm.g, which, dt, tables.get(), n, x, y, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return MQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1108 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+//  k_assemble      per-sample materials (Eq. (1) coefficients sigma, nu per
+//                  element) and the P1 stencils of M_sigma and K_nu (Eq. (4))
+//                  on the sample-dependent box, FP64.
+//  k_ie_resident   persistent implicit Euler (Eqs. (6)-(7), increment form)
+//                  with FP64 iterative refinement around a Jacobi-scaled CG in
+//                  VT (float or double); one workgroup owns one instance and
+//                  keeps the CG vectors in registers and LDS; the Joule-loss
+//                  sum of Eq. (26) is accumulated in FP64.
+//  k_ie_stream     same algorithm with the CG vectors in global memory, for
+//                  meshes whose state does not fit one compute unit.
+//  small kernels   debug operator apply, layout copies, level statistics of
+//                  Eq. (9), Parareal interface jumps (Eq. (12) stopping test).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mq_internal.h"
+
+namespace mq {
+
+// ---------------------------------------------------------------------------
+// materials + assembly
+// ---------------------------------------------------------------------------
+struct MatParams {
+  double sigma0, nu_cond, nu_air, s_sigma, s_nu, s_kl, k1, k2, k3, s_k;
+};
+
+__device__ inline void elem_material(int material, const MatParams& mp, const uint8_t* cond,
+                                     const double* kl, int n_modes, int e, const double* xi,
+                                     double* sig, double* nu) {
+  if (!cond[e]) {
+    *sig = 0.0;
+    *nu = mp.nu_air;
+    return;
+  }
+  if (material == MQ_MAT_LOGNORMAL_SCALAR) {
+    *sig = mp.sigma0 * exp(mp.s_sigma * xi[0]);
+    *nu = mp.nu_cond * exp(mp.s_nu * xi[1]);
+  } else if (material == MQ_MAT_KL) {
+    double gsum = 0.0;
+    for (int k = 0; k < n_modes; ++k) gsum = fma(kl[(size_t)e * n_modes + k], xi[k], gsum);
+    *sig = exp(log(mp.sigma0) + mp.s_kl * gsum);
+    *nu = mp.nu_cond;
+  } else {  // nonlinear iron: nu at B = 0 here, updated by the Picard loop
+    *sig = mp.sigma0;
+    *nu = mp.k1 * exp(mp.s_k * xi[0]) + mp.k3 * exp(mp.s_k * xi[2]);
+  }
+}
+
+// One thread per (table node, sample).  Box nodes get the six-triangle P1
+// stencil; other table nodes the air constants (M = 0, K = nu_air * [4, -1]).
+//   K_C = nu(a0)/2 + nu(a1)/2 + nu(b0) + nu(c1) + nu(d0)/2 + nu(d1)/2
+//   K_E = -(nu(a0) + nu(c1))/2          K_N = -(nu(a1) + nu(b0))/2
+//   M_C = h^2/12 * (sum of the six sigmas)
+//   M_E = h^2/24 (s(a0) + s(c1))  M_N = h^2/24 (s(a1) + s(b0))  M_NE = h^2/24 (s(a0) + s(a1))
+// with a = cell (I, J), b = cell (I-1, J), c = cell (I, J-1), d = cell (I-1, J-1)
+// of full-grid node (I, J); t0 = {(I,J),(I+1,J),(I+1,J+1)}, t1 = {(I,J),(I+1,J+1),(I,J+1)}.
+__global__ void k_assemble(Geom g, CellRegion cr, const uint8_t* __restrict__ cond,
+                           const double* __restrict__ kl, int n_modes, int material, MatParams mp,
+                           const double* __restrict__ xi, int n_xi, int n_samples,
+                           double* __restrict__ tables) {
+  const int RHW = g.RW * g.RH;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (t >= RHW || smp >= n_samples) return;
+  double* T = tables + (size_t)smp * T_NPLANES * RHW;
+  const int i = g.bx0 - 1 + t % g.RW;
+  const int j = g.by0 - 1 + t / g.RW;
+  const bool inbox = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+  if (!inbox) {
+    T[T_MC * RHW + t] = 0.0;
+    T[T_ME * RHW + t] = 0.0;
+    T[T_MN * RHW + t] = 0.0;
+    T[T_MNE * RHW + t] = 0.0;
+    T[T_KC * RHW + t] = 4.0 * g.nu_air;
+    T[T_KE * RHW + t] = -g.nu_air;
+    T[T_KN * RHW + t] = -g.nu_air;
+    return;
+  }
+  const double* x = xi + (size_t)smp * n_xi;
+  const int I = i + 1, J = j + 1;  // full-grid node
+  auto eidx = [&](int ci, int cj, int tt) { return ((cj - cr.cy0) * cr.cw + (ci - cr.cx0)) * 2 + tt; };
+  double sa0, na0, sa1, na1, sb0, nb0, sc1, nc1, sd0, nd0, sd1, nd1;
+  elem_material(material, mp, cond, kl, n_modes, eidx(I, J, 0), x, &sa0, &na0);
+  elem_material(material, mp, cond, kl, n_modes, eidx(I, J, 1), x, &sa1, &na1);
+  elem_material(material, mp, cond, kl, n_modes, eidx(I - 1, J, 0), x, &sb0, &nb0);
+  elem_material(material, mp, cond, kl, n_modes, eidx(I, J - 1, 1), x, &sc1, &nc1);
+  elem_material(material, mp, cond, kl, n_modes, eidx(I - 1, J - 1, 0), x, &sd0, &nd0);
+  elem_material(material, mp, cond, kl, n_modes, eidx(I - 1, J - 1, 1), x, &sd1, &nd1);
+  const double h12 = g.h2 / 12.0, h24 = g.h2 / 24.0;
+  T[T_MC * RHW + t] = h12 * (sa0 + sa1 + sb0 + sc1 + sd0 + sd1);
+  T[T_ME * RHW + t] = h24 * (sa0 + sc1);
+  T[T_MN * RHW + t] = h24 * (sa1 + sb0);
+  T[T_MNE * RHW + t] = h24 * (sa0 + sa1);
+  T[T_KC * RHW + t] = 0.5 * (na0 + na1 + nd0 + nd1) + nb0 + nc1;
+  T[T_KE * RHW + t] = -0.5 * (na0 + nc1);
+  T[T_KN * RHW + t] = -0.5 * (na1 + nb0);
+}
+
+hipError_t launch_assemble(const Geom& g, const CellRegion& cr, const uint8_t* cond,
+                           const double* kltab, int n_modes, int material, const double* xi,
+                           int n_xi, int n_samples, const double* mat_params, double* tables,
+                           hipStream_t st) {
+  MatParams mp;
+  mp.sigma0 = mat_params[0];
+  mp.nu_cond = mat_params[1];
+  mp.nu_air = mat_params[2];
+  mp.s_sigma = mat_params[3];
+  mp.s_nu = mat_params[4];
+  mp.s_kl = mat_params[5];
+  mp.k1 = mat_params[6];
+  mp.k2 = mat_params[7];
+  mp.k3 = mat_params[8];
+  mp.s_k = mat_params[9];
+  const int RHW = g.RW * g.RH;
+  dim3 grid((RHW + 255) / 256, n_samples);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, st, g, cr, cond, kltab, n_modes, material,
+                     mp, xi, n_xi, n_samples, tables);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 stencil helpers on full-grid vectors (pitch P, zero boundary ring)
+// ---------------------------------------------------------------------------
+struct NodeRef {
+  int gi;     // full-grid index
+  int t;      // table index (valid when inL)
+  bool inL;   // node reads its couplings from the tables
+};
+
+__device__ inline NodeRef node_ref(const Geom& g, int i, int j) {
+  NodeRef r;
+  r.gi = (j + 1) * g.P + (i + 1);
+  r.inL = i >= g.bx0 && i < g.lx1 && j >= g.by0 && j < g.ly1;
+  r.t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
+  return r;
+}
+
+// (K v)_node
+__device__ inline double K_apply(const Geom& g, const double* __restrict__ tab, const double* v,
+                                 const NodeRef& nr) {
+  const int P = g.P;
+  const double c = v[nr.gi], e = v[nr.gi + 1], w = v[nr.gi - 1], n = v[nr.gi + P], s = v[nr.gi - P];
+  if (!nr.inL) return g.nu_air * (4.0 * c - (e + w) - (n + s));
+  const int RHW = g.RW * g.RH, t = nr.t;
+  const double* KC = tab + T_KC * RHW;
+  const double* KE = tab + T_KE * RHW;
+  const double* KN = tab + T_KN * RHW;
+  return KC[t] * c + KE[t] * e + KE[t - 1] * w + KN[t] * n + KN[t - g.RW] * s;
+}
+
+// (M v)_node (zero outside the lookup region)
+__device__ inline double M_apply(const Geom& g, const double* __restrict__ tab, const double* v,
+                                 const NodeRef& nr) {
+  if (!nr.inL) return 0.0;
+  const int P = g.P, RHW = g.RW * g.RH, t = nr.t;
+  const double* MC = tab + T_MC * RHW;
+  const double* ME = tab + T_ME * RHW;
+  const double* MN = tab + T_MN * RHW;
+  const double* MNE = tab + T_MNE * RHW;
+  const int gi = nr.gi;
+  return MC[t] * v[gi] + ME[t] * v[gi + 1] + ME[t - 1] * v[gi - 1] + MN[t] * v[gi + P] +
+         MN[t - g.RW] * v[gi - P] + MNE[t] * v[gi + P + 1] + MNE[t - g.RW - 1] * v[gi - P - 1];
+}
+
+// ((M/dt + K) v)_node
+__device__ inline double A_apply(const Geom& g, const double* __restrict__ tab, const double* v,
+                                 const NodeRef& nr, double inv_dt) {
+  if (!nr.inL) return K_apply(g, tab, v, nr);
+  return M_apply(g, tab, v, nr) * inv_dt + K_apply(g, tab, v, nr);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions (wave64 butterfly, then waves in order)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Reduce NV values over the workgroup; every thread gets the same sums.
+// `red` holds 2 slots of [NWAVES][4] doubles; `slot` alternates between calls
+// so that one barrier per reduction suffices.
+template <int NV, int NWAVES>
+__device__ inline void block_sum(double (&v)[NV], double* red, int& slot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  double* base = red + slot * NWAVES * 4;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) base[wv * 4 + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int k = 0; k < NWAVES; ++k) s += base[k * 4 + q];
+    v[q] = s;
+  }
+  slot ^= 1;
+}
+
+// ---------------------------------------------------------------------------
+// resident time-stepping kernel
+// ---------------------------------------------------------------------------
+// Workgroup = CW * NS threads; thread (c, s) owns interior column i = c and
+// rows [s*SH, s*SH + SH) (rows >= n idle).  CG vectors y, r, p, s, w of the
+// thread's SH nodes stay in registers; r is mirrored into an LDS grid with a
+// zero halo for the stencil; the scaled coupling tables of the box sit in LDS.
+//
+// Solver per step (increment form of Eq. (7)):
+//   b = J(t_{k+1}) S - K a;   x = previous increment (warm start)
+//   repeat: r64 = b - (M/dt + K) x in FP64; stop if ||r64|| <= tol ||b||;
+//           g = D^{-1/2} r64 (VT); CG on D^{-1/2} A D^{-1/2} y = g from y = 0
+//           (Jacobi preconditioning as a symmetric scaling) to ||r|| <=
+//           inner_rtol ||g||; x += D^{-1/2} y
+//   q += x^T M x / dt;  a += x
+// CG uses the single-reduction recurrences of Chronopoulos and Gear (J. Comput.
+// Appl. Math. 25 (1989)): s = A p and w = A r are carried so each iteration
+// needs one stencil apply and one fused reduction of (r.r, w.r).
+template <typename VT>
+__device__ inline VT vt(double x) { return (VT)x; }
+
+// LDS pitches are compile-time constants (LP = CW + 2 for the grid, TP for
+// the tables) so that every per-node LDS offset folds into the instruction's
+// immediate offset instead of occupying a register.
+template <typename VT, int CW, int SH, int NS, int TP>
+__global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
+                                                        const Inst* __restrict__ insts, int n_inst,
+                                                        int* counter, double* work,
+                                                        const double* __restrict__ S) {
+  constexpr int NT = CW * NS;
+  constexpr int NWAVES = NT / 64;
+  constexpr int LP = CW + 2;
+  extern __shared__ double smem_d[];
+  const int n = g.n, RHW = g.RW * g.RH, TRH = g.RH * TP;
+  double* red = smem_d;                                  // 2 * NWAVES * 4 doubles
+  VT* rl = reinterpret_cast<VT*>(red + 2 * NWAVES * 4);  // (n+2) x LP grid with zero halo
+  VT* tE = rl + (n + 2) * LP;                            // scaled tables, RH x TP each
+  VT* tN = tE + TRH;
+  VT* tNE = tN + TRH;
+  VT* tD = tNE + TRH;
+  __shared__ int s_inst;
+
+  const int tid = threadIdx.x;
+  const int ci = tid % CW;
+  const int j0 = (tid / CW) * SH;
+  const bool colok = ci < n;
+  const bool strip_ok = colok && j0 < n;
+  const size_t FS = (size_t)g.N * g.P;
+  double* Av = work + (size_t)blockIdx.x * 3 * FS;
+  double* Xv = Av + FS;
+  double* Bv = Xv + FS;
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  int slot = 0;
+
+  // node k of this thread is row j0 + k of column ci; indices are affine in k
+  const int gi0 = (j0 + 1) * g.P + ci + 1;
+  const int t0 = (j0 - g.by0 + 1) * g.RW + (ci - g.bx0 + 1);  // FP64 tables (pitch RW)
+  const int s0 = (j0 - g.by0 + 1) * TP + (ci - g.bx0 + 1);    // LDS tables (pitch TP)
+  const int l0 = (j0 + 1) * LP + ci + 1;
+  const bool col_L = ci >= g.bx0 && ci < g.lx1;
+  const bool col_box = ci >= g.bx0 && ci < g.bx1;
+  auto ACT = [&](int k) { return colok && (j0 + k) < n; };
+  auto NREF = [&](int k) {
+    NodeRef r;
+    const int j = j0 + k;
+    r.gi = gi0 + k * g.P;
+    r.t = t0 + k * g.RW;
+    r.inL = col_L && j >= g.by0 && j < g.ly1;
+    return r;
+  };
+  auto INBOX = [&](int k) {
+    const int j = j0 + k;
+    return col_box && j >= g.by0 && j < g.by1;
+  };
+
+  for (;;) {
+    if (tid == 0) s_inst = atomicAdd(counter, 1);
+    __syncthreads();
+    const int id = s_inst;
+    __syncthreads();
+    if (id >= n_inst) break;
+    const Inst in = insts[id];
+    const double* tab = in.tab;
+    const double inv_dt = 1.0 / in.dt;
+
+    // scaled couplings D^{-1/2} A D^{-1/2} over the table region, FP64 -> VT
+    auto dscale = [&](int i, int j) -> double {
+      if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
+        const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
+        return 1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]);
+      }
+      return d_air;
+    };
+    for (int t = tid; t < RHW; t += NT) {
+      const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
+      const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+      const double di = dscale(i, j);
+      double e = -0.25, nn = -0.25, ne = 0.0;
+      if (box) {
+        e = (tab[T_ME * RHW + t] * inv_dt + tab[T_KE * RHW + t]) * di * dscale(i + 1, j);
+        nn = (tab[T_MN * RHW + t] * inv_dt + tab[T_KN * RHW + t]) * di * dscale(i, j + 1);
+        ne = tab[T_MNE * RHW + t] * inv_dt * di * dscale(i + 1, j + 1);
+      }
+      const int ts = (t / g.RW) * TP + t % g.RW;
+      tE[ts] = vt<VT>(e);
+      tN[ts] = vt<VT>(nn);
+      tNE[ts] = vt<VT>(ne);
+      tD[ts] = vt<VT>(di);
+    }
+    for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
+#pragma unroll 1
+    for (int k = 0; k < SH; ++k) {
+      if (ACT(k)) {
+        const int gi = gi0 + k * g.P;
+        Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
+        Xv[gi] = 0.0;
+      }
+    }
+    __syncthreads();
+    auto DN = [&](int k) -> double { return INBOX(k) ? (double)tD[s0 + k * TP] : (double)vt<VT>(d_air); };
+
+    double qsum = 0.0;
+    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
+    const int n_seg = in.n_chain > 0 ? in.n_chain : 1;
+    for (int seg = 0; seg < n_seg; ++seg) {
+      const int kseg0 = in.k0 + seg * in.n_steps;
+      for (int step = 0; step < in.n_steps; ++step) {
+        const double Jt = in.src[kseg0 + step + 1];
+        // b = J(t_{k+1}) S - K a and ||b||^2
+        double part[1] = {0.0};
+#pragma unroll 1
+        for (int k = 0; k < SH; ++k) {
+          if (ACT(k)) {
+            const NodeRef nr = NREF(k);
+            const double b = Jt * S[nr.gi] - K_apply(g, tab, Av, nr);
+            Bv[nr.gi] = b;
+            part[0] += b * b;
+          }
+        }
+        block_sum<1, NWAVES>(part, red, slot);
+        const double bb = part[0];
+        int it_step = 0;
+        if (bb == 0.0) {
+#pragma unroll 1
+          for (int k = 0; k < SH; ++k)
+            if (ACT(k)) Xv[gi0 + k * g.P] = 0.0;
+          __syncthreads();
+        } else {
+          bool conv = false;
+          for (int sweep = 0; sweep <= sv.max_sweeps; ++sweep) {
+            // FP64 residual of the current increment; its scaled copy goes to LDS
+            double rr[1] = {0.0};
+#pragma unroll 1
+            for (int k = 0; k < SH; ++k) {
+              if (ACT(k)) {
+                const NodeRef nr = NREF(k);
+                const double res = Bv[nr.gi] - A_apply(g, tab, Xv, nr, inv_dt);
+                rr[0] += res * res;
+                rl[l0 + k * LP] = vt<VT>(res * DN(k));
+              }
+            }
+            block_sum<1, NWAVES>(rr, red, slot);  // barrier: LDS residual complete
+            if (!(rr[0] == rr[0]) || isinf(rr[0])) {
+              flags |= FLAG_FAILED;
+              break;
+            }
+            if (rr[0] <= sv.tol * sv.tol * bb) {
+              conv = true;
+              break;
+            }
+            if (sweep == sv.max_sweeps) break;
+            sw_total++;
+            // ---- inner CG on the scaled system, y0 = 0, r0 = g ----
+            // Chronopoulos-Gear ordering: the reduction of r.r shares its
+            // barrier with the LDS publication of r, the stencil result w is
+            // folded into p, s and r.w at once, so y, r, p, s are the only
+            // per-node registers and each iteration has two barriers.
+            VT y[SH], r[SH], p[SH], s[SH];
+#pragma unroll
+            for (int k = 0; k < SH; ++k) {
+              r[k] = ACT(k) ? rl[l0 + k * LP] : VT(0);
+              y[k] = VT(0);
+              p[k] = VT(0);
+              s[k] = VT(0);
+            }
+            double gam_prev = 1.0, alpha = 1.0, stop = 0.0;
+            int it = 0;
+            for (;; ++it) {
+              double gv[1];
+              {
+                VT pg = VT(0);
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  if (ACT(k)) rl[l0 + k * LP] = r[k];
+                  pg += r[k] * r[k];
+                }
+                gv[0] = (double)pg;
+              }
+              block_sum<1, NWAVES>(gv, red, slot);  // also publishes r in LDS
+              const double gam = gv[0];
+              if (it == 0) {
+                stop = sv.inner_rtol * sv.inner_rtol * gam;
+                if (!(gam > 0.0)) break;
+              } else if (gam <= stop || !(gam == gam)) {
+                break;
+              }
+              if (it == sv.max_iter) break;
+              const double beta = it == 0 ? 0.0 : gam / gam_prev;
+              const VT b_ = vt<VT>(beta);
+              VT pd = VT(0);
+              if (strip_ok) {
+                VT lprev = rl[l0 - LP - 1];    // (i-1, j0-1)
+                VT rcur = rl[l0 + 1];          // (i+1, j0)
+                const VT below = rl[l0 - LP];  // (i, j0-1)
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  const int j = j0 + k;
+                  if (j < n) {
+                    const VT lcur = rl[l0 + k * LP - 1];        // (i-1, j)
+                    const VT rnxt = rl[l0 + (k + 1) * LP + 1];  // (i+1, j+1)
+                    const VT up = (k + 1 < SH) ? r[(k + 1 < SH) ? k + 1 : k] : rl[l0 + (k + 1) * LP];
+                    const VT dnv = (k > 0) ? r[(k > 0) ? k - 1 : 0] : below;
+                    VT w;
+                    if (col_L && j >= g.by0 && j < g.ly1) {
+                      const int t = s0 + k * TP;
+                      w = r[k] + tE[t] * rcur + tE[t - 1] * lcur + tN[t] * up + tN[t - TP] * dnv +
+                          tNE[t] * rnxt + tNE[t - TP - 1] * lprev;
+                    } else {
+                      w = r[k] - VT(0.25) * ((rcur + lcur) + (up + dnv));
+                    }
+                    p[k] = r[k] + b_ * p[k];
+                    s[k] = w + b_ * s[k];
+                    pd += w * r[k];
+                    lprev = lcur;
+                    rcur = rnxt;
+                  }
+                  // keep the scheduler from hoisting every node's LDS loads
+                  // to the top (register pressure at 1024 threads)
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+              }
+              double dv[1] = {(double)pd};
+              block_sum<1, NWAVES>(dv, red, slot);
+              alpha = it == 0 ? gam / dv[0] : gam / (dv[0] - beta * gam / alpha);
+              gam_prev = gam;
+              const VT a_ = vt<VT>(alpha);
+#pragma unroll
+              for (int k = 0; k < SH; ++k) {
+                y[k] = y[k] + a_ * p[k];
+                r[k] = r[k] - a_ * s[k];
+              }
+            }
+            it_step += it;
+            // stage y in the thread's own LDS cells (read back by the same
+            // thread only), then x += D^{-1/2} y in FP64
+#pragma unroll
+            for (int k = 0; k < SH; ++k)
+              if (ACT(k)) rl[l0 + k * LP] = y[k];
+#pragma unroll 1
+            for (int k = 0; k < SH; ++k)
+              if (ACT(k)) Xv[gi0 + k * g.P] += DN(k) * (double)rl[l0 + k * LP];
+            __syncthreads();
+          }
+          if (!conv) flags |= FLAG_NOT_CONVERGED;
+        }
+        it_total += it_step;
+        it_max_step = it_step > it_max_step ? it_step : it_max_step;
+        // Joule-loss term d^T M d / dt and the state update a += d
+        double qq[1] = {0.0};
+#pragma unroll 1
+        for (int k = 0; k < SH; ++k) {
+          const NodeRef nr = NREF(k);
+          if (ACT(k) && nr.inL) qq[0] += Xv[nr.gi] * M_apply(g, tab, Xv, nr);
+        }
+        block_sum<1, NWAVES>(qq, red, slot);
+        qsum += qq[0] * inv_dt;
+#pragma unroll 1
+        for (int k = 0; k < SH; ++k)
+          if (ACT(k)) Av[gi0 + k * g.P] += Xv[gi0 + k * g.P];
+        __syncthreads();
+      }
+      if (in.n_chain > 0) {
+        // Parareal coarse chain: A holds C(U_{n-1}); U_n = F_n + (C_new - C_old_n)
+        const double* Fn = in.chain_f[seg];
+        double* Cn = in.chain_c[seg];
+        double* Un = in.chain_u[seg];
+#pragma unroll 1
+        for (int k = 0; k < SH; ++k) {
+          if (ACT(k)) {
+            const int gi = gi0 + k * g.P;
+            const double cn = Av[gi];
+            const double u = Fn ? Fn[gi] + (cn - Cn[gi]) : cn;
+            Cn[gi] = cn;
+            Un[gi] = u;
+            Av[gi] = u;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (in.a_out) {
+#pragma unroll 1
+      for (int k = 0; k < SH; ++k)
+        if (ACT(k)) in.a_out[gi0 + k * g.P] = Av[gi0 + k * g.P];
+    }
+    if (tid == 0) {
+      if (in.q_out) *in.q_out = qsum * in.q_scale;
+      if (in.stat) {
+        in.stat[0] = it_total;
+        in.stat[1] = sw_total;
+        in.stat[2] = it_max_step;
+        in.stat[3] = flags;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct ResCfg {
+  int cw, sh, ns, tp;
+};
+
+template <typename VT>
+static size_t resident_lds(const Geom& g, const ResCfg& c) {
+  const int nw = c.cw * c.ns / 64;
+  return 2 * nw * 4 * sizeof(double) +
+         (size_t)((g.n + 2) * (c.cw + 2) + 4 * g.RH * c.tp) * sizeof(VT);
+}
+
+static bool pick_resident(const Geom& g, ResCfg* c) {
+  if (g.n <= 31) {
+    *c = {32, 16, 2, 32};
+  } else if (g.n <= 63) {
+    *c = {64, 16, 4, 64};
+  } else if (g.n <= 127) {
+    *c = {128, 16, 8, 64};
+  } else {
+    return false;
+  }
+  return g.n <= c->sh * c->ns && g.RW <= c->tp;
+}
+
+int resident_supported(const Geom& g, int precision, int lds_limit, int* lds_bytes) {
+  ResCfg c;
+  if (!pick_resident(g, &c)) return 0;
+  // 1024-thread FP64 workgroups would need more than 128 VGPRs per lane
+  if (precision == MQ_PREC_FP64 && c.cw * c.ns > 256) return 0;
+  size_t b = precision == MQ_PREC_FP64 ? resident_lds<double>(g, c) : resident_lds<float>(g, c);
+  if (lds_bytes) *lds_bytes = (int)b;
+  return b <= (size_t)lds_limit ? 1 : 0;
+}
+
+size_t ie_work_doubles(const Geom& g) { return 3 * (size_t)g.N * g.P; }
+
+template <typename VT, int CW, int SH, int NS, int TP>
+static hipError_t launch_res(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+                             int* counter, double* work, int max_grid, const double* S,
+                             int* grid_out, int* block_out, hipStream_t st) {
+  constexpr int NT = CW * NS;
+  const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP});
+  auto kern = k_ie_resident<VT, CW, SH, NS, TP>;
+  hipError_t e0 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e0 != hipSuccess) return e0;
+  const int grid = max_grid < n_inst ? max_grid : n_inst;
+  if (grid_out) *grid_out = grid;
+  if (block_out) *block_out = NT;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, g, sv, insts, n_inst, counter, work, S);
+  return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t dispatch_res(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+                               int* counter, double* work, int max_grid, const double* S,
+                               int* grid_out, int* block_out, hipStream_t st) {
+  ResCfg c;
+  if (!pick_resident(g, &c)) return hipErrorInvalidValue;
+  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  return launch_res<VT, 128, 16, 8, 64>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+}
+
+int ie_slots_per_cu(const Geom& g, int path, int precision) {
+  ResCfg c;
+  if (path == MQ_PATH_RESIDENT && pick_resident(g, &c)) {
+    int nb = 0;
+    const int nt = c.cw * c.ns;
+    hipError_t e;
+    if (precision == MQ_PREC_FP64) {
+      size_t lds = resident_lds<double>(g, c);
+      if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 32, 16, 2, 32>, nt, lds);
+      else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 64, 16, 4, 64>, nt, lds);
+      else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 128, 16, 8, 64>, nt, lds);
+    } else {
+      size_t lds = resident_lds<float>(g, c);
+      if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 32, 16, 2, 32>, nt, lds);
+      else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 64, 16, 4, 64>, nt, lds);
+      else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 128, 16, 8, 64>, nt, lds);
+    }
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+  }
+  return 2;
+}
+
+hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+                            int* counter, double* work, int n_slots, int max_grid, const double* S,
+                            int* grid_out, int* block_out, hipStream_t st);
+
+// n_slots: slots the work buffer was laid out for; max_grid (<= n_slots):
+// workgroups to launch.
+hipError_t launch_ie(const Geom& g, const Solver& sv, const Inst* insts, int n_inst, int* counter,
+                     double* work, int n_slots, int max_grid, const double* S, int path, int precision,
+                     const CellRegion& cr, const uint8_t* cond, const double* nl_params,
+                     int* grid_out, int* block_out, hipStream_t st) {
+  (void)cr;
+  (void)cond;
+  (void)nl_params;
+  if (max_grid > n_slots) max_grid = n_slots;
+  if (path == MQ_PATH_RESIDENT) {
+    if (precision == MQ_PREC_FP64)
+      return dispatch_res<double>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+    return dispatch_res<float>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  }
+  return launch_ie_stream(g, sv, insts, n_inst, counter, work, n_slots, max_grid, S, grid_out, block_out, st);
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_apply(Geom g, int which, double inv_dt, const double* __restrict__ tables, int nsmp,
+                        const double* __restrict__ x, double* __restrict__ y, double* scratch) {
+  // scratch: full-grid copy of x per sample, boundary zero
+  const int nd = g.n * g.n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (idx >= nd || smp >= nsmp) return;
+  const size_t FS = (size_t)g.N * g.P;
+  const double* v = scratch + smp * FS;
+  const double* tab = tables + (size_t)smp * T_NPLANES * g.RW * g.RH;
+  const int i = idx % g.n, j = idx / g.n;
+  const NodeRef nr = node_ref(g, i, j);
+  double out;
+  if (which == MQ_APPLY_M) out = M_apply(g, tab, v, nr);
+  else if (which == MQ_APPLY_K) out = K_apply(g, tab, v, nr);
+  else out = A_apply(g, tab, v, nr, inv_dt);
+  y[(size_t)smp * nd + idx] = out;
+}
+
+__global__ void k_scatter_full(Geom g, int nsmp, const double* __restrict__ in, double* out) {
+  const int nd = g.n * g.n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (idx >= nd || smp >= nsmp) return;
+  const int i = idx % g.n, j = idx / g.n;
+  out[(size_t)smp * g.N * g.P + (j + 1) * g.P + i + 1] = in[(size_t)smp * nd + idx];
+}
+
+__global__ void k_zero(double* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+__global__ void k_zero_i(int* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero_i, dim3(blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const Geom& g, int which, double dt, const double* tables, int n,
+                        const double* x, double* y, hipStream_t st) {
+  // x: [n][nd] interior order; builds full-grid copies in y's scratch? Use a temporary.
+  const size_t FS = (size_t)g.N * g.P;
+  double* scratch = nullptr;
+  hipError_t e = hipMallocAsync((void**)&scratch, FS * n * sizeof(double), st);
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero(scratch, FS * n, st);
+  if (e != hipSuccess) return e;
+  const int nd = g.n * g.n;
+  dim3 grid((nd + 255) / 256, n);
+  hipLaunchKernelGGL(k_scatter_full, grid, dim3(256), 0, st, g, n, x, scratch);
+  hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, st, g, which, 1.0 / dt, tables, n, x, y, scratch);
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(scratch, st);
+  return e != hipSuccess ? e : e2;
+}
+
+__global__ void k_gather_interior(Geom g, const double* const* full, double* out) {
+  const int nd = g.n * g.n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (idx >= nd) return;
+  const int i = idx % g.n, j = idx / g.n;
+  out[(size_t)smp * nd + idx] = full[smp][(j + 1) * g.P + i + 1];
+}
+
+hipError_t launch_to_interior(const Geom& g, int n, const double* const* full, double* out,
+                              hipStream_t st) {
+  const int nd = g.n * g.n;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_interior, dim3((nd + 255) / 256, n), dim3(256), 0, st, g, full, out);
+  return hipGetLastError();
+}
+
+__global__ void k_scatter_interior(Geom g, const double* in, double* const* full) {
+  const int nd = g.n * g.n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (idx >= nd) return;
+  const int i = idx % g.n, j = idx / g.n;
+  full[smp][(j + 1) * g.P + i + 1] = in[(size_t)smp * nd + idx];
+}
+
+hipError_t launch_to_full(const Geom& g, int n, const double* in, double* const* full, hipStream_t st) {
+  const int nd = g.n * g.n;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_interior, dim3((nd + 255) / 256, n), dim3(256), 0, st, g, in, full);
+  return hipGetLastError();
+}
+
+// Level statistics of Eq. (9): one workgroup (256 threads) per level; each
+// thread sums a contiguous chunk in sample order, chunks are combined by a
+// fixed binary tree.  out = {E, Y_0..Y_L, V_0..V_L}; E is summed over levels
+// in order by the last block to finish (a second tiny kernel).
+__global__ void k_level_stats(const int* nper, const double* const* qf, const double* const* qc,
+                              double* out, int n_levels) {
+  const int l = blockIdx.x;
+  const int N = nper[l];
+  const double* f = qf[l];
+  const double* c = (l > 0) ? qc[l] : nullptr;
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const int chunk = (N + 255) / 256;
+  const int b = tid * chunk, e = min(N, b + chunk);
+  double s = 0.0;
+  for (int k = b; k < e; ++k) s += c ? f[k] - c[k] : f[k];
+  sh[tid] = s;
+  __syncthreads();
+  for (int m = 128; m >= 1; m >>= 1) {
+    if (tid < m) sh[tid] = sh[tid] + sh[tid + m];
+    __syncthreads();
+  }
+  const double mean = sh[0] / N;
+  __syncthreads();
+  double v = 0.0;
+  for (int k = b; k < e; ++k) {
+    const double d = (c ? f[k] - c[k] : f[k]) - mean;
+    v += d * d;
+  }
+  sh[tid] = v;
+  __syncthreads();
+  for (int m = 128; m >= 1; m >>= 1) {
+    if (tid < m) sh[tid] = sh[tid] + sh[tid + m];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[1 + l] = mean;
+    out[1 + n_levels + l] = N > 1 ? sh[0] / (N - 1) : 0.0;
+  }
+}
+
+__global__ void k_level_total(double* out, int n_levels) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double e = 0.0;
+    for (int l = 0; l < n_levels; ++l) e += out[1 + l];
+    out[0] = e;
+  }
+}
+
+hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double* const* qf,
+                              const double* const* qc, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_stats, dim3(n_levels), dim3(256), 0, st, n_per_level, qf, qc, out, n_levels);
+  hipLaunchKernelGGL(k_level_total, dim3(1), dim3(64), 0, st, out, n_levels);
+  return hipGetLastError();
+}
+
+// Interface jumps: for pair p, out2[2p] = ||F - U||^2, out2[2p+1] = ||F||^2 over interior nodes.
+__global__ void k_jumps(Geom g, const double* const* f, const double* const* u, double* out2) {
+  const int pidx = blockIdx.x;
+  const double* F = f[pidx];
+  const double* U = u[pidx];
+  const int nd = g.n * g.n;
+  double a = 0.0, b = 0.0;
+  for (int idx = threadIdx.x; idx < nd; idx += blockDim.x) {
+    const int i = idx % g.n, j = idx / g.n;
+    const int gi = (j + 1) * g.P + i + 1;
+    const double d = F[gi] - U[gi];
+    a += d * d;
+    b += F[gi] * F[gi];
+  }
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int m = 128; m >= 1; m >>= 1) {
+    if ((int)threadIdx.x < m) {
+      sa[threadIdx.x] += sa[threadIdx.x + m];
+      sb[threadIdx.x] += sb[threadIdx.x + m];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[2 * pidx] = sa[0];
+    out2[2 * pidx + 1] = sb[0];
+  }
+}
+
+hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f, const double* const* u,
+                        double* out2, hipStream_t st) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jumps, dim3(n_pairs), dim3(256), 0, st, g, f, u, out2);
+  return hipGetLastError();
+}
+
+__global__ void k_check_finite(const double* x, size_t n, int* bad) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_check_finite, dim3(blocks), dim3(256), 0, st, x, n, bad);
+  return hipGetLastError();
+}
+
+}  // namespace mq
+
+namespace mq {
+
+// ---------------------------------------------------------------------------
+// streaming time-stepping kernel (CG vectors in global memory)
+// ---------------------------------------------------------------------------
+// Same instance loop and solver as k_ie_resident; each thread walks interior
+// nodes idx = tid, tid + NT, ... (row-major, coalesced).  Per slot the VT
+// workspace holds R (full grid, zero ring), Y, P, S, W and the scaled tables.
+template <typename VT>
+__device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, const VT* tE,
+                                    const VT* tN, const VT* tNE, const NodeRef& nr) {
+  const int gi = nr.gi, P = g.P;
+  const VT c = R[gi], e = R[gi + 1], w = R[gi - 1], nn = R[gi + P], s = R[gi - P];
+  if (!nr.inL) return c - VT(0.25) * ((e + w) + (nn + s));
+  const int t = nr.t;
+  return c + tE[t] * e + tE[t - 1] * w + tN[t] * nn + tN[t - g.RW] * s + tNE[t] * R[gi + P + 1] +
+         tNE[t - g.RW - 1] * R[gi - P - 1];
+}
+
+template <typename VT, int NT>
+__global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst* __restrict__ insts,
+                                                  int n_inst, int* counter, double* work,
+                                                  const double* __restrict__ S, VT* vwork) {
+  constexpr int NWAVES = NT / 64;
+  __shared__ double red[2 * NWAVES * 4];
+  __shared__ int s_inst;
+  const int tid = threadIdx.x;
+  const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
+  const size_t FS = (size_t)g.N * g.P;
+  double* Av = work + (size_t)blockIdx.x * 3 * FS;
+  double* Xv = Av + FS;
+  double* Bv = Xv + FS;
+  VT* Rv = vwork + (size_t)blockIdx.x * (5 * FS + 4 * (size_t)RHW);
+  VT* Yv = Rv + FS;
+  VT* Pv = Yv + FS;
+  VT* Sv = Pv + FS;
+  VT* Wv = Sv + FS;
+  VT* tE = Wv + FS;
+  VT* tN = tE + RHW;
+  VT* tNE = tN + RHW;
+  VT* tD = tNE + RHW;
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  const int lw = g.lx1 - g.bx0, lh = g.ly1 - g.by0;
+  int slot = 0;
+
+  for (;;) {
+    if (tid == 0) s_inst = atomicAdd(counter, 1);
+    __syncthreads();
+    const int id = s_inst;
+    __syncthreads();
+    if (id >= n_inst) break;
+    const Inst in = insts[id];
+    const double* tab = in.tab;
+    const double inv_dt = 1.0 / in.dt;
+    auto dscale = [&](int i, int j) -> double {
+      if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
+        const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
+        return 1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]);
+      }
+      return d_air;
+    };
+    for (int t = tid; t < RHW; t += NT) {
+      const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
+      const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+      const double di = dscale(i, j);
+      double e = -0.25, nn = -0.25, ne = 0.0;
+      if (box) {
+        e = (tab[T_ME * RHW + t] * inv_dt + tab[T_KE * RHW + t]) * di * dscale(i + 1, j);
+        nn = (tab[T_MN * RHW + t] * inv_dt + tab[T_KN * RHW + t]) * di * dscale(i, j + 1);
+        ne = tab[T_MNE * RHW + t] * inv_dt * di * dscale(i + 1, j + 1);
+      }
+      tE[t] = (VT)e;
+      tN[t] = (VT)nn;
+      tNE[t] = (VT)ne;
+      tD[t] = (VT)di;
+    }
+    for (int idx = tid; idx < nd; idx += NT) {
+      const int gi = (idx / n + 1) * g.P + idx % n + 1;
+      Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
+      Xv[gi] = 0.0;
+    }
+    __syncthreads();
+    auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
+      const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+      return box ? tD[nr.t] : (VT)d_air;
+    };
+
+    double qsum = 0.0;
+    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
+    const int n_seg = in.n_chain > 0 ? in.n_chain : 1;
+    for (int seg = 0; seg < n_seg; ++seg) {
+      const int kseg0 = in.k0 + seg * in.n_steps;
+      for (int step = 0; step < in.n_steps; ++step) {
+        const double Jt = in.src[kseg0 + step + 1];
+        double part[1] = {0.0};
+        for (int idx = tid; idx < nd; idx += NT) {
+          const NodeRef nr = node_ref(g, idx % n, idx / n);
+          const double b = Jt * S[nr.gi] - K_apply(g, tab, Av, nr);
+          Bv[nr.gi] = b;
+          part[0] += b * b;
+        }
+        block_sum<1, NWAVES>(part, red, slot);
+        const double bb = part[0];
+        int it_step = 0;
+        if (bb == 0.0) {
+          for (int idx = tid; idx < nd; idx += NT) Xv[(idx / n + 1) * g.P + idx % n + 1] = 0.0;
+          __syncthreads();
+        } else {
+          bool conv = false;
+          for (int sweep = 0; sweep <= sv.max_sweeps; ++sweep) {
+            double rr[1] = {0.0};
+            for (int idx = tid; idx < nd; idx += NT) {
+              const int i = idx % n, j = idx / n;
+              const NodeRef nr = node_ref(g, i, j);
+              const double res = Bv[nr.gi] - A_apply(g, tab, Xv, nr, inv_dt);
+              rr[0] += res * res;
+              Rv[nr.gi] = (VT)(res * (double)dnode(i, j, nr));
+              Yv[nr.gi] = VT(0);
+              Pv[nr.gi] = VT(0);
+              Sv[nr.gi] = VT(0);
+            }
+            block_sum<1, NWAVES>(rr, red, slot);
+            if (!(rr[0] == rr[0]) || isinf(rr[0])) {
+              flags |= FLAG_FAILED;
+              break;
+            }
+            if (rr[0] <= sv.tol * sv.tol * bb) {
+              conv = true;
+              break;
+            }
+            if (sweep == sv.max_sweeps) break;
+            sw_total++;
+            double gd[2] = {0.0, 0.0};
+            for (int idx = tid; idx < nd; idx += NT) {
+              const NodeRef nr = node_ref(g, idx % n, idx / n);
+              const VT w = stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr);
+              const VT r = Rv[nr.gi];
+              Wv[nr.gi] = w;
+              gd[0] += (double)(r * r);
+              gd[1] += (double)(w * r);
+            }
+            block_sum<2, NWAVES>(gd, red, slot);
+            const double g0 = gd[0];
+            double gam = gd[0], alpha = gd[0] / gd[1], beta = 0.0;
+            const double stop = sv.inner_rtol * sv.inner_rtol * g0;
+            int it = 0;
+            if (g0 > 0.0) {
+              for (it = 1; it <= sv.max_iter; ++it) {
+                const VT a_ = (VT)alpha, b_ = (VT)beta;
+                for (int idx = tid; idx < nd; idx += NT) {
+                  const int gi = (idx / n + 1) * g.P + idx % n + 1;
+                  const VT p = Rv[gi] + b_ * Pv[gi];
+                  const VT s = Wv[gi] + b_ * Sv[gi];
+                  Pv[gi] = p;
+                  Sv[gi] = s;
+                  Yv[gi] = Yv[gi] + a_ * p;
+                  Rv[gi] = Rv[gi] - a_ * s;
+                }
+                __syncthreads();
+                gd[0] = 0.0;
+                gd[1] = 0.0;
+                for (int idx = tid; idx < nd; idx += NT) {
+                  const NodeRef nr = node_ref(g, idx % n, idx / n);
+                  const VT w = stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr);
+                  const VT r = Rv[nr.gi];
+                  Wv[nr.gi] = w;
+                  gd[0] += (double)(r * r);
+                  gd[1] += (double)(w * r);
+                }
+                block_sum<2, NWAVES>(gd, red, slot);
+                if (gd[0] <= stop || !(gd[0] == gd[0])) break;
+                const double bn = gd[0] / gam;
+                alpha = gd[0] / (gd[1] - bn * gd[0] / alpha);
+                beta = bn;
+                gam = gd[0];
+              }
+              if (it > sv.max_iter) it = sv.max_iter;
+            }
+            it_step += it;
+            for (int idx = tid; idx < nd; idx += NT) {
+              const int i = idx % n, j = idx / n;
+              const NodeRef nr = node_ref(g, i, j);
+              Xv[nr.gi] += (double)dnode(i, j, nr) * (double)Yv[nr.gi];
+            }
+            __syncthreads();
+          }
+          if (!conv) flags |= FLAG_NOT_CONVERGED;
+        }
+        it_total += it_step;
+        it_max_step = it_step > it_max_step ? it_step : it_max_step;
+        double qq[1] = {0.0};
+        for (int idx = tid; idx < lw * lh; idx += NT) {
+          const NodeRef nr = node_ref(g, g.bx0 + idx % lw, g.by0 + idx / lw);
+          qq[0] += Xv[nr.gi] * M_apply(g, tab, Xv, nr);
+        }
+        block_sum<1, NWAVES>(qq, red, slot);
+        qsum += qq[0] * inv_dt;
+        for (int idx = tid; idx < nd; idx += NT) {
+          const int gi = (idx / n + 1) * g.P + idx % n + 1;
+          Av[gi] += Xv[gi];
+        }
+        __syncthreads();
+      }
+      if (in.n_chain > 0) {
+        const double* Fn = in.chain_f[seg];
+        double* Cn = in.chain_c[seg];
+        double* Un = in.chain_u[seg];
+        for (int idx = tid; idx < nd; idx += NT) {
+          const int gi = (idx / n + 1) * g.P + idx % n + 1;
+          const double cn = Av[gi];
+          const double u = Fn ? Fn[gi] + (cn - Cn[gi]) : cn;
+          Cn[gi] = cn;
+          Un[gi] = u;
+          Av[gi] = u;
+        }
+        __syncthreads();
+      }
+    }
+    if (in.a_out) {
+      for (int idx = tid; idx < nd; idx += NT) {
+        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        in.a_out[gi] = Av[gi];
+      }
+    }
+    if (tid == 0) {
+      if (in.q_out) *in.q_out = qsum * in.q_scale;
+      if (in.stat) {
+        in.stat[0] = it_total;
+        in.stat[1] = sw_total;
+        in.stat[2] = it_max_step;
+        in.stat[3] = flags;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int STREAM_NT = 1024;
+
+size_t stream_vwork_elems(const Geom& g) {
+  return 5 * (size_t)g.N * g.P + 4 * (size_t)g.RW * g.RH;
+}
+
+hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+                            int* counter, double* work, int n_slots, int max_grid, const double* S,
+                            int* grid_out, int* block_out, hipStream_t st) {
+  // the VT workspace follows the FP64 work buffers of all n_slots slots
+  const int grid = max_grid < n_inst ? max_grid : n_inst;
+  if (grid_out) *grid_out = grid;
+  if (block_out) *block_out = STREAM_NT;
+  double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
+  if (sv.precision == MQ_PREC_FP64) {
+    hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT>), dim3(grid), dim3(STREAM_NT), 0, st, g, sv,
+                       insts, n_inst, counter, work, S, vbase);
+  } else {
+    hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT>), dim3(grid), dim3(STREAM_NT), 0, st, g, sv,
+                       insts, n_inst, counter, work, S, reinterpret_cast<float*>(vbase));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mq

@@ -1,0 +1,108 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mq.h"
+
+namespace mq {
+
+// Geometry of one structured mesh as seen by the kernels.
+//
+// Interior nodes (i, j), 0 <= i, j < n = N - 2, are the unknowns.  FP64 state
+// vectors live on the full N x N grid (boundary ring = the Dirichlet zeros)
+// with row pitch P: node (i, j) sits at (j + 1) * P + (i + 1).
+//
+// Only rows of nodes near the conductor depend on the sample.  The "box"
+// [bx0, bx1) x [by0, by1) is the bounding rectangle of the interior nodes that
+// touch a conductor element, grown by one node; every matrix entry owned by a
+// node outside the box (its E, N, NE couplings and its diagonal) is the air
+// value.  Stencil tables cover the region R = [bx0-1, bx1+1) x [by0-1, by1+1)
+// (RW x RH nodes, air constants outside the box), so a node in the lookup
+// region L = [bx0, bx1+1) x [by0, by1+1) reads all six of its couplings
+// (own E, N, NE; W = E(i-1, j), S = N(i, j-1), SW = NE(i-1, j-1)) from tables,
+// and every other node uses the constant air stencil.
+struct Geom {
+  int N, n, P;
+  int bx0, bx1, by0, by1;
+  int lx1, ly1;   // lookup region upper bounds (exclusive, clipped to n)
+  int RW, RH;     // table region size
+  double h, h2, nu_air;
+};
+
+// FP64 coefficient planes of one sample over the table region R.
+enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
+
+// Element data over the cells that touch the box: full-grid cells
+// [bx0, bx1 + 1) x [by0, by1 + 1), two triangles per cell
+// (t = 0: {(I,J), (I+1,J), (I+1,J+1)}, t = 1: {(I,J), (I+1,J+1), (I,J+1)}).
+struct CellRegion {
+  int cx0, cy0, cw, ch;  // first cell (full-grid cell coords) and extent
+};
+
+// One time-integration instance (a sample on one time grid, or one Parareal
+// slice / coarse chain).
+struct Inst {
+  const double* tab;     // FP64 tables of the sample [T_NPLANES][RH*RW]
+  const double* src;     // J(t_k) by global step index k for this dt
+  const double* a_init;  // full-grid initial state or null (zeros)
+  double* a_out;         // full-grid final state or null
+  double* q_out;         // receives q_scale * sum_k d_k^T M d_k / dt
+  double q_scale;
+  int* stat;             // [4]: inner iterations, sweeps, max inner per step, flags
+  double dt;
+  int n_steps;           // steps per chain segment
+  int k0;                // global index of the first step
+  // Parareal coarse-chain mode (n_chain > 0): run segments s = 0..n_chain-1
+  // from chain_u[s] ... see kernels for the exact recurrence.
+  int n_chain;
+  double* const* chain_u;       // U_n full-grid states (in/out)
+  const double* const* chain_f; // F_n fine end states
+  double* const* chain_c;       // C_old_n coarse values (in/out)
+  int sample;                   // sample index (nonlinear coefficients)
+};
+
+struct Solver {
+  int precision;   // MQ_PREC_*
+  double tol, inner_rtol;
+  int max_iter, max_sweeps;
+  // nonlinear material
+  int nonlinear;
+  double picard_tol;
+  int picard_max;
+};
+
+enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
+
+// Launch helpers implemented in the .hip translation units.
+int resident_supported(const Geom& g, int precision, int lds_limit, int* lds_bytes);
+hipError_t launch_assemble(const Geom& g, const CellRegion& cr, const uint8_t* cond,
+                           const double* kltab, int n_modes, int material, const double* xi,
+                           int n_xi, int n_samples, const double* mat_params, double* tables,
+                           hipStream_t st);
+hipError_t launch_ie(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+                     int* counter, double* work, int n_slots, int max_grid, const double* S, int path,
+                     int precision, const CellRegion& cr, const uint8_t* cond,
+                     const double* nl_params, int* grid_out, int* block_out, hipStream_t st);
+hipError_t launch_apply(const Geom& g, int which, double dt, const double* tables, int n,
+                        const double* x, double* y, hipStream_t st);
+hipError_t launch_to_interior(const Geom& g, int n, const double* const* full, double* out,
+                              hipStream_t st);
+hipError_t launch_to_full(const Geom& g, int n, const double* in, double* const* full,
+                          hipStream_t st);
+hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double* const* qf,
+                              const double* const* qc, double* out, hipStream_t st);
+hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
+                        const double* const* u, double* out2, hipStream_t st);
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
+hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
+hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);
+int ie_slots_per_cu(const Geom& g, int path, int precision);
+size_t ie_work_doubles(const Geom& g);
+size_t stream_vwork_elems(const Geom& g);
+
+}  // namespace mq

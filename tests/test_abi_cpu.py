@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+that include/mq.h declares, its ctypes structs match the C layout, and calls
+without a GPU fail cleanly with the documented status codes."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "mq.h")
+
+
+def header_functions():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (load the HIP runtime that torch ships first)
+    from paper_2507_19246_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmq.so not built")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ["fem_setup", "mlmc_level_run", "parareal_run", "mlmc_estimate", "mq_debug_apply",
+                 "mq_server_create", "mq_submit", "mq_poll", "mq_server_destroy", "mq_last_error"]:
+        assert name in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2507_19246_amd import _lib
+    fns = header_functions()
+    for name in fns:
+        assert hasattr(lib, name), name
+    assert set(fns) == set(_lib.SIGNATURES), set(fns) ^ set(_lib.SIGNATURES)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    from paper_2507_19246_amd import _lib
+    structs = {"mq_problem_desc": _lib.ProblemDesc, "mq_problem_info": _lib.ProblemInfo,
+               "mq_run_stats": _lib.RunStats, "mq_level_desc": _lib.LevelDesc,
+               "mq_parareal_desc": _lib.PararealDesc, "mq_server_desc": _lib.ServerDesc,
+               "mq_request": _lib.Request, "mq_result": _lib.Result}
+    src = tmp_path / "sz.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void){']
+    for cname in structs:
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+    lines.append('printf("off_tol %zu\\n", offsetof(mq_problem_desc, tol));')
+    lines.append('printf("off_kernel_ms %zu\\n", offsetof(mq_run_stats, kernel_ms));')
+    lines.append('printf("off_t_done %zu\\n", offsetof(mq_result, t_done_ns));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-o", str(exe), str(src)])
+    out = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in structs.items():
+        assert int(out[cname]) == C.sizeof(cls), cname
+    assert int(out["off_tol"]) == _lib.ProblemDesc.tol.offset
+    assert int(out["off_kernel_ms"]) == _lib.RunStats.kernel_ms.offset
+    assert int(out["off_t_done"]) == _lib.Result.t_done_ns.offset
+
+
+def test_no_device_and_invalid_arguments(lib):
+    import torch
+    from paper_2507_19246_amd import _lib
+    import workloads as W
+    from paper_2507_19246_amd.api import default_desc
+    d = default_desc(W.plain_fp64_33().problem, _lib.MQ_PREC_FP64)
+    h = C.c_void_p()
+    bad = _lib.ProblemDesc.from_buffer_copy(d)
+    bad.n_nodes = 2
+    assert lib.fem_setup(C.byref(bad), None, C.byref(h)) == _lib.MQ_ERR_INVALID_ARG
+    assert b"n_nodes" in lib.mq_last_error()
+    bad = _lib.ProblemDesc.from_buffer_copy(d)
+    bad.tol = 0.0
+    assert lib.fem_setup(C.byref(bad), None, C.byref(h)) == _lib.MQ_ERR_INVALID_ARG
+    if not torch.cuda.is_available():
+        assert lib.fem_setup(C.byref(d), None, C.byref(h)) == _lib.MQ_ERR_NO_DEVICE
+        assert not h.value
+    # estimator argument validation happens before any device work
+    ns = (C.c_int32 * 2)(3, 0)
+    null = (C.c_void_p * 2)()
+    assert lib.mlmc_estimate(2, ns, null, null, None, None) == _lib.MQ_ERR_INVALID_ARG
+    assert lib.mq_problem_destroy(None) == _lib.MQ_OK

@@ -1,0 +1,197 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances: FP64 path 1e-10 relative on Q and on the final state; mixed
+path (FP32 CG inside FP64 refinement) 1e-6 relative on Q.  Operator applies
+are compared entry-wise at FP64 rounding level.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem, mesh as omesh, mlmc as omlmc, parareal as opara, timestep as ots
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_19246_amd as mq
+    mq.load()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mqmod():
+    import paper_2507_19246_amd as mq
+    from paper_2507_19246_amd import _lib
+    return mq, _lib
+
+
+def oracle_q(problem, xi, spp, nper):
+    m = omesh.build(problem.n_nodes)
+    tab = ots.kl_table_for(problem, m)
+    out = [ots.solve_sample(problem, x, spp, nper, m=m, kl_table=tab) for x in xi]
+    return np.array([o[0] for o in out]), np.stack([o[1] for o in out])
+
+
+@pytest.mark.parametrize("n,kind", [(5, 0), (9, 1), (33, 0), (33, 1), (129, 1)])
+def test_operator_apply_matches_oracle(n, kind):
+    mq, L = mqmod()
+    say(f"apply n={n} kind={kind}")
+    prob = W.Problem(n, W.Material(kind=kind))
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    nxi = prob.material.n_xi
+    xi = W.normals(3, 11, 0, range(3), nxi)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((3, prob.n_dof))
+    dt = 1e-4
+    m = omesh.build(n)
+    tab = ots.kl_table_for(prob, m)
+    for which in (L.MQ_APPLY_A, L.MQ_APPLY_M, L.MQ_APPLY_K):
+        y = mq.debug_apply(p, which, dt, xi, x).cpu().numpy()
+        for s in range(3):
+            sysm = ots.build_system(prob, xi[s], m, tab)
+            Mat = {L.MQ_APPLY_A: sysm.M / dt + sysm.K, L.MQ_APPLY_M: sysm.M, L.MQ_APPLY_K: sysm.K}[which]
+            ref = Mat @ x[s]
+            scale = abs(Mat) @ np.abs(x[s]) + 1e-300
+            assert np.max(np.abs(y[s] - ref) / scale.max()) < 1e-14, (which, s)
+    p.close()
+
+
+def test_plain_fp64_33_full_parity():
+    """Plain MC, FP64, 33x33, 16 samples, 64 steps: Q and a_N within 1e-10."""
+    mq, L = mqmod()
+    w = W.plain_fp64_33()
+    lv = w.levels[0]
+    xi = W.level_xi(w, 0)
+    say("plain fp64 33 full")
+    p = mq.Problem(w.problem, L.MQ_PREC_FP64)
+    qf, qc, fs, rc, st = mq.mlmc_level_run(p, lv.steps_per_period, 0, lv.n_periods, xi, want_state=True)
+    assert rc == 0 and qc is None
+    say("stats", st)
+    qref, aref = oracle_q(w.problem, xi, lv.steps_per_period, lv.n_periods)
+    q = qf.cpu().numpy()
+    err = np.abs(q - qref) / np.abs(qref)
+    say("max rel err Q", err.max())
+    assert err.max() <= 1e-10
+    a = fs.cpu().numpy()
+    for s in range(len(xi)):
+        assert np.linalg.norm(a[s] - aref[s]) <= 1e-10 * np.linalg.norm(aref[s])
+    p.close()
+
+
+@pytest.mark.parametrize("n,path", [(33, 1), (33, 2), (65, 1), (65, 2)])
+def test_mixed_kl_coupled_level(n, path):
+    """Mixed precision, KL field, coupled fine/coarse run: Q within 1e-6."""
+    mq, L = mqmod()
+    prob = W.Problem(n, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 21, 1, range(6), 8)
+    say(f"mixed kl n={n} path={path}")
+    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path)
+    qf, qc, _, rc, st = mq.mlmc_level_run(p, 32, 16, 2, xi)
+    assert rc == 0
+    say("stats", st)
+    rf, _ = oracle_q(prob, xi, 32, 2)
+    rcq, _ = oracle_q(prob, xi, 16, 2)
+    ef = np.abs(qf.cpu().numpy() - rf) / np.abs(rf)
+    ec = np.abs(qc.cpu().numpy() - rcq) / np.abs(rcq)
+    say("max rel err fine/coarse", ef.max(), ec.max())
+    assert ef.max() <= 1e-6 and ec.max() <= 1e-6
+    p.close()
+
+
+def test_streaming_fp64_matches_oracle():
+    mq, L = mqmod()
+    w = W.plain_fp64_33()
+    xi = W.level_xi(w, 0, 4)
+    p = mq.Problem(w.problem, L.MQ_PREC_FP64, path=L.MQ_PATH_STREAMING)
+    qf, _, _, rc, st = mq.mlmc_level_run(p, 64, 0, 1, xi)
+    qref, _ = oracle_q(w.problem, xi, 64, 1)
+    assert np.max(np.abs(qf.cpu().numpy() - qref) / qref) <= 1e-10
+    p.close()
+
+
+def test_deterministic_and_alone_equals_mix():
+    mq, L = mqmod()
+    prob = W.Problem(33, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 22, 0, range(10), 8)
+    p = mq.Problem(prob, L.MQ_PREC_MIXED)
+    q1 = mq.mlmc_level_run(p, 32, 16, 1, xi)[0].cpu().numpy()
+    q2 = mq.mlmc_level_run(p, 32, 16, 1, xi)[0].cpu().numpy()
+    assert np.array_equal(q1, q2)
+    for k in (0, 7):
+        qa = mq.mlmc_level_run(p, 32, 16, 1, xi[k:k + 1])[0].cpu().numpy()
+        assert qa[0] == q1[k]
+    p.close()
+
+
+def test_mlmc_estimate_matches_oracle():
+    mq, L = mqmod()
+    rng = np.random.default_rng(3)
+    qf = [rng.normal(10, 1, 37), rng.normal(1, 0.1, 11), rng.normal(0.1, 0.01, 5)]
+    qc = [None, rng.normal(1, 0.1, 11), rng.normal(0.1, 0.01, 5)]
+    e, y, v = mq.mlmc_estimate([torch.tensor(q, dtype=torch.float64, device="cuda") for q in qf],
+                               [None] + [torch.tensor(q, dtype=torch.float64, device="cuda") for q in qc[1:]])
+    er, yr, vr = omlmc.estimate(qf, qc)
+    assert float(e) == pytest.approx(er, rel=1e-14)
+    assert np.allclose(y.cpu().numpy(), yr, rtol=1e-13)
+    assert np.allclose(v.cpu().numpy(), vr, rtol=1e-12)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_parareal_matches_oracle(path):
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 23, 0, range(3), 8)
+    p = mq.Problem(prob, L.MQ_PREC_FP64, path=path)
+    say(f"parareal path={path}")
+    # fixed K = M: the serial fine solution
+    q, it, fs, rc, st = mq.parareal_run(p, 1, 6, 4, 1, 6, 0.0, xi, fixed_k=6, want_state=True)
+    for s in range(3):
+        ref = opara.serial_fine(prob, xi[s], 1, 6, 4)
+        assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-10)
+        a = fs[s].cpu().numpy()
+        assert np.linalg.norm(a - ref["state"]) <= 1e-10 * np.linalg.norm(ref["state"])
+    assert np.all(it.cpu().numpy() == 6)
+    # tolerance mode: K and Q as the oracle
+    q, it, fs, rc, st = mq.parareal_run(p, 1, 8, 8, 1, 8, 1e-5, xi)
+    for s in range(3):
+        ref = opara.run(prob, xi[s], 1, 8, 8, 1, k_max=8, tol=1e-5)
+        assert abs(int(it[s]) - ref["K"]) <= 1
+        if int(it[s]) == ref["K"]:
+            assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-9)
+    p.close()
+
+
+def test_nonfinite_xi_rejected():
+    mq, L = mqmod()
+    prob = W.Problem(9, W.Material(kind=W.MAT_KL))
+    p = mq.Problem(prob, L.MQ_PREC_MIXED)
+    xi = np.zeros((2, 8))
+    xi[1, 3] = np.nan
+    with pytest.raises(L.MQError) as e:
+        mq.mlmc_level_run(p, 8, 0, 1, xi)
+    assert e.value.code == L.MQ_ERR_NONFINITE
+    p.close()
+
+
+def test_single_dof_mesh():
+    mq, L = mqmod()
+    prob = W.Problem(3, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0, 1, 0, 1), strip=(0, 1))
+    xi = np.array([[0.1, -0.3]])
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    qf, _, fs, rc, _ = mq.mlmc_level_run(p, 16, 0, 1, xi, want_state=True)
+    qref, aref = oracle_q(prob, xi, 16, 1)
+    assert float(qf[0]) == pytest.approx(qref[0], rel=1e-12)
+    p.close()
