@@ -123,6 +123,8 @@ typedef struct mq_run_stats {
   int32_t grid, block;         /* launch shape of the time-stepping kernel */
   double kernel_ms;            /* device time of the time-stepping launches */
   double total_ms;             /* wall time of the call */
+  double lat_p50_ms, lat_p99_ms, lat_max_ms; /* per-sample completion time after the first
+                                                instance started (device clock, last launch) */
 } mq_run_stats;
 
 /* One MLMC level (Section II-B): every sample runs steps_per_period *

@@ -58,6 +58,7 @@ class RunStats(C.Structure):
         ("max_inner_per_step", C.c_int32), ("n_not_converged", C.c_int32), ("n_failed", C.c_int32),
         ("path", C.c_int32), ("grid", C.c_int32), ("block", C.c_int32),
         ("kernel_ms", C.c_double), ("total_ms", C.c_double),
+        ("lat_p50_ms", C.c_double), ("lat_p99_ms", C.c_double), ("lat_max_ms", C.c_double),
     ]
 
     def as_dict(self):

@@ -64,6 +64,7 @@ struct mq_problem {
   int num_cu = 0;
   int lds_limit = 0;
   int n_xi = 0;
+  double wall_khz = 100000.0;
   int resident_ok = 0;
   int lds_bytes = 0;
   int path = MQ_PATH_STREAMING;
@@ -167,8 +168,8 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   const int n = (int)insts.size();
   if (n == 0) return MQ_OK;
   DevPtr<int> dstat;
-  HIP_TRY(dev_alloc(dstat, (size_t)n * 4));
-  for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + 4 * i;
+  HIP_TRY(dev_alloc(dstat, (size_t)n * STAT_N));
+  for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + STAT_N * i;
   DevPtr<Inst> dinst;
   HIP_TRY(dev_alloc(dinst, n));
   HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
@@ -194,7 +195,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     return fail(MQ_ERR_DEVICE, std::string("time-stepping launch: ") + hipGetErrorString(le));
   }
   HIP_TRY(hipEventRecord(e1, p->stream));
-  std::vector<int> sh((size_t)n * 4);
+  std::vector<int> sh((size_t)n * STAT_N);
   HIP_TRY(hipMemcpyAsync(sh.data(), dstat.get(), sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   float ms = 0;
@@ -202,8 +203,38 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ro->kernel_ms += ms;
+  // per-instance device wall-clock stamps -> per-group completion latency
+  auto stamp = [&](int i, int w) {
+    const int* q = &sh[(size_t)STAT_N * i + 4 + 2 * w];
+    return (uint64_t)(uint32_t)q[0] | ((uint64_t)(uint32_t)q[1] << 32);
+  };
+  uint64_t t_first = ~0ull;
+  for (int i = 0; i < n; ++i) t_first = std::min(t_first, stamp(i, 0));
+  {
+    std::vector<std::pair<int, uint64_t>> done;
+    for (int i = 0; i < n; ++i) done.push_back({insts[i].group, stamp(i, 1)});
+    std::sort(done.begin(), done.end());
+    std::vector<double> lat;
+    for (size_t a = 0; a < done.size();) {
+      uint64_t e = 0;
+      size_t b = a;
+      for (; b < done.size() && done[b].first == done[a].first; ++b) e = std::max(e, done[b].second);
+      lat.push_back((double)(e - t_first) / p->wall_khz);
+      a = b;
+    }
+    if (st && !lat.empty()) {
+      std::sort(lat.begin(), lat.end());
+      auto pct = [&](double f) {
+        const size_t k = (size_t)std::min<double>(lat.size() - 1, std::ceil(f * lat.size()) - 1);
+        return lat[k];
+      };
+      st->lat_p50_ms = pct(0.50);
+      st->lat_p99_ms = pct(0.99);
+      st->lat_max_ms = lat.back();
+    }
+  }
   for (int i = 0; i < n; ++i) {
-    const int* s4 = &sh[4 * i];
+    const int* s4 = &sh[(size_t)STAT_N * i];
     if (st) {
       st->n_instances += 1;
       st->sample_steps += (int64_t)insts[i].n_steps * std::max(1, insts[i].n_chain);
@@ -241,7 +272,7 @@ struct LevelBufs {
 // Append the instances of one level (fine first) and allocate their inputs.
 int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* xi, double* qf,
                   double* qc, bool want_state, LevelBufs& lb, std::vector<Inst>& fine,
-                  std::vector<Inst>& coarse) {
+                  std::vector<Inst>& coarse, int group0) {
   if (!lv) return fail(MQ_ERR_INVALID_ARG, "null level description");
   if (n < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
   if (lv->steps_per_period < 1 || lv->n_periods < 1 || lv->coarse_steps_per_period < 0)
@@ -288,6 +319,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
     in.dt = dtf;
     in.n_steps = (int)nf;
     in.sample = s;
+    in.group = group0 + s;
     fine.push_back(in);
     if (nc > 0) {
       Inst ic = in;
@@ -333,6 +365,9 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, p->device) == hipSuccess && optin > p->lds_limit)
     p->lds_limit = optin;
   p->stream = (hipStream_t)stream;
+  int wk = 0;
+  if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && wk > 0)
+    p->wall_khz = wk;
   p->n_xi = n_xi_of(*d);
   p->resident_ok = resident_supported(p->hm.g, d->precision, p->lds_limit, &p->lds_bytes);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
@@ -396,7 +431,7 @@ int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, co
   if (st) std::memset(st, 0, sizeof(*st));
   LevelBufs lb;
   std::vector<Inst> fine, coarse;
-  int rc = prepare_level(p, lv, n_samples, xi, q_fine, q_coarse, final_state != nullptr, lb, fine, coarse);
+  int rc = prepare_level(p, lv, n_samples, xi, q_fine, q_coarse, final_state != nullptr, lb, fine, coarse, 0);
   if (rc) return rc;
   std::vector<Inst> all = fine;
   all.insert(all.end(), coarse.begin(), coarse.end());
@@ -424,9 +459,11 @@ int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv
   std::vector<LevelBufs> lbs(n_levels);
   std::vector<Inst> all;
   std::vector<std::pair<int64_t, Inst>> keyed;
+  int group0 = 0;
   for (int l = 0; l < n_levels; ++l) {
     std::vector<Inst> f, c;
-    int rc = prepare_level(p, &lv[l], n_samples[l], xi[l], q_fine[l], q_coarse[l], false, lbs[l], f, c);
+    int rc = prepare_level(p, &lv[l], n_samples[l], xi[l], q_fine[l], q_coarse[l], false, lbs[l], f, c, group0);
+    group0 += n_samples[l];
     if (rc) return rc;
     for (auto& i : f) keyed.push_back({i.n_steps, i});
     for (auto& i : c) keyed.push_back({i.n_steps, i});
@@ -511,6 +548,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
       in.n_steps = cs;
       in.k0 = (first - 1) * cs;
       in.n_chain = nseg;
+      in.group = (int)a;
       in.chain_u = darr.get() + a * nseg;
       in.chain_f = darr.get() + L + a * nseg;
       in.chain_c = darr.get() + 2 * L + a * nseg;
@@ -540,6 +578,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
         in.n_steps = fs;
         in.k0 = (nn - 1) * fs;
         in.sample = s;
+        in.group = s;
         insts.push_back(in);
       }
     rc = run_instances(p, insts, st, &ro, nullptr);

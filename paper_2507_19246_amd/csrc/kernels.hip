@@ -289,6 +289,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
     const Inst in = insts[id];
     const double* tab = in.tab;
     const double inv_dt = 1.0 / in.dt;
+    const unsigned long long t_begin = wall_clock64();
 
     // scaled couplings D^{-1/2} A D^{-1/2} over the table region, FP64 -> VT
     auto dscale = [&](int i, int j) -> double {
@@ -513,10 +514,15 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;
       if (in.stat) {
+        const unsigned long long t_end = wall_clock64();
         in.stat[0] = it_total;
         in.stat[1] = sw_total;
         in.stat[2] = it_max_step;
         in.stat[3] = flags;
+        in.stat[4] = (int)(t_begin & 0xffffffffull);
+        in.stat[5] = (int)(t_begin >> 32);
+        in.stat[6] = (int)(t_end & 0xffffffffull);
+        in.stat[7] = (int)(t_end >> 32);
       }
     }
     __syncthreads();
@@ -898,6 +904,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
     const Inst in = insts[id];
     const double* tab = in.tab;
     const double inv_dt = 1.0 / in.dt;
+    const unsigned long long t_begin = wall_clock64();
     auto dscale = [&](int i, int j) -> double {
       if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
         const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
@@ -1071,10 +1078,15 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;
       if (in.stat) {
+        const unsigned long long t_end = wall_clock64();
         in.stat[0] = it_total;
         in.stat[1] = sw_total;
         in.stat[2] = it_max_step;
         in.stat[3] = flags;
+        in.stat[4] = (int)(t_begin & 0xffffffffull);
+        in.stat[5] = (int)(t_begin >> 32);
+        in.stat[6] = (int)(t_end & 0xffffffffull);
+        in.stat[7] = (int)(t_end >> 32);
       }
     }
     __syncthreads();

@@ -53,7 +53,8 @@ struct Inst {
   double* a_out;         // full-grid final state or null
   double* q_out;         // receives q_scale * sum_k d_k^T M d_k / dt
   double q_scale;
-  int* stat;             // [4]: inner iterations, sweeps, max inner per step, flags
+  int* stat;             // [STAT_N]: inner iterations, sweeps, max inner per step, flags,
+                         // device wall-clock start (lo, hi) and end (lo, hi)
   double dt;
   int n_steps;           // steps per chain segment
   int k0;                // global index of the first step
@@ -64,6 +65,7 @@ struct Inst {
   const double* const* chain_f; // F_n fine end states
   double* const* chain_c;       // C_old_n coarse values (in/out)
   int sample;                   // sample index (nonlinear coefficients)
+  int group;                    // latency group (host bookkeeping: one per sample)
 };
 
 struct Solver {
@@ -77,6 +79,7 @@ struct Solver {
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
+enum { STAT_N = 8 };
 
 // Launch helpers implemented in the .hip translation units.
 int resident_supported(const Geom& g, int precision, int lds_limit, int* lds_bytes);
