@@ -33,6 +33,32 @@ CG_FLOPS_PER_DOF_ITER = 26          # 7-point scaled stencil (14) + CG vector up
 CG_BYTES_PER_DOF_ITER_FP32 = 72     # modelled streaming traffic of one FP32 CG iteration
 
 
+def _kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    h.update(open(os.path.join(ROOT, "paper_2507_19246_amd", "csrc", "kernels.hip"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("traffic_"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("traffic_source_sha256") != _kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _oracle_task(args):
     """One oracle solve (runs in a worker process with one BLAS thread)."""
     problem, xi, spp, nper = args
@@ -146,13 +172,7 @@ def main():
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     units = nd * (sum(s["inner_iters"] for s in stats) / len(stats))   # DoF-iterations per launch
     achieved_tflops = CG_FLOPS_PER_DOF_ITER * units / avg_kern_s / 1e12
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_ie_resident_mlmc3_129.json")
-    if os.path.exists(tpath):
-        try:
-            traffic = json.load(open(tpath)).get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic("ie_resident_mlmc3_129_hbm_counters.md")
 
     # QoI error of the mixed path against FP64 references
     q_mixed = [q.cpu().numpy() for q in qfs]
