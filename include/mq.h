@@ -62,6 +62,10 @@ enum { MQ_PREC_FP64 = 0, MQ_PREC_MIXED = 1 };
 enum { MQ_APPLY_A = 0, MQ_APPLY_M = 1, MQ_APPLY_K = 2 };
 /* kernel path selection (mq_problem_desc.path) */
 enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2 };
+/* inner preconditioner (mq_problem_desc.precond): Jacobi is a symmetric
+ * diagonal scaling; MULTIGRID is a geometric V(1,1)-cycle with damped-Jacobi
+ * smoothing and Galerkin coarse operators (resident path, n_nodes = 2^k + 1) */
+enum { MQ_PRECOND_AUTO = 0, MQ_PRECOND_JACOBI = 1, MQ_PRECOND_MULTIGRID = 2 };
 
 /* Problem description (Section II-A; materials per the workload).
  * Unit square, n_nodes x n_nodes nodes, each cell split along "/" into two P1
@@ -76,7 +80,7 @@ enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2 };
  *  NONLINEAR: sigma = sigma0, nu(|B|) = k1' exp(k2' |B|^2) + k3',
  *       k_i' = k_i exp(s_k xi_i), solved per step by Picard iteration
  *       (||a^(i+1) - a^(i)|| <= picard_tol ||a^(i+1)||, at most picard_max).
- * Linear solves: Jacobi-preconditioned CG inside iterative refinement; a step
+ * Linear solves: preconditioned CG inside iterative refinement; a step
  * is converged when ||b - (M/dt + K) d||_2 <= tol ||b||_2 in FP64.  The inner
  * CG runs in FP64 (MQ_PREC_FP64) or FP32 (MQ_PREC_MIXED) to inner_rtol
  * relative to its own initial residual, at most max_iter iterations per
@@ -96,6 +100,9 @@ typedef struct mq_problem_desc {
   double k1, k2, k3, s_k, picard_tol;
   double tol, inner_rtol;
   int32_t max_iter, max_sweeps;
+  int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available, else Jacobi */
+  int32_t reserved0;
+  double mg_omega;   /* damped-Jacobi weight of the multigrid smoother (0: 0.8) */
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;
@@ -105,6 +112,8 @@ typedef struct mq_problem_info {
   int32_t box[4];        /* interior-node box [x0, x1) x [y0, y1) of sample-dependent rows */
   int32_t resident_ok;   /* 1 if the register/LDS-resident path fits this mesh/precision */
   int32_t lds_bytes;     /* LDS per workgroup of the resident path */
+  int32_t precond;       /* preconditioner in use (MQ_PRECOND_JACOBI or _MULTIGRID) */
+  int32_t mg_levels;     /* coarse levels of the multigrid hierarchy (0 if unused) */
   int32_t n_modes_used;
   double kl_lambda[16];  /* 2-D KL eigenvalues in use (KL material) */
 } mq_problem_info;

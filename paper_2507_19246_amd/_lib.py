@@ -25,6 +25,7 @@ MQ_MAT_LOGNORMAL_SCALAR, MQ_MAT_KL, MQ_MAT_NONLINEAR = 0, 1, 2
 MQ_PREC_FP64, MQ_PREC_MIXED = 0, 1
 MQ_APPLY_A, MQ_APPLY_M, MQ_APPLY_K = 0, 1, 2
 MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING = 0, 1, 2
+MQ_PRECOND_AUTO, MQ_PRECOND_JACOBI, MQ_PRECOND_MULTIGRID = 0, 1, 2
 
 
 class ProblemDesc(C.Structure):
@@ -40,6 +41,7 @@ class ProblemDesc(C.Structure):
         ("picard_tol", C.c_double),
         ("tol", C.c_double), ("inner_rtol", C.c_double),
         ("max_iter", C.c_int32), ("max_sweeps", C.c_int32),
+        ("precond", C.c_int32), ("reserved0", C.c_int32), ("mg_omega", C.c_double),
     ]
 
 
@@ -47,6 +49,7 @@ class ProblemInfo(C.Structure):
     _fields_ = [
         ("n_nodes", C.c_int32), ("n_dof", C.c_int32), ("pitch", C.c_int32), ("n_xi", C.c_int32),
         ("box", C.c_int32 * 4), ("resident_ok", C.c_int32), ("lds_bytes", C.c_int32),
+        ("precond", C.c_int32), ("mg_levels", C.c_int32),
         ("n_modes_used", C.c_int32), ("kl_lambda", C.c_double * 16),
     ]
 

@@ -68,6 +68,8 @@ struct mq_problem {
   int resident_ok = 0;
   int lds_bytes = 0;
   int path = MQ_PATH_STREAMING;
+  int precond = MQ_PRECOND_JACOBI;
+  MGGeom mg{};
   double mat[10];
   DevPtr<double> dS;
   DevPtr<uint8_t> dcond;
@@ -107,11 +109,15 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->max_iter < 1 || d->max_sweeps < 1) return fail(MQ_ERR_INVALID_ARG, "max_iter and max_sweeps must be >= 1");
   if (d->material == MQ_MAT_NONLINEAR && (d->picard_max < 1 || !(d->picard_tol > 0)))
     return fail(MQ_ERR_INVALID_ARG, "bad Picard parameters");
+  if (d->precond < 0 || d->precond > 2) return fail(MQ_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!(d->mg_omega >= 0) || !(d->mg_omega < 1)) return fail(MQ_ERR_INVALID_ARG, "mg_omega must be in [0, 1)");
   return MQ_OK;
 }
 
 Solver solver_of(const mq_problem* p) {
   Solver sv;
+  sv.precond = p->precond == MQ_PRECOND_MULTIGRID ? 1 : 0;
+  sv.mg_omega = p->d.mg_omega > 0 ? p->d.mg_omega : 0.8;
   sv.precision = p->d.precision;
   sv.tol = p->d.tol;
   sv.inner_rtol = p->d.inner_rtol;
@@ -174,7 +180,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   HIP_TRY(dev_alloc(dinst, n));
   HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
   const Geom& g = p->hm.g;
-  const int per_cu = ie_slots_per_cu(g, p->path, p->d.precision);
+  const int per_cu = ie_slots_per_cu(g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision);
   const size_t slots = std::min<size_t>((size_t)n, (size_t)p->num_cu * per_cu);
   int rc = ensure_work(p, slots);
   if (rc) return rc;
@@ -186,7 +192,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   HIP_TRY(hipEventRecord(e0, p->stream));
   // the slot layout of the work buffer is fixed by its allocation (work_slots);
   // the grid is the occupancy-limited slot count
-  hipError_t le = launch_ie(g, sv, dinst.get(), n, p->dcounter.get(), p->work.get(), (int)p->work_slots, (int)slots,
+  hipError_t le = launch_ie(g, p->mg, sv, dinst.get(), n, p->dcounter.get(), p->work.get(), (int)p->work_slots, (int)slots,
                             p->dS.get(), p->path, p->d.precision, p->hm.cr, p->dcond.get(), p->mat,
                             &ro->grid, &ro->block, p->stream);
   if (le != hipSuccess) {
@@ -369,7 +375,16 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && wk > 0)
     p->wall_khz = wk;
   p->n_xi = n_xi_of(*d);
-  p->resident_ok = resident_supported(p->hm.g, d->precision, p->lds_limit, &p->lds_bytes);
+  // multigrid hierarchy (resident path only); fall back to Jacobi if it does not fit
+  const int lp = p->hm.g.n <= 31 ? 34 : (p->hm.g.n <= 63 ? 66 : 130);
+  const bool want_mg = d->precond != MQ_PRECOND_JACOBI && d->path != MQ_PATH_STREAMING;
+  bool have_mg = want_mg && build_mg(p->hm.g, lp, &p->mg);
+  if (have_mg && !resident_supported(p->hm.g, &p->mg, d->precision, p->lds_limit, nullptr)) have_mg = false;
+  if (d->precond == MQ_PRECOND_MULTIGRID && !have_mg)
+    return fail(MQ_ERR_INVALID_ARG, "multigrid needs the resident path and n_nodes = 2^k + 1");
+  if (!have_mg) p->mg.nlev = 0;
+  p->precond = have_mg ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
+  p->resident_ok = resident_supported(p->hm.g, have_mg ? &p->mg : nullptr, d->precision, p->lds_limit, &p->lds_bytes);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
     return fail(MQ_ERR_INVALID_ARG, "the resident path does not fit this mesh/precision");
   p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
@@ -419,6 +434,8 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   info->box[3] = g.by1;
   info->resident_ok = p->resident_ok;
   info->lds_bytes = p->lds_bytes;
+  info->precond = p->path == MQ_PATH_RESIDENT ? p->precond : MQ_PRECOND_JACOBI;
+  info->mg_levels = p->path == MQ_PATH_RESIDENT ? p->mg.nlev : 0;
   info->n_modes_used = p->hm.n_modes;
   for (int k = 0; k < p->hm.n_modes && k < 16; ++k) info->kl_lambda[k] = p->hm.kl_lambda[k];
   return MQ_OK;

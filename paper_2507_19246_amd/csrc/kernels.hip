@@ -14,6 +14,7 @@
 //                  Eq. (9), Parareal interface jumps (Eq. (12) stopping test).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -226,11 +227,115 @@ __device__ inline void block_sum(double (&v)[NV], double* red, int& slot) {
 template <typename VT>
 __device__ inline VT vt(double x) { return (VT)x; }
 
+// ---------------------------------------------------------------------------
+// multigrid helpers (resident path)
+// ---------------------------------------------------------------------------
+// Coarse-level view: Galerkin tables over the box +- 1 ring and the level's
+// vectors (n x n, row-major, no halo: out-of-range neighbours read as zero,
+// i.e. the Dirichlet boundary).
+template <typename VT>
+struct CView {
+  int n, bx0, bx1, by0, by1, lx1, ly1, RW;
+  const VT *C, *E, *N, *NE;
+  VT *r, *z, *t;
+  __device__ bool inL(int i, int j) const { return i >= bx0 && i < lx1 && j >= by0 && j < ly1; }
+  __device__ int tix(int i, int j) const { return (j - by0 + 1) * RW + (i - bx0 + 1); }
+};
+
+template <typename VT>
+__device__ inline VT cget(const VT* v, int n, int i, int j) {
+  return (i >= 0 && i < n && j >= 0 && j < n) ? v[j * n + i] : VT(0);
+}
+
+// (A v)_{ij} and the diagonal at a coarse node
+template <typename VT>
+__device__ inline VT capply(const CView<VT>& L, const VT* v, int i, int j, VT* diag) {
+  const int n = L.n;
+  const VT c = v[j * n + i], e = cget(v, n, i + 1, j), w = cget(v, n, i - 1, j);
+  const VT nn = cget(v, n, i, j + 1), s = cget(v, n, i, j - 1);
+  if (L.inL(i, j)) {
+    const int t = L.tix(i, j);
+    const VT ne = cget(v, n, i + 1, j + 1), sw = cget(v, n, i - 1, j - 1);
+    *diag = L.C[t];
+    return L.C[t] * c + L.E[t] * e + L.E[t - 1] * w + L.N[t] * nn + L.N[t - L.RW] * s + L.NE[t] * ne +
+           L.NE[t - L.RW - 1] * sw;
+  }
+  *diag = VT(1);
+  return c - VT(0.25) * ((e + w) + (nn + s));
+}
+
+template <typename VT>
+__device__ inline VT cdiag(const CView<VT>& L, int i, int j) {
+  return L.inL(i, j) ? L.C[L.tix(i, j)] : VT(1);
+}
+
+// Restriction r_c = P^T t (coarse c <-> fine 2c+1; weights 1 and 1/2 on the
+// six "/"-mesh neighbours), fine vector given by an accessor.
+template <typename VT, class FT>
+__device__ inline VT restrict_at(FT tf, int ic, int jc) {
+  const int i = 2 * ic + 1, j = 2 * jc + 1;
+  return tf(i, j) + VT(0.5) * ((tf(i + 1, j) + tf(i - 1, j)) + (tf(i, j + 1) + tf(i, j - 1)) +
+                               (tf(i + 1, j + 1) + tf(i - 1, j - 1)));
+}
+
+// Prolongation (P z_c)_{ij}: P1 interpolation on the coarse "/" triangulation.
+template <typename VT>
+__device__ inline VT prolong_at(const VT* zc, int nc, int i, int j) {
+  const bool io = i & 1, jo = j & 1;
+  if (io && jo) return cget(zc, nc, (i - 1) >> 1, (j - 1) >> 1);
+  if (!io && jo) return VT(0.5) * (cget(zc, nc, (i >> 1) - 1, (j - 1) >> 1) + cget(zc, nc, i >> 1, (j - 1) >> 1));
+  if (io && !jo) return VT(0.5) * (cget(zc, nc, (i - 1) >> 1, (j >> 1) - 1) + cget(zc, nc, (i - 1) >> 1, j >> 1));
+  return VT(0.5) * (cget(zc, nc, (i >> 1) - 1, (j >> 1) - 1) + cget(zc, nc, i >> 1, j >> 1));
+}
+
+// Synchronisation of the threads working on one level: the whole workgroup
+// (level 1) or wave 0 alone (coarser levels): LDS traffic of one wave is
+// ordered once its outstanding LDS operations have completed.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Galerkin coarse entries A_c(c, c + D) = (P e_c)^T A_f (P e_{c+D}) for
+// D in {0, E, N, NE}; `cf(i, j, d)` returns the fine coupling of node (i, j)
+// in direction d (0 C, 1 E, 2 W, 3 N, 4 S, 5 NE, 6 SW).
+template <class CF>
+__device__ inline void galerkin_entries(CF cf, int nf, int nc, int ic, int jc, double out[4]) {
+  const int OX[7] = {0, 1, -1, 0, 0, 1, -1};
+  const int OY[7] = {0, 0, 0, 1, -1, 1, -1};
+  const double PW[7] = {1.0, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
+  const int DX[4] = {0, 1, 0, 1}, DY[4] = {0, 0, 1, 1};
+  for (int q = 0; q < 4; ++q) {
+    const int cx = ic + DX[q], cy = jc + DY[q];
+    double s = 0.0;
+    if (cx < nc && cy < nc) {
+      for (int a = 0; a < 7; ++a) {
+        const int fi = 2 * ic + 1 + OX[a], fj = 2 * jc + 1 + OY[a];
+        if (fi < 0 || fj < 0 || fi >= nf || fj >= nf) continue;
+        for (int d = 0; d < 7; ++d) {
+          const int gi = fi + OX[d], gj = fj + OY[d];
+          if (gi < 0 || gj < 0 || gi >= nf || gj >= nf) continue;
+          const int ox = gi - (2 * cx + 1), oy = gj - (2 * cy + 1);
+          double w2 = 0.0;
+          if (ox == 0 && oy == 0) w2 = 1.0;
+          else if ((ox == 1 && oy == 0) || (ox == -1 && oy == 0) || (ox == 0 && oy == 1) ||
+                   (ox == 0 && oy == -1) || (ox == 1 && oy == 1) || (ox == -1 && oy == -1))
+            w2 = 0.5;
+          if (w2 != 0.0) s += PW[a] * cf(fi, fj, d) * w2;
+        }
+      }
+    }
+    out[q] = s;
+  }
+}
+
+
 // LDS pitches are compile-time constants (LP = CW + 2 for the grid, TP for
 // the tables) so that every per-node LDS offset folds into the instruction's
 // immediate offset instead of occupying a register.
-template <typename VT, int CW, int SH, int NS, int TP>
-__global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
+template <typename VT, int CW, int SH, int NS, int TP, bool MG>
+__global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solver sv,
                                                         const Inst* __restrict__ insts, int n_inst,
                                                         int* counter, double* work,
                                                         const double* __restrict__ S) {
@@ -241,10 +346,12 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
   const int n = g.n, RHW = g.RW * g.RH, TRH = g.RH * TP;
   double* red = smem_d;                                  // 2 * NWAVES * 4 doubles
   VT* rl = reinterpret_cast<VT*>(red + 2 * NWAVES * 4);  // (n+2) x LP grid with zero halo
-  VT* tE = rl + (n + 2) * LP;                            // scaled tables, RH x TP each
+  const int region = MG ? mg.region_elems : (n + 2) * LP; // multigrid: shared with coarse vectors
+  VT* tE = rl + region;                                  // scaled tables, RH x TP each
   VT* tN = tE + TRH;
   VT* tNE = tN + TRH;
   VT* tD = tNE + TRH;
+  VT* ctab = tD + TRH;                                   // coarse Galerkin tables (multigrid)
   __shared__ int s_inst;
 
   const int tid = threadIdx.x;
@@ -253,9 +360,10 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
   const bool colok = ci < n;
   const bool strip_ok = colok && j0 < n;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 3 * FS;
+  double* Av = work + (size_t)blockIdx.x * 4 * FS;
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
+  VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate (full grid)
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   int slot = 0;
 
@@ -325,6 +433,50 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
       }
     }
     __syncthreads();
+    if constexpr (MG) {
+      // Galerkin coarse operators A_l = P^T A_{l-1} P of the scaled system
+      for (int l = 1; l <= mg.nlev; ++l) {
+        const MGLevel& M = mg.lv[l];
+        const MGLevel& F = mg.lv[l - 1];
+        const int pl = M.RW * M.RH;
+        VT* C = ctab + M.tab_off;
+        VT* E = C + pl;
+        VT* Nn = E + pl;
+        VT* NE = Nn + pl;
+        const int fp = l == 1 ? TP : F.RW;
+        const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
+        const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
+        const VT* fN = l == 1 ? tN : fE + F.RW * F.RH;
+        const VT* fNE = l == 1 ? tNE : fN + F.RW * F.RH;
+        auto cf = [&](int fi, int fj, int d) -> double {
+          if (!(fi >= F.bx0 && fi < F.lx1 && fj >= F.by0 && fj < F.ly1)) {
+            if (d == 0) return 1.0;
+            return d <= 4 ? -0.25 : 0.0;
+          }
+          const int t = (fj - F.by0 + 1) * fp + (fi - F.bx0 + 1);
+          switch (d) {
+            case 0: return fC ? (double)fC[t] : 1.0;
+            case 1: return (double)fE[t];
+            case 2: return (double)fE[t - 1];
+            case 3: return (double)fN[t];
+            case 4: return (double)fN[t - fp];
+            case 5: return (double)fNE[t];
+            default: return (double)fNE[t - fp - 1];
+          }
+        };
+        for (int t = tid; t < pl; t += NT) {
+          const int i = M.bx0 - 1 + t % M.RW, j = M.by0 - 1 + t / M.RW;
+          const bool box = i >= M.bx0 && i < M.bx1 && j >= M.by0 && j < M.by1;
+          double o[4] = {1.0, -0.25, -0.25, 0.0};
+          if (box) galerkin_entries(cf, F.n, M.n, i, j, o);
+          C[t] = vt<VT>(o[0]);
+          E[t] = vt<VT>(o[1]);
+          Nn[t] = vt<VT>(o[2]);
+          NE[t] = vt<VT>(o[3]);
+        }
+        __syncthreads();
+      }
+    }
     auto DN = [&](int k) -> double { return INBOX(k) ? (double)tD[s0 + k * TP] : (double)vt<VT>(d_air); };
 
     double qsum = 0.0;
@@ -378,6 +530,287 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
             }
             if (sweep == sv.max_sweeps) break;
             sw_total++;
+            if constexpr (MG) {
+              // ---- CG preconditioned by a geometric multigrid V(1,1)-cycle ----
+              // (standard PCG ordering; registers y, r, p and one of q / t / z)
+              const VT om = vt<VT>(sv.mg_omega);
+              auto publish = [&](const VT(&v)[SH]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int k = 0; k < SH; ++k)
+                  if (ACT(k)) rl[l0 + k * LP] = v[k];
+              };
+              // w = A v on the fine level (v published in the LDS grid)
+              auto fine_apply = [&](const VT(&v)[SH], VT(&w)[SH]) __attribute__((always_inline)) {
+                if (!strip_ok) {
+#pragma unroll
+                  for (int k = 0; k < SH; ++k) w[k] = VT(0);
+                  return;
+                }
+                VT lprev = rl[l0 - LP - 1];
+                VT rcur = rl[l0 + 1];
+                const VT below = rl[l0 - LP];
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  const int j = j0 + k;
+                  if (j < n) {
+                    const VT lcur = rl[l0 + k * LP - 1];
+                    const VT rnxt = rl[l0 + (k + 1) * LP + 1];
+                    const VT up = (k + 1 < SH) ? v[(k + 1 < SH) ? k + 1 : k] : rl[l0 + (k + 1) * LP];
+                    const VT dnv = (k > 0) ? v[(k > 0) ? k - 1 : 0] : below;
+                    if (col_L && j >= g.by0 && j < g.ly1) {
+                      const int t = s0 + k * TP;
+                      w[k] = v[k] + tE[t] * rcur + tE[t - 1] * lcur + tN[t] * up + tN[t - TP] * dnv +
+                             tNE[t] * rnxt + tNE[t - TP - 1] * lprev;
+                    } else {
+                      w[k] = v[k] - VT(0.25) * ((rcur + lcur) + (up + dnv));
+                    }
+                    lprev = lcur;
+                    rcur = rnxt;
+                  } else {
+                    w[k] = VT(0);
+                  }
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+              };
+              // post-smoothing z <- z + om (r - A z) in place (old z kept for the stencil)
+              auto fine_smooth = [&](VT(&v)[SH], const VT(&rr_)[SH]) __attribute__((always_inline)) {
+                if (!strip_ok) return;
+                VT lprev = rl[l0 - LP - 1];
+                VT rcur = rl[l0 + 1];
+                VT dnv = rl[l0 - LP];
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  const int j = j0 + k;
+                  if (j < n) {
+                    const VT lcur = rl[l0 + k * LP - 1];
+                    const VT rnxt = rl[l0 + (k + 1) * LP + 1];
+                    const VT up = (k + 1 < SH) ? v[(k + 1 < SH) ? k + 1 : k] : rl[l0 + (k + 1) * LP];
+                    const VT c = v[k];
+                    VT w;
+                    if (col_L && j >= g.by0 && j < g.ly1) {
+                      const int t = s0 + k * TP;
+                      w = c + tE[t] * rcur + tE[t - 1] * lcur + tN[t] * up + tN[t - TP] * dnv +
+                          tNE[t] * rnxt + tNE[t - TP - 1] * lprev;
+                    } else {
+                      w = c - VT(0.25) * ((rcur + lcur) + (up + dnv));
+                    }
+                    v[k] = c + om * (rr_[k] - w);
+                    dnv = c;
+                    lprev = lcur;
+                    rcur = rnxt;
+                  }
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+              };
+              // coarse levels 1..nlev (level 1 by the whole workgroup, the
+              // coarser ones by wave 0); returns level 1's output vector
+              auto cview = [&](int l) __attribute__((always_inline)) {
+                const MGLevel& M = mg.lv[l];
+                CView<VT> v;
+                v.n = M.n;
+                v.bx0 = M.bx0;
+                v.bx1 = M.bx1;
+                v.by0 = M.by0;
+                v.by1 = M.by1;
+                v.lx1 = M.lx1;
+                v.ly1 = M.ly1;
+                v.RW = M.RW;
+                const int pl = M.RW * M.RH;
+                v.C = ctab + M.tab_off;
+                v.E = v.C + pl;
+                v.N = v.E + pl;
+                v.NE = v.N + pl;
+                v.r = rl + M.vec_off;
+                v.z = v.r + M.n * M.n;
+                v.t = v.z + M.n * M.n;
+                return v;
+              };
+              auto level_out = [&](const CView<VT>& L) __attribute__((always_inline)) -> VT* { return L.n == 1 ? L.z : L.t; };
+              // one descent+ascent step of level l, threads me, me+st, ...
+              auto level_down = [&](const CView<VT>& L, const CView<VT>* Lc, int me, int st, bool wave) __attribute__((always_inline)) {
+                const int nn = L.n * L.n;
+                if (L.n == 1) {
+                  if (me == 0) L.z[0] = L.r[0] / cdiag(L, 0, 0);
+                  if (wave) wave_sync(); else __syncthreads();
+                  return;
+                }
+                for (int idx = me; idx < nn; idx += st) {
+                  const int i = idx % L.n, j = idx / L.n;
+                  L.z[idx] = om * L.r[idx] / cdiag(L, i, j);
+                }
+                if (wave) wave_sync(); else __syncthreads();
+                for (int idx = me; idx < nn; idx += st) {
+                  const int i = idx % L.n, j = idx / L.n;
+                  VT d;
+                  L.t[idx] = L.r[idx] - capply(L, L.z, i, j, &d);
+                }
+                if (wave) wave_sync(); else __syncthreads();
+                const int nc = Lc->n;
+                auto tf = [&](int i, int j) __attribute__((always_inline)) { return L.t[j * L.n + i]; };
+                for (int idx = me; idx < nc * nc; idx += st)
+                  Lc->r[idx] = restrict_at<VT>(tf, idx % nc, idx / nc);
+                if (wave) wave_sync(); else __syncthreads();
+              };
+              auto level_up = [&](const CView<VT>& L, const CView<VT>* Lc, int me, int st, bool wave) __attribute__((always_inline)) {
+                if (L.n == 1) return;
+                const int nn = L.n * L.n;
+                const VT* zc = level_out(*Lc);
+                for (int idx = me; idx < nn; idx += st) {
+                  const int i = idx % L.n, j = idx / L.n;
+                  L.z[idx] += prolong_at<VT>(zc, Lc->n, i, j);
+                }
+                if (wave) wave_sync(); else __syncthreads();
+                for (int idx = me; idx < nn; idx += st) {
+                  const int i = idx % L.n, j = idx / L.n;
+                  VT d;
+                  const VT az = capply(L, L.z, i, j, &d);
+                  L.t[idx] = L.z[idx] + om * (L.r[idx] - az) / d;
+                }
+                if (wave) wave_sync(); else __syncthreads();
+              };
+              auto coarse_cycle = [&]() __attribute__((always_inline)) -> VT* {
+                const CView<VT> L1 = cview(1);
+                if (L1.n == 1 || mg.nlev == 1) {
+                  level_down(L1, nullptr, tid, NT, false);
+                  return L1.z;
+                }
+                const CView<VT> L2 = cview(2);
+                level_down(L1, &L2, tid, NT, false);
+                if (tid < 64) {
+                  // levels >= 2 on wave 0
+                  for (int l = 2; l <= mg.nlev; ++l) {
+                    const CView<VT> Ll = cview(l);
+                    if (l < mg.nlev) {
+                      const CView<VT> Lc = cview(l + 1);
+                      level_down(Ll, &Lc, tid, 64, true);
+                    } else {
+                      level_down(Ll, nullptr, tid, 64, true);
+                    }
+                  }
+                  for (int l = mg.nlev - 1; l >= 2; --l) {
+                    const CView<VT> Ll = cview(l);
+                    const CView<VT> Lc = cview(l + 1);
+                    level_up(Ll, &Lc, tid, 64, true);
+                  }
+                }
+                __syncthreads();
+                level_up(L1, &L2, tid, NT, false);
+                return L1.t;
+              };
+              // z = B r (symmetric V(1,1) cycle)
+              auto vcycle = [&](const VT(&rv)[SH], VT(&zv)[SH]) __attribute__((always_inline)) {
+                publish(rv);
+                __syncthreads();
+                fine_apply(rv, zv);  // zv used as scratch: A r
+#pragma unroll
+                for (int k = 0; k < SH; ++k) zv[k] = rv[k] - om * zv[k];  // t = r - A (om r)
+                __syncthreads();
+                publish(zv);
+                __syncthreads();
+                // restriction to level 1 into registers, then into the shared region
+                const CView<VT> L1 = cview(1);
+                const int n1 = L1.n;
+                VT rc[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                  const int idx = tid + NT * m;
+                  rc[m] = VT(0);
+                  if (idx < n1 * n1) {
+                    auto tf = [&](int i, int j) __attribute__((always_inline)) { return rl[(j + 1) * LP + i + 1]; };
+                    rc[m] = restrict_at<VT>(tf, idx % n1, idx / n1);
+                  }
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                  const int idx = tid + NT * m;
+                  if (idx < n1 * n1) L1.r[idx] = rc[m];
+                }
+                __syncthreads();
+                const VT* z1 = coarse_cycle();
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  zv[k] = ACT(k) ? om * rv[k] + prolong_at<VT>(z1, n1, ci, j0 + k) : VT(0);
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                publish(zv);
+                // restore the zero halo of the fine grid (the region held coarse data)
+                for (int q = tid; q < 2 * LP + 2 * n; q += NT) {
+                  int idx;
+                  if (q < LP) idx = q;
+                  else if (q < 2 * LP) idx = (n + 1) * LP + (q - LP);
+                  else if (q < 2 * LP + n) idx = (q - 2 * LP + 1) * LP;
+                  else idx = (q - 2 * LP - n + 1) * LP + n + 1;
+                  rl[idx] = VT(0);
+                }
+                __syncthreads();
+                fine_smooth(zv, rv);
+              };
+
+              // the iterate y is accumulated in the slot's global VT buffer
+              // (owner-thread access only) to keep three vectors in registers
+              VT r[SH], p[SH], z[SH];
+#pragma unroll
+              for (int k = 0; k < SH; ++k) {
+                r[k] = ACT(k) ? rl[l0 + k * LP] : VT(0);
+                p[k] = VT(0);
+                if (ACT(k)) Yv[gi0 + k * g.P] = VT(0);
+              }
+              double rho = 1.0, stop = 0.0;
+              int it = 0;
+              for (;;) {
+                vcycle(r, z);
+                double rz[2];
+                {
+                  VT a = VT(0), b = VT(0);
+#pragma unroll
+                  for (int k = 0; k < SH; ++k) {
+                    a += r[k] * z[k];
+                    b += r[k] * r[k];
+                  }
+                  rz[0] = (double)a;
+                  rz[1] = (double)b;
+                }
+                block_sum<2, NWAVES>(rz, red, slot);
+                double beta = 0.0;
+                if (it == 0) {
+                  stop = sv.inner_rtol * sv.inner_rtol * rz[1];
+                  if (!(rz[1] > 0.0) || !(rz[0] > 0.0)) break;
+                } else {
+                  if (rz[1] <= stop || !(rz[1] == rz[1])) break;
+                  beta = rz[0] / rho;
+                }
+                rho = rz[0];
+                const VT b_ = vt<VT>(beta);
+#pragma unroll
+                for (int k = 0; k < SH; ++k) p[k] = z[k] + b_ * p[k];
+                if (it == sv.max_iter) break;
+                ++it;
+                publish(p);
+                __syncthreads();
+                fine_apply(p, z);  // z holds q = A p here
+                double pq[1];
+                {
+                  VT a = VT(0);
+#pragma unroll
+                  for (int k = 0; k < SH; ++k) a += p[k] * z[k];
+                  pq[0] = (double)a;
+                }
+                block_sum<1, NWAVES>(pq, red, slot);
+                const VT a_ = vt<VT>(rho / pq[0]);
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                  if (ACT(k)) Yv[gi0 + k * g.P] += a_ * p[k];
+                  r[k] = r[k] - a_ * z[k];
+                }
+              }
+              it_step += it;
+#pragma unroll
+              for (int k = 0; k < SH; ++k)
+                if (ACT(k)) rl[l0 + k * LP] = Yv[gi0 + k * g.P];
+            } else {
             // ---- inner CG on the scaled system, y0 = 0, r0 = g ----
             // Chronopoulos-Gear ordering: the reduction of r.r shares its
             // barrier with the LDS publication of r, the stencil result w is
@@ -464,6 +897,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, Solver sv,
 #pragma unroll
             for (int k = 0; k < SH; ++k)
               if (ACT(k)) rl[l0 + k * LP] = y[k];
+            }
 #pragma unroll 1
             for (int k = 0; k < SH; ++k)
               if (ACT(k)) Xv[gi0 + k * g.P] += DN(k) * (double)rl[l0 + k * LP];
@@ -533,11 +967,75 @@ struct ResCfg {
   int cw, sh, ns, tp;
 };
 
+bool build_mg(const Geom& g, int lp, MGGeom* mg) {
+  mg->nlev = 0;
+  mg->region_elems = 0;
+  mg->ctab_elems = 0;
+  const int n = g.n;
+  if (n < 3 || ((n + 1) & n) != 0) return false;  // n = 2^k - 1
+  MGLevel& f = mg->lv[0];
+  f.n = n;
+  f.bx0 = g.bx0;
+  f.bx1 = g.bx1;
+  f.by0 = g.by0;
+  f.by1 = g.by1;
+  f.lx1 = g.lx1;
+  f.ly1 = g.ly1;
+  f.RW = g.RW;
+  f.RH = g.RH;
+  f.tab_off = 0;
+  f.vec_off = 0;
+  int l = 0, vec = 0, tab = 0;
+  while (mg->lv[l].n > 1) {
+    if (l + 1 >= MG_MAX_LEVELS) return false;
+    const MGLevel& F = mg->lv[l];
+    const int nc = (F.n - 1) / 2;
+    MGLevel c{};
+    c.n = nc;
+    // coarse node ic owns non-air entries iff the fine rows 2ic..2ic+2 meet
+    // the fine lookup region [bx0, lx1)
+    auto range = [&](int f0, int f1, int* c0, int* c1) {
+      *c0 = nc;
+      *c1 = 0;
+      if (f1 <= f0) {
+        *c0 = *c1 = 0;
+        return;
+      }
+      for (int ic = 0; ic < nc; ++ic)
+        if (2 * ic + 2 >= f0 && 2 * ic <= f1 - 1) {
+          if (ic < *c0) *c0 = ic;
+          *c1 = ic + 1;
+        }
+      if (*c1 <= *c0) *c0 = *c1 = 0;
+    };
+    range(F.bx0, F.lx1, &c.bx0, &c.bx1);
+    range(F.by0, F.ly1, &c.by0, &c.by1);
+    if (c.bx1 == c.bx0 || c.by1 == c.by0) c.bx0 = c.bx1 = c.by0 = c.by1 = 0;
+    c.lx1 = c.bx1 > c.bx0 ? std::min(nc, c.bx1 + 1) : c.bx0;
+    c.ly1 = c.by1 > c.by0 ? std::min(nc, c.by1 + 1) : c.by0;
+    c.RW = (c.bx1 - c.bx0) + 2;
+    c.RH = (c.by1 - c.by0) + 2;
+    c.tab_off = tab;
+    tab += 4 * c.RW * c.RH;
+    c.vec_off = vec;
+    vec += 3 * nc * nc;
+    mg->lv[++l] = c;
+  }
+  mg->nlev = l;
+  mg->region_elems = std::max((n + 2) * lp, vec);
+  mg->ctab_elems = tab;
+  return true;
+}
+
 template <typename VT>
-static size_t resident_lds(const Geom& g, const ResCfg& c) {
+static size_t resident_lds(const Geom& g, const ResCfg& c, const MGGeom* mg) {
   const int nw = c.cw * c.ns / 64;
-  return 2 * nw * 4 * sizeof(double) +
-         (size_t)((g.n + 2) * (c.cw + 2) + 4 * g.RH * c.tp) * sizeof(VT);
+  size_t region = (size_t)(g.n + 2) * (c.cw + 2), ctab = 0;
+  if (mg && mg->nlev > 0) {
+    region = mg->region_elems;
+    ctab = mg->ctab_elems;
+  }
+  return 2 * nw * 4 * sizeof(double) + (region + 4 * (size_t)g.RH * c.tp + ctab) * sizeof(VT);
 }
 
 static bool pick_resident(const Geom& g, ResCfg* c) {
@@ -553,66 +1051,69 @@ static bool pick_resident(const Geom& g, ResCfg* c) {
   return g.n <= c->sh * c->ns && g.RW <= c->tp;
 }
 
-int resident_supported(const Geom& g, int precision, int lds_limit, int* lds_bytes) {
+int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes) {
   ResCfg c;
   if (!pick_resident(g, &c)) return 0;
   // 1024-thread FP64 workgroups would need more than 128 VGPRs per lane
   if (precision == MQ_PREC_FP64 && c.cw * c.ns > 256) return 0;
-  size_t b = precision == MQ_PREC_FP64 ? resident_lds<double>(g, c) : resident_lds<float>(g, c);
+  // the restriction to the first coarse level keeps 4 coarse nodes per thread
+  if (mg && mg->nlev > 0 && mg->lv[1].n * mg->lv[1].n > 4 * c.cw * c.ns) return 0;
+  size_t b = precision == MQ_PREC_FP64 ? resident_lds<double>(g, c, mg) : resident_lds<float>(g, c, mg);
   if (lds_bytes) *lds_bytes = (int)b;
   return b <= (size_t)lds_limit ? 1 : 0;
 }
 
-size_t ie_work_doubles(const Geom& g) { return 3 * (size_t)g.N * g.P; }
+size_t ie_work_doubles(const Geom& g) { return 4 * (size_t)g.N * g.P; }
 
-template <typename VT, int CW, int SH, int NS, int TP>
-static hipError_t launch_res(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
-                             int* counter, double* work, int max_grid, const double* S,
+template <typename VT, int CW, int SH, int NS, int TP, bool MG>
+static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
+                             int n_inst, int* counter, double* work, int max_grid, const double* S,
                              int* grid_out, int* block_out, hipStream_t st) {
   constexpr int NT = CW * NS;
-  const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP});
-  auto kern = k_ie_resident<VT, CW, SH, NS, TP>;
+  const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP}, MG ? &mg : nullptr);
+  auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG>;
   hipError_t e0 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e0 != hipSuccess) return e0;
   const int grid = max_grid < n_inst ? max_grid : n_inst;
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = NT;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, g, sv, insts, n_inst, counter, work, S);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst, counter, work, S);
   return hipGetLastError();
 }
 
-template <typename VT>
-static hipError_t dispatch_res(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
-                               int* counter, double* work, int max_grid, const double* S,
+template <typename VT, bool MG>
+static hipError_t dispatch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
+                               int n_inst, int* counter, double* work, int max_grid, const double* S,
                                int* grid_out, int* block_out, hipStream_t st) {
   ResCfg c;
   if (!pick_resident(g, &c)) return hipErrorInvalidValue;
-  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-  return launch_res<VT, 128, 16, 8, 64>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  return launch_res<VT, 128, 16, 8, 64, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
 }
 
-int ie_slots_per_cu(const Geom& g, int path, int precision) {
+template <typename VT, bool MG>
+static int occupancy_res(const Geom& g, const MGGeom* mg, const ResCfg& c) {
+  int nb = 0;
+  const int nt = c.cw * c.ns;
+  const size_t lds = resident_lds<VT>(g, c, MG ? mg : nullptr);
+  hipError_t e;
+  if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG>, nt, lds);
+  else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG>, nt, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG>, nt, lds);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision) {
   ResCfg c;
   if (path == MQ_PATH_RESIDENT && pick_resident(g, &c)) {
-    int nb = 0;
-    const int nt = c.cw * c.ns;
-    hipError_t e;
-    if (precision == MQ_PREC_FP64) {
-      size_t lds = resident_lds<double>(g, c);
-      if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 32, 16, 2, 32>, nt, lds);
-      else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 64, 16, 4, 64>, nt, lds);
-      else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<double, 128, 16, 8, 64>, nt, lds);
-    } else {
-      size_t lds = resident_lds<float>(g, c);
-      if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 32, 16, 2, 32>, nt, lds);
-      else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 64, 16, 4, 64>, nt, lds);
-      else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<float, 128, 16, 8, 64>, nt, lds);
-    }
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+    const bool usemg = mg && mg->nlev > 0;
+    if (precision == MQ_PREC_FP64)
+      return usemg ? occupancy_res<double, true>(g, mg, c) : occupancy_res<double, false>(g, mg, c);
+    return usemg ? occupancy_res<float, true>(g, mg, c) : occupancy_res<float, false>(g, mg, c);
   }
-  return 2;
+  return 1;
 }
 
 hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
@@ -620,19 +1121,23 @@ hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, 
                             int* grid_out, int* block_out, hipStream_t st);
 
 // n_slots: slots the work buffer was laid out for; max_grid (<= n_slots):
-// workgroups to launch.
-hipError_t launch_ie(const Geom& g, const Solver& sv, const Inst* insts, int n_inst, int* counter,
-                     double* work, int n_slots, int max_grid, const double* S, int path, int precision,
-                     const CellRegion& cr, const uint8_t* cond, const double* nl_params,
+// workgroups to launch.  The multigrid variant runs when mg.nlev > 0 and
+// sv.precond == 1.
+hipError_t launch_ie(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
+                     int* counter, double* work, int n_slots, int max_grid, const double* S, int path,
+                     int precision, const CellRegion& cr, const uint8_t* cond, const double* nl_params,
                      int* grid_out, int* block_out, hipStream_t st) {
   (void)cr;
   (void)cond;
   (void)nl_params;
   if (max_grid > n_slots) max_grid = n_slots;
   if (path == MQ_PATH_RESIDENT) {
+    const bool usemg = sv.precond == 1 && mg.nlev > 0;
     if (precision == MQ_PREC_FP64)
-      return dispatch_res<double>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-    return dispatch_res<float>(g, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+      return usemg ? dispatch_res<double, true>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st)
+                   : dispatch_res<double, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+    return usemg ? dispatch_res<float, true>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st)
+                 : dispatch_res<float, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
   }
   return launch_ie_stream(g, sv, insts, n_inst, counter, work, n_slots, max_grid, S, grid_out, block_out, st);
 }
@@ -879,7 +1384,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
   const int tid = threadIdx.x;
   const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 3 * FS;
+  double* Av = work + (size_t)blockIdx.x * 4 * FS;
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   VT* Rv = vwork + (size_t)blockIdx.x * (5 * FS + 4 * (size_t)RHW);

@@ -68,7 +68,26 @@ struct Inst {
   int group;                    // latency group (host bookkeeping: one per sample)
 };
 
+// Geometric multigrid hierarchy of the resident path (fine interior n = 2^k - 1;
+// level l+1 has (n_l - 1)/2 nodes per side, coarse node c sits at fine 2c + 1).
+// Each coarse level keeps Galerkin 7-point tables (C, E, N, NE planes, pitch
+// RW) over its box +- 1 ring; its vectors r, z, t (n_l^2 each, no halo) sit
+// at vec_off inside the LDS region shared with the fine exchange grid.
+constexpr int MG_MAX_LEVELS = 12;
+struct MGLevel {
+  int n, bx0, bx1, by0, by1, lx1, ly1, RW, RH, tab_off, vec_off;
+};
+struct MGGeom {
+  int nlev;          // coarse levels (lv[1..nlev]); 0 = multigrid unavailable
+  int region_elems;  // LDS elements of the shared region (fine grid or coarse vectors)
+  int ctab_elems;    // LDS elements of all coarse tables
+  MGLevel lv[MG_MAX_LEVELS];
+};
+bool build_mg(const Geom& g, int lp, MGGeom* mg);
+
 struct Solver {
+  int precond;     // 0 = Jacobi scaling only, 1 = multigrid V(1,1) (resident path)
+  double mg_omega; // damped-Jacobi weight of the multigrid smoother
   int precision;   // MQ_PREC_*
   double tol, inner_rtol;
   int max_iter, max_sweeps;
@@ -82,12 +101,12 @@ enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
 enum { STAT_N = 8 };
 
 // Launch helpers implemented in the .hip translation units.
-int resident_supported(const Geom& g, int precision, int lds_limit, int* lds_bytes);
+int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes);
 hipError_t launch_assemble(const Geom& g, const CellRegion& cr, const uint8_t* cond,
                            const double* kltab, int n_modes, int material, const double* xi,
                            int n_xi, int n_samples, const double* mat_params, double* tables,
                            hipStream_t st);
-hipError_t launch_ie(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+hipError_t launch_ie(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                      int* counter, double* work, int n_slots, int max_grid, const double* S, int path,
                      int precision, const CellRegion& cr, const uint8_t* cond,
                      const double* nl_params, int* grid_out, int* block_out, hipStream_t st);
@@ -104,7 +123,7 @@ hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);
-int ie_slots_per_cu(const Geom& g, int path, int precision);
+int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision);
 size_t ie_work_doubles(const Geom& g);
 size_t stream_vwork_elems(const Geom& g);
 

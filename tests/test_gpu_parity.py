@@ -69,14 +69,15 @@ def test_operator_apply_matches_oracle(n, kind):
     p.close()
 
 
-def test_plain_fp64_33_full_parity():
+@pytest.mark.parametrize("pc", [1, 2])
+def test_plain_fp64_33_full_parity(pc):
     """Plain MC, FP64, 33x33, 16 samples, 64 steps: Q and a_N within 1e-10."""
     mq, L = mqmod()
     w = W.plain_fp64_33()
     lv = w.levels[0]
     xi = W.level_xi(w, 0)
-    say("plain fp64 33 full")
-    p = mq.Problem(w.problem, L.MQ_PREC_FP64)
+    say(f"plain fp64 33 full precond={pc}")
+    p = mq.Problem(w.problem, L.MQ_PREC_FP64, precond=pc)
     qf, qc, fs, rc, st = mq.mlmc_level_run(p, lv.steps_per_period, 0, lv.n_periods, xi, want_state=True)
     assert rc == 0 and qc is None
     say("stats", st)
@@ -91,14 +92,17 @@ def test_plain_fp64_33_full_parity():
     p.close()
 
 
-@pytest.mark.parametrize("n,path", [(33, 1), (33, 2), (65, 1), (65, 2)])
-def test_mixed_kl_coupled_level(n, path):
-    """Mixed precision, KL field, coupled fine/coarse run: Q within 1e-6."""
+@pytest.mark.parametrize("n,path,pc", [(33, 1, 1), (33, 1, 2), (33, 2, 1), (65, 1, 1), (65, 1, 2),
+                                       (65, 2, 1), (129, 1, 2)])
+def test_mixed_kl_coupled_level(n, path, pc):
+    """Mixed precision, KL field, coupled fine/coarse run: Q within 1e-6
+    (resident/streaming path, Jacobi/multigrid preconditioner)."""
     mq, L = mqmod()
     prob = W.Problem(n, W.Material(kind=W.MAT_KL))
-    xi = W.normals(0, 21, 1, range(6), 8)
-    say(f"mixed kl n={n} path={path}")
-    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path)
+    xi = W.normals(0, 21, 1, range(6 if n < 129 else 3), 8)
+    say(f"mixed kl n={n} path={path} precond={pc}")
+    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path, precond=pc)
+    assert p.info.precond == pc
     qf, qc, _, rc, st = mq.mlmc_level_run(p, 32, 16, 2, xi)
     assert rc == 0
     say("stats", st)
