@@ -62,10 +62,13 @@ class RunStats(C.Structure):
         ("path", C.c_int32), ("grid", C.c_int32), ("block", C.c_int32),
         ("kernel_ms", C.c_double), ("total_ms", C.c_double),
         ("lat_p50_ms", C.c_double), ("lat_p99_ms", C.c_double), ("lat_max_ms", C.c_double),
+        ("phase_ms", C.c_double * 4),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 class LevelDesc(C.Structure):

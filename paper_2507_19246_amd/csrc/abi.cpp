@@ -175,6 +175,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   if (n == 0) return MQ_OK;
   DevPtr<int> dstat;
   HIP_TRY(dev_alloc(dstat, (size_t)n * STAT_N));
+  HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)n * STAT_N, p->stream));
   for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + STAT_N * i;
   DevPtr<Inst> dinst;
   HIP_TRY(dev_alloc(dinst, n));
@@ -247,6 +248,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
       st->inner_iters += s4[0];
       st->sweeps += s4[1];
       st->max_inner_per_step = std::max(st->max_inner_per_step, s4[2]);
+      for (int q = 0; q < 4; ++q) st->phase_ms[q] += (double)(uint32_t)s4[8 + q] * 16.0 / p->wall_khz;
       if (s4[3] & FLAG_NOT_CONVERGED) st->n_not_converged++;
       if (s4[3] & FLAG_FAILED) st->n_failed++;
     }

@@ -481,6 +481,17 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
 
     double qsum = 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
+    // per-phase device wall-clock ticks (thread 0): fine V-cycle descent,
+    // coarse levels, fine ascent, CG apply + reductions
+    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long tmark = 0;
+    auto tick = [&](int q) __attribute__((always_inline)) {
+      if (tid == 0) {
+        const unsigned long long t = wall_clock64();
+        if (q >= 0) ph[q] += t - tmark;
+        tmark = t;
+      }
+    };
     const int n_seg = in.n_chain > 0 ? in.n_chain : 1;
     for (int seg = 0; seg < n_seg; ++seg) {
       const int kseg0 = in.k0 + seg * in.n_steps;
@@ -699,6 +710,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               };
               // z = B r (symmetric V(1,1) cycle)
               auto vcycle = [&](const VT(&rv)[SH], VT(&zv)[SH]) __attribute__((always_inline)) {
+                tick(-1);
                 publish(rv);
                 __syncthreads();
                 fine_apply(rv, zv);  // zv used as scratch: A r
@@ -728,7 +740,9 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                   if (idx < n1 * n1) L1.r[idx] = rc[m];
                 }
                 __syncthreads();
+                tick(0);
                 const VT* z1 = coarse_cycle();
+                tick(1);
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
                   zv[k] = ACT(k) ? om * rv[k] + prolong_at<VT>(z1, n1, ci, j0 + k) : VT(0);
@@ -747,6 +761,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 }
                 __syncthreads();
                 fine_smooth(zv, rv);
+                tick(2);
               };
 
               // the iterate y is accumulated in the slot's global VT buffer
@@ -788,6 +803,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 for (int k = 0; k < SH; ++k) p[k] = z[k] + b_ * p[k];
                 if (it == sv.max_iter) break;
                 ++it;
+                tick(-1);
                 publish(p);
                 __syncthreads();
                 fine_apply(p, z);  // z holds q = A p here
@@ -805,6 +821,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                   if (ACT(k)) Yv[gi0 + k * g.P] += a_ * p[k];
                   r[k] = r[k] - a_ * z[k];
                 }
+                tick(3);
               }
               it_step += it;
 #pragma unroll
@@ -957,6 +974,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         in.stat[5] = (int)(t_begin >> 32);
         in.stat[6] = (int)(t_end & 0xffffffffull);
         in.stat[7] = (int)(t_end >> 32);
+        for (int q = 0; q < 4; ++q) in.stat[8 + q] = (int)(ph[q] >> 4);  // units of 16 ticks
       }
     }
     __syncthreads();

@@ -54,7 +54,8 @@ struct Inst {
   double* q_out;         // receives q_scale * sum_k d_k^T M d_k / dt
   double q_scale;
   int* stat;             // [STAT_N]: inner iterations, sweeps, max inner per step, flags,
-                         // device wall-clock start (lo, hi) and end (lo, hi)
+                         // device wall-clock start (lo, hi) and end (lo, hi), four
+                         // phase-time counters (units of 16 wall-clock ticks)
   double dt;
   int n_steps;           // steps per chain segment
   int k0;                // global index of the first step
@@ -98,7 +99,7 @@ struct Solver {
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
-enum { STAT_N = 8 };
+enum { STAT_N = 12 };
 
 // Launch helpers implemented in the .hip translation units.
 int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes);
