@@ -230,71 +230,200 @@ __device__ inline VT vt(double x) { return (VT)x; }
 // ---------------------------------------------------------------------------
 // multigrid helpers (resident path)
 // ---------------------------------------------------------------------------
-// Coarse-level view: Galerkin tables over the box +- 1 ring and the level's
-// vectors (n x n, row-major, no halo: out-of-range neighbours read as zero,
-// i.e. the Dirichlet boundary).
+// Coarse level l in LDS: vectors R, Z, T with a zero halo ((n+2)^2 each) and
+// Galerkin tables C, E, N, NE and the inverse diagonal ID over the box +- 1
+// ring (pitch RW).  Threads map to nodes as a TX x TY grid (TX = 2^txs >= n),
+// so no integer division appears in the level loops.
 template <typename VT>
-struct CView {
-  int n, bx0, bx1, by0, by1, lx1, ly1, RW;
-  const VT *C, *E, *N, *NE;
-  VT *r, *z, *t;
-  __device__ bool inL(int i, int j) const { return i >= bx0 && i < lx1 && j >= by0 && j < ly1; }
-  __device__ int tix(int i, int j) const { return (j - by0 + 1) * RW + (i - bx0 + 1); }
+struct CLev {
+  int n, np, bx0, by0, lx1, ly1, RW, txs;
+  VT *R, *Z, *T;
+  const VT *C, *E, *N, *NE, *ID;
 };
 
 template <typename VT>
-__device__ inline VT cget(const VT* v, int n, int i, int j) {
-  return (i >= 0 && i < n && j >= 0 && j < n) ? v[j * n + i] : VT(0);
+__device__ inline CLev<VT> clev(const MGGeom& mg, int l, VT* region, const VT* ctab, int nthr) {
+  const MGLevel& M = mg.lv[l];
+  CLev<VT> L;
+  L.n = M.n;
+  L.np = M.n + 2;
+  L.bx0 = M.bx0;
+  L.by0 = M.by0;
+  L.lx1 = M.lx1;
+  L.ly1 = M.ly1;
+  L.RW = M.RW;
+  int s = 0;
+  while ((1 << s) < M.n && (2 << s) <= nthr) ++s;
+  L.txs = s;
+  const int sz = L.np * L.np;
+  L.R = region + M.vec_off;
+  L.Z = L.R + sz;
+  L.T = L.Z + sz;
+  const int pl = M.RW * M.RH;
+  L.C = ctab + M.tab_off;
+  L.E = L.C + pl;
+  L.N = L.E + pl;
+  L.NE = L.N + pl;
+  L.ID = L.NE + pl;
+  return L;
 }
 
-// (A v)_{ij} and the diagonal at a coarse node
 template <typename VT>
-__device__ inline VT capply(const CView<VT>& L, const VT* v, int i, int j, VT* diag) {
-  const int n = L.n;
-  const VT c = v[j * n + i], e = cget(v, n, i + 1, j), w = cget(v, n, i - 1, j);
-  const VT nn = cget(v, n, i, j + 1), s = cget(v, n, i, j - 1);
-  if (L.inL(i, j)) {
-    const int t = L.tix(i, j);
-    const VT ne = cget(v, n, i + 1, j + 1), sw = cget(v, n, i - 1, j - 1);
-    *diag = L.C[t];
-    return L.C[t] * c + L.E[t] * e + L.E[t - 1] * w + L.N[t] * nn + L.N[t - L.RW] * s + L.NE[t] * ne +
-           L.NE[t - L.RW - 1] * sw;
+__device__ inline bool clev_inL(const CLev<VT>& L, int i, int j) {
+  return i >= L.bx0 && i < L.lx1 && j >= L.by0 && j < L.ly1;
+}
+
+// (A v)(i, j) and the inverse diagonal at a coarse node (v halo'd, pitch np)
+template <typename VT>
+__device__ inline VT capp(const CLev<VT>& L, const VT* v, int i, int j, VT* idg) {
+  const int np = L.np, p = (j + 1) * np + i + 1;
+  const VT c = v[p], e = v[p + 1], w = v[p - 1], nn = v[p + np], s = v[p - np];
+  if (clev_inL(L, i, j)) {
+    const int t = (j - L.by0 + 1) * L.RW + (i - L.bx0 + 1);
+    *idg = L.ID[t];
+    return L.C[t] * c + L.E[t] * e + L.E[t - 1] * w + L.N[t] * nn + L.N[t - L.RW] * s +
+           L.NE[t] * v[p + np + 1] + L.NE[t - L.RW - 1] * v[p - np - 1];
   }
-  *diag = VT(1);
+  *idg = VT(1);
   return c - VT(0.25) * ((e + w) + (nn + s));
 }
 
 template <typename VT>
-__device__ inline VT cdiag(const CView<VT>& L, int i, int j) {
-  return L.inL(i, j) ? L.C[L.tix(i, j)] : VT(1);
+__device__ inline VT clev_id(const CLev<VT>& L, int i, int j) {
+  return clev_inL(L, i, j) ? L.ID[(j - L.by0 + 1) * L.RW + (i - L.bx0 + 1)] : VT(1);
 }
 
-// Restriction r_c = P^T t (coarse c <-> fine 2c+1; weights 1 and 1/2 on the
-// six "/"-mesh neighbours), fine vector given by an accessor.
-template <typename VT, class FT>
-__device__ inline VT restrict_at(FT tf, int ic, int jc) {
-  const int i = 2 * ic + 1, j = 2 * jc + 1;
-  return tf(i, j) + VT(0.5) * ((tf(i + 1, j) + tf(i - 1, j)) + (tf(i, j + 1) + tf(i, j - 1)) +
-                               (tf(i + 1, j + 1) + tf(i - 1, j - 1)));
-}
-
-// Prolongation (P z_c)_{ij}: P1 interpolation on the coarse "/" triangulation.
+// Restriction P^T t at coarse node (ic, jc): coarse c <-> fine 2c+1, weights 1
+// and 1/2 on the six "/"-mesh neighbours; t halo'd with pitch fp.
 template <typename VT>
-__device__ inline VT prolong_at(const VT* zc, int nc, int i, int j) {
-  const bool io = i & 1, jo = j & 1;
-  if (io && jo) return cget(zc, nc, (i - 1) >> 1, (j - 1) >> 1);
-  if (!io && jo) return VT(0.5) * (cget(zc, nc, (i >> 1) - 1, (j - 1) >> 1) + cget(zc, nc, i >> 1, (j - 1) >> 1));
-  if (io && !jo) return VT(0.5) * (cget(zc, nc, (i - 1) >> 1, (j >> 1) - 1) + cget(zc, nc, (i - 1) >> 1, j >> 1));
-  return VT(0.5) * (cget(zc, nc, (i >> 1) - 1, (j >> 1) - 1) + cget(zc, nc, i >> 1, j >> 1));
+__device__ inline VT restrict_at(const VT* t, int fp, int ic, int jc) {
+  const int p = (2 * jc + 2) * fp + 2 * ic + 2;
+  return t[p] + VT(0.5) * ((t[p + 1] + t[p - 1]) + (t[p + fp] + t[p - fp]) + (t[p + fp + 1] + t[p - fp - 1]));
 }
 
-// Synchronisation of the threads working on one level: the whole workgroup
-// (level 1) or wave 0 alone (coarser levels): LDS traffic of one wave is
-// ordered once its outstanding LDS operations have completed.
+// Prolongation (P z_c)(i, j): P1 interpolation on the coarse "/" triangulation;
+// zc halo'd with pitch cp (its zero ring is the Dirichlet boundary).
+template <typename VT>
+__device__ inline VT prolong_at(const VT* zc, int cp, int i, int j) {
+  const int ic = i >> 1, jc = j >> 1;  // i odd: coarse (i-1)/2 = ic; i even: coarse ic-1 and ic
+  auto Zc = [&](int a, int b) { return zc[(b + 1) * cp + a + 1]; };
+  const bool io = i & 1, jo = j & 1;
+  if (io && jo) return Zc(ic, jc);
+  if (!io && jo) return VT(0.5) * (Zc(ic - 1, jc) + Zc(ic, jc));
+  if (io && !jo) return VT(0.5) * (Zc(ic, jc - 1) + Zc(ic, jc));
+  return VT(0.5) * (Zc(ic - 1, jc - 1) + Zc(ic, jc));
+}
+
+// Synchronisation of wave 0 alone (coarse levels it handles by itself): its
+// LDS operations are complete and ordered once they have been waited for.
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Level passes; (me, nthr) are the participating threads.
+template <typename VT>
+__device__ inline void c_resid(const CLev<VT>& L, int me, int nthr) {  // T = R - A Z
+  const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
+  if (tx >= L.n) return;
+  for (int j = me >> L.txs; j < L.n; j += ty) {
+    VT d;
+    const int p = (j + 1) * L.np + tx + 1;
+    L.T[p] = L.R[p] - capp(L, L.Z, tx, j, &d);
+  }
+}
+template <typename VT>
+__device__ inline void c_restrict(const CLev<VT>& F, const CLev<VT>& Cc, VT om, bool exact, int me,
+                                  int nthr) {  // Cc.R = P^T F.T, Cc.Z = om ID R (ID R at the coarsest)
+  const int tx = me & ((1 << Cc.txs) - 1), ty = nthr >> Cc.txs;
+  if (tx >= Cc.n) return;
+  for (int j = me >> Cc.txs; j < Cc.n; j += ty) {
+    const VT r = restrict_at(F.T, F.np, tx, j);
+    const int p = (j + 1) * Cc.np + tx + 1;
+    Cc.R[p] = r;
+    Cc.Z[p] = (exact ? VT(1) : om) * clev_id(Cc, tx, j) * r;
+  }
+}
+template <typename VT>
+__device__ inline void c_prolong(const CLev<VT>& L, const VT* zc, int cp, int me, int nthr) {
+  const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
+  if (tx >= L.n) return;
+  for (int j = me >> L.txs; j < L.n; j += ty) L.Z[(j + 1) * L.np + tx + 1] += prolong_at(zc, cp, tx, j);
+}
+template <typename VT>
+__device__ inline void c_post(const CLev<VT>& L, VT om, int me, int nthr) {  // T = Z + om ID (R - A Z)
+  const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
+  if (tx >= L.n) return;
+  for (int j = me >> L.txs; j < L.n; j += ty) {
+    VT id;
+    const int p = (j + 1) * L.np + tx + 1;
+    const VT az = capp(L, L.Z, tx, j, &id);
+    L.T[p] = L.Z[p] + om * id * (L.R[p] - az);
+  }
+}
+template <typename VT>
+__device__ inline void c_zero_halo(const CLev<VT>& L, int me, int nthr) {
+  const int np = L.np, m = 4 * (L.n + 1);
+  for (int q = me; q < m; q += nthr) {
+    int p;
+    if (q < np) p = q;                                   // row 0
+    else if (q < 2 * np) p = (L.n + 1) * np + (q - np);  // row n+1
+    else if (q < 2 * np + L.n) p = (q - 2 * np + 1) * np;          // column 0
+    else p = (q - 2 * np - L.n + 1) * np + L.n + 1;                // column n+1
+    L.R[p] = VT(0);
+    L.Z[p] = VT(0);
+    L.T[p] = VT(0);
+  }
+}
+
+// Coarse part of the V(1,1) cycle: levels 1..nlev, R_1 and Z_1 = om ID R_1
+// already in place.  Levels with n >= 31 use the whole workgroup, smaller
+// ones run on wave 0 alone.  Output: T_1 (or Z_1 if level 1 is the coarsest).
+template <typename VT, int NT>
+__device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid) {
+  const int L = mg.nlev;
+  auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= 31; };
+  int lb = 0;  // last block level
+  while (lb + 1 <= L && is_block(lb + 1)) ++lb;
+  // block levels: descent
+  for (int l = 1; l <= lb && l < L; ++l) {
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT);
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT);
+    c_resid(F, tid, NT);
+    __syncthreads();
+    c_restrict(F, Cc, om, l + 1 == L, tid, NT);
+    __syncthreads();
+  }
+  // wave levels
+  if (lb < L && tid < 64) {
+    for (int l = lb + 1; l < L; ++l) {
+      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64);
+      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64);
+      c_resid(F, tid, 64);
+      wave_sync();
+      c_restrict(F, Cc, om, l + 1 == L, tid, 64);
+      wave_sync();
+    }
+    for (int l = L - 1; l > lb; --l) {
+      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64);
+      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64);
+      c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, 64);
+      wave_sync();
+      c_post(F, om, tid, 64);
+      wave_sync();
+    }
+  }
+  if (lb < L) __syncthreads();
+  // block levels: ascent
+  for (int l = (lb < L ? lb : L - 1); l >= 1; --l) {
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT);
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT);
+    c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, NT);
+    __syncthreads();
+    c_post(F, om, tid, NT);
+    __syncthreads();
+  }
 }
 
 // Galerkin coarse entries A_c(c, c + D) = (P e_c)^T A_f (P e_{c+D}) for
@@ -350,8 +479,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   VT* tE = rl + region;                                  // scaled tables, RH x TP each
   VT* tN = tE + TRH;
   VT* tNE = tN + TRH;
-  VT* tD = tNE + TRH;
-  VT* ctab = tD + TRH;                                   // coarse Galerkin tables (multigrid)
+  VT* ctab = tNE + TRH;                                  // coarse Galerkin tables (multigrid)
   __shared__ int s_inst;
 
   const int tid = threadIdx.x;
@@ -421,7 +549,6 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       tE[ts] = vt<VT>(e);
       tN[ts] = vt<VT>(nn);
       tNE[ts] = vt<VT>(ne);
-      tD[ts] = vt<VT>(di);
     }
     for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
 #pragma unroll 1
@@ -443,6 +570,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         VT* E = C + pl;
         VT* Nn = E + pl;
         VT* NE = Nn + pl;
+        VT* ID = NE + pl;
         const int fp = l == 1 ? TP : F.RW;
         const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
         const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
@@ -473,11 +601,18 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           E[t] = vt<VT>(o[1]);
           Nn[t] = vt<VT>(o[2]);
           NE[t] = vt<VT>(o[3]);
+          ID[t] = vt<VT>(1.0 / o[0]);
         }
         __syncthreads();
       }
     }
-    auto DN = [&](int k) -> double { return INBOX(k) ? (double)tD[s0 + k * TP] : (double)vt<VT>(d_air); };
+    // per-node D^{-1/2} (box: from the FP64 tables; elsewhere the air value),
+    // rounded to VT like the scaled system it multiplies
+    auto DN = [&](int k) -> double {
+      if (!INBOX(k)) return (double)vt<VT>(d_air);
+      const int t = t0 + k * g.RW;
+      return (double)vt<VT>(1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]));
+    };
 
     double qsum = 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
@@ -613,101 +748,6 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                   __builtin_amdgcn_sched_barrier(0);
                 }
               };
-              // coarse levels 1..nlev (level 1 by the whole workgroup, the
-              // coarser ones by wave 0); returns level 1's output vector
-              auto cview = [&](int l) __attribute__((always_inline)) {
-                const MGLevel& M = mg.lv[l];
-                CView<VT> v;
-                v.n = M.n;
-                v.bx0 = M.bx0;
-                v.bx1 = M.bx1;
-                v.by0 = M.by0;
-                v.by1 = M.by1;
-                v.lx1 = M.lx1;
-                v.ly1 = M.ly1;
-                v.RW = M.RW;
-                const int pl = M.RW * M.RH;
-                v.C = ctab + M.tab_off;
-                v.E = v.C + pl;
-                v.N = v.E + pl;
-                v.NE = v.N + pl;
-                v.r = rl + M.vec_off;
-                v.z = v.r + M.n * M.n;
-                v.t = v.z + M.n * M.n;
-                return v;
-              };
-              auto level_out = [&](const CView<VT>& L) __attribute__((always_inline)) -> VT* { return L.n == 1 ? L.z : L.t; };
-              // one descent+ascent step of level l, threads me, me+st, ...
-              auto level_down = [&](const CView<VT>& L, const CView<VT>* Lc, int me, int st, bool wave) __attribute__((always_inline)) {
-                const int nn = L.n * L.n;
-                if (L.n == 1) {
-                  if (me == 0) L.z[0] = L.r[0] / cdiag(L, 0, 0);
-                  if (wave) wave_sync(); else __syncthreads();
-                  return;
-                }
-                for (int idx = me; idx < nn; idx += st) {
-                  const int i = idx % L.n, j = idx / L.n;
-                  L.z[idx] = om * L.r[idx] / cdiag(L, i, j);
-                }
-                if (wave) wave_sync(); else __syncthreads();
-                for (int idx = me; idx < nn; idx += st) {
-                  const int i = idx % L.n, j = idx / L.n;
-                  VT d;
-                  L.t[idx] = L.r[idx] - capply(L, L.z, i, j, &d);
-                }
-                if (wave) wave_sync(); else __syncthreads();
-                const int nc = Lc->n;
-                auto tf = [&](int i, int j) __attribute__((always_inline)) { return L.t[j * L.n + i]; };
-                for (int idx = me; idx < nc * nc; idx += st)
-                  Lc->r[idx] = restrict_at<VT>(tf, idx % nc, idx / nc);
-                if (wave) wave_sync(); else __syncthreads();
-              };
-              auto level_up = [&](const CView<VT>& L, const CView<VT>* Lc, int me, int st, bool wave) __attribute__((always_inline)) {
-                if (L.n == 1) return;
-                const int nn = L.n * L.n;
-                const VT* zc = level_out(*Lc);
-                for (int idx = me; idx < nn; idx += st) {
-                  const int i = idx % L.n, j = idx / L.n;
-                  L.z[idx] += prolong_at<VT>(zc, Lc->n, i, j);
-                }
-                if (wave) wave_sync(); else __syncthreads();
-                for (int idx = me; idx < nn; idx += st) {
-                  const int i = idx % L.n, j = idx / L.n;
-                  VT d;
-                  const VT az = capply(L, L.z, i, j, &d);
-                  L.t[idx] = L.z[idx] + om * (L.r[idx] - az) / d;
-                }
-                if (wave) wave_sync(); else __syncthreads();
-              };
-              auto coarse_cycle = [&]() __attribute__((always_inline)) -> VT* {
-                const CView<VT> L1 = cview(1);
-                if (L1.n == 1 || mg.nlev == 1) {
-                  level_down(L1, nullptr, tid, NT, false);
-                  return L1.z;
-                }
-                const CView<VT> L2 = cview(2);
-                level_down(L1, &L2, tid, NT, false);
-                if (tid < 64) {
-                  // levels >= 2 on wave 0
-                  for (int l = 2; l <= mg.nlev; ++l) {
-                    const CView<VT> Ll = cview(l);
-                    if (l < mg.nlev) {
-                      const CView<VT> Lc = cview(l + 1);
-                      level_down(Ll, &Lc, tid, 64, true);
-                    } else {
-                      level_down(Ll, nullptr, tid, 64, true);
-                    }
-                  }
-                  for (int l = mg.nlev - 1; l >= 2; --l) {
-                    const CView<VT> Ll = cview(l);
-                    const CView<VT> Lc = cview(l + 1);
-                    level_up(Ll, &Lc, tid, 64, true);
-                  }
-                }
-                __syncthreads();
-                level_up(L1, &L2, tid, NT, false);
-                return L1.t;
-              };
               // z = B r (symmetric V(1,1) cycle)
               auto vcycle = [&](const VT(&rv)[SH], VT(&zv)[SH]) __attribute__((always_inline)) {
                 tick(-1);
@@ -719,33 +759,37 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 __syncthreads();
                 publish(zv);
                 __syncthreads();
-                // restriction to level 1 into registers, then into the shared region
-                const CView<VT> L1 = cview(1);
+                // restriction to level 1 (registers), then R_1, Z_1 into the shared region
+                const CLev<VT> L1 = clev<VT>(mg, 1, rl, ctab, NT);
                 const int n1 = L1.n;
+                const int tx1 = tid & ((1 << L1.txs) - 1), ty1 = NT >> L1.txs, jb1 = tid >> L1.txs;
                 VT rc[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                  const int idx = tid + NT * m;
-                  rc[m] = VT(0);
-                  if (idx < n1 * n1) {
-                    auto tf = [&](int i, int j) __attribute__((always_inline)) { return rl[(j + 1) * LP + i + 1]; };
-                    rc[m] = restrict_at<VT>(tf, idx % n1, idx / n1);
-                  }
+                  const int j = jb1 + m * ty1;
+                  rc[m] = (tx1 < n1 && j < n1) ? restrict_at(rl, LP, tx1, j) : VT(0);
                   __builtin_amdgcn_sched_barrier(0);
                 }
                 __syncthreads();
+                for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, rl, ctab, NT), tid, NT);
+                const bool exact1 = mg.nlev == 1;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                  const int idx = tid + NT * m;
-                  if (idx < n1 * n1) L1.r[idx] = rc[m];
+                  const int j = jb1 + m * ty1;
+                  if (tx1 < n1 && j < n1) {
+                    const int q = (j + 1) * L1.np + tx1 + 1;
+                    L1.R[q] = rc[m];
+                    L1.Z[q] = (exact1 ? VT(1) : om) * clev_id(L1, tx1, j) * rc[m];
+                  }
                 }
                 __syncthreads();
                 tick(0);
-                const VT* z1 = coarse_cycle();
+                coarse_cycle<VT, NT>(mg, rl, ctab, om, tid);
                 tick(1);
+                const VT* z1 = exact1 ? L1.Z : L1.T;
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
-                  zv[k] = ACT(k) ? om * rv[k] + prolong_at<VT>(z1, n1, ci, j0 + k) : VT(0);
+                  zv[k] = ACT(k) ? om * rv[k] + prolong_at(z1, L1.np, ci, j0 + k) : VT(0);
                   __builtin_amdgcn_sched_barrier(0);
                 }
                 __syncthreads();
@@ -1034,9 +1078,9 @@ bool build_mg(const Geom& g, int lp, MGGeom* mg) {
     c.RW = (c.bx1 - c.bx0) + 2;
     c.RH = (c.by1 - c.by0) + 2;
     c.tab_off = tab;
-    tab += 4 * c.RW * c.RH;
+    tab += 5 * c.RW * c.RH;
     c.vec_off = vec;
-    vec += 3 * nc * nc;
+    vec += 3 * (nc + 2) * (nc + 2);
     mg->lv[++l] = c;
   }
   mg->nlev = l;
@@ -1053,7 +1097,7 @@ static size_t resident_lds(const Geom& g, const ResCfg& c, const MGGeom* mg) {
     region = mg->region_elems;
     ctab = mg->ctab_elems;
   }
-  return 2 * nw * 4 * sizeof(double) + (region + 4 * (size_t)g.RH * c.tp + ctab) * sizeof(VT);
+  return 2 * nw * 4 * sizeof(double) + (region + 3 * (size_t)g.RH * c.tp + ctab) * sizeof(VT);
 }
 
 static bool pick_resident(const Geom& g, ResCfg* c) {
@@ -1074,8 +1118,13 @@ int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_l
   if (!pick_resident(g, &c)) return 0;
   // 1024-thread FP64 workgroups would need more than 128 VGPRs per lane
   if (precision == MQ_PREC_FP64 && c.cw * c.ns > 256) return 0;
-  // the restriction to the first coarse level keeps 4 coarse nodes per thread
-  if (mg && mg->nlev > 0 && mg->lv[1].n * mg->lv[1].n > 4 * c.cw * c.ns) return 0;
+  // the restriction to the first coarse level keeps 4 coarse rows per thread
+  if (mg && mg->nlev > 0) {
+    int tx = 1;
+    while (tx < mg->lv[1].n && 2 * tx <= c.cw * c.ns) tx *= 2;
+    const int ty = c.cw * c.ns / tx;
+    if ((mg->lv[1].n + ty - 1) / ty > 4) return 0;
+  }
   size_t b = precision == MQ_PREC_FP64 ? resident_lds<double>(g, c, mg) : resident_lds<float>(g, c, mg);
   if (lds_bytes) *lds_bytes = (int)b;
   return b <= (size_t)lds_limit ? 1 : 0;
