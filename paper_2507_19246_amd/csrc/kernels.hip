@@ -481,6 +481,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   VT* tNE = tN + TRH;
   VT* ctab = tNE + TRH;                                  // coarse Galerkin tables (multigrid)
   __shared__ int s_inst;
+  __shared__ int s_dmin;  // bits of min_i D_ii^{-1/2} (positive float: int order = float order)
 
   const int tid = threadIdx.x;
   const int ci = tid % CW;
@@ -488,10 +489,11 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   const bool colok = ci < n;
   const bool strip_ok = colok && j0 < n;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 4 * FS;
+  double* Av = work + (size_t)blockIdx.x * 5 * FS;
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate (full grid)
+  double* Pv = Bv + 2 * FS;                  // previous increment (extrapolated start)
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   int slot = 0;
 
@@ -535,10 +537,13 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       }
       return d_air;
     };
+    if (tid == 0) s_dmin = __float_as_int((float)d_air);
+    __syncthreads();
     for (int t = tid; t < RHW; t += NT) {
       const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       const double di = dscale(i, j);
+      if (box) atomicMin(&s_dmin, __float_as_int((float)di));
       double e = -0.25, nn = -0.25, ne = 0.0;
       if (box) {
         e = (tab[T_ME * RHW + t] * inv_dt + tab[T_KE * RHW + t]) * di * dscale(i + 1, j);
@@ -557,9 +562,14 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         const int gi = gi0 + k * g.P;
         Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
         Xv[gi] = 0.0;
+        Pv[gi] = 0.0;
       }
     }
     __syncthreads();
+    // inner solves stop once the scaled residual guarantees the outer test:
+    // ||b - A x|| <= D_max^{1/2} ||r_scaled|| (half the outer tolerance)
+    const double dmin = (double)__int_as_float(s_dmin) * 0.999;
+    const double floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
     if constexpr (MG) {
       // Galerkin coarse operators A_l = P^T A_{l-1} P of the scaled system
       for (int l = 1; l <= mg.nlev; ++l) {
@@ -835,7 +845,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 block_sum<2, NWAVES>(rz, red, slot);
                 double beta = 0.0;
                 if (it == 0) {
-                  stop = sv.inner_rtol * sv.inner_rtol * rz[1];
+                  stop = fmax(sv.inner_rtol * sv.inner_rtol * rz[1], floor_fac * bb);
                   if (!(rz[1] > 0.0) || !(rz[0] > 0.0)) break;
                 } else {
                   if (rz[1] <= stop || !(rz[1] == rz[1])) break;
@@ -901,7 +911,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               block_sum<1, NWAVES>(gv, red, slot);  // also publishes r in LDS
               const double gam = gv[0];
               if (it == 0) {
-                stop = sv.inner_rtol * sv.inner_rtol * gam;
+                stop = fmax(sv.inner_rtol * sv.inner_rtol * gam, floor_fac * bb);
                 if (!(gam > 0.0)) break;
               } else if (gam <= stop || !(gam == gam)) {
                 break;
@@ -978,8 +988,16 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         block_sum<1, NWAVES>(qq, red, slot);
         qsum += qq[0] * inv_dt;
 #pragma unroll 1
-        for (int k = 0; k < SH; ++k)
-          if (ACT(k)) Av[gi0 + k * g.P] += Xv[gi0 + k * g.P];
+        for (int k = 0; k < SH; ++k) {
+          if (ACT(k)) {
+            // a += d; next start 2 d_k - d_{k-1} (linear extrapolation)
+            const int gi = gi0 + k * g.P;
+            const double d = Xv[gi];
+            Av[gi] += d;
+            Xv[gi] = 2.0 * d - Pv[gi];
+            Pv[gi] = d;
+          }
+        }
         __syncthreads();
       }
       if (in.n_chain > 0) {
@@ -1130,7 +1148,7 @@ int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_l
   return b <= (size_t)lds_limit ? 1 : 0;
 }
 
-size_t ie_work_doubles(const Geom& g) { return 4 * (size_t)g.N * g.P; }
+size_t ie_work_doubles(const Geom& g) { return 5 * (size_t)g.N * g.P; }
 
 template <typename VT, int CW, int SH, int NS, int TP, bool MG>
 static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
@@ -1448,12 +1466,14 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
   constexpr int NWAVES = NT / 64;
   __shared__ double red[2 * NWAVES * 4];
   __shared__ int s_inst;
+  __shared__ int s_dmin;
   const int tid = threadIdx.x;
   const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 4 * FS;
+  double* Av = work + (size_t)blockIdx.x * 5 * FS;
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
+  double* Xprev = Bv + 2 * FS;
   VT* Rv = vwork + (size_t)blockIdx.x * (5 * FS + 4 * (size_t)RHW);
   VT* Yv = Rv + FS;
   VT* Pv = Yv + FS;
@@ -1484,10 +1504,13 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
       }
       return d_air;
     };
+    if (tid == 0) s_dmin = __float_as_int((float)d_air);
+    __syncthreads();
     for (int t = tid; t < RHW; t += NT) {
       const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       const double di = dscale(i, j);
+      if (box) atomicMin(&s_dmin, __float_as_int((float)di));
       double e = -0.25, nn = -0.25, ne = 0.0;
       if (box) {
         e = (tab[T_ME * RHW + t] * inv_dt + tab[T_KE * RHW + t]) * di * dscale(i + 1, j);
@@ -1503,8 +1526,11 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
       const int gi = (idx / n + 1) * g.P + idx % n + 1;
       Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
       Xv[gi] = 0.0;
+      Xprev[gi] = 0.0;
     }
     __syncthreads();
+    const double dmin = (double)__int_as_float(s_dmin) * 0.999;
+    const double floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
     auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       return box ? tD[nr.t] : (VT)d_air;
@@ -1567,7 +1593,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
             block_sum<2, NWAVES>(gd, red, slot);
             const double g0 = gd[0];
             double gam = gd[0], alpha = gd[0] / gd[1], beta = 0.0;
-            const double stop = sv.inner_rtol * sv.inner_rtol * g0;
+            const double stop = fmax(sv.inner_rtol * sv.inner_rtol * g0, floor_fac * bb);
             int it = 0;
             if (g0 > 0.0) {
               for (it = 1; it <= sv.max_iter; ++it) {
@@ -1622,7 +1648,10 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
         qsum += qq[0] * inv_dt;
         for (int idx = tid; idx < nd; idx += NT) {
           const int gi = (idx / n + 1) * g.P + idx % n + 1;
-          Av[gi] += Xv[gi];
+          const double d = Xv[gi];
+          Av[gi] += d;
+          Xv[gi] = 2.0 * d - Xprev[gi];
+          Xprev[gi] = d;
         }
         __syncthreads();
       }
