@@ -30,6 +30,11 @@ if ROOT not in sys.path:
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
 CG_FLOPS_PER_DOF_ITER = 26          # 7-point scaled stencil (14) + CG vector updates and dots (12)
+# one multigrid-preconditioned CG iteration on the fine level: the CG stencil
+# and vector work (26), the V(1,1) cycle's residual and post-smoothing stencils
+# (2 x 14), smoothing/residual updates (6), restriction and prolongation (8),
+# plus the coarse levels (1/4 + 1/16 + ... of that work)
+MG_FLOPS_PER_DOF_ITER = 26 + (28 + 6 + 8) * 4.0 / 3.0
 CG_BYTES_PER_DOF_ITER_FP32 = 72     # modelled streaming traffic of one FP32 CG iteration
 
 
@@ -171,7 +176,8 @@ def main():
     kern_ms = [s["kernel_ms"] for s in stats]
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     units = nd * (sum(s["inner_iters"] for s in stats) / len(stats))   # DoF-iterations per launch
-    achieved_tflops = CG_FLOPS_PER_DOF_ITER * units / avg_kern_s / 1e12
+    flops_unit = MG_FLOPS_PER_DOF_ITER if prob.info.precond == L.MQ_PRECOND_MULTIGRID else CG_FLOPS_PER_DOF_ITER
+    achieved_tflops = flops_unit * units / avg_kern_s / 1e12
     traffic = measured_traffic("ie_resident_mlmc3_129_hbm_counters.md")
 
     # QoI error of the mixed path against FP64 references
@@ -241,9 +247,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_ie_resident<float,128,16,8,64>",
+                     "kernel": "k_ie_resident<float,128,16,8,64,multigrid>",
                      "avg_launch_ms": 1e3 * avg_kern_s,
-                     "flops_per_dof_iter": CG_FLOPS_PER_DOF_ITER,
+                     "flops_per_dof_iter": flops_unit,
+                     "precond": "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi",
                      "dof_iters_per_launch": units,
                      "hbm_equivalent_gbs": CG_BYTES_PER_DOF_ITER_FP32 * units / avg_kern_s / 1e9},
         "cpu_baseline": cpu,
