@@ -249,6 +249,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
       st->sweeps += s4[1];
       st->max_inner_per_step = std::max(st->max_inner_per_step, s4[2]);
       for (int q = 0; q < 4; ++q) st->phase_ms[q] += (double)(uint32_t)s4[8 + q] * 16.0 / p->wall_khz;
+      st->picard_iters += s4[12];
       if (s4[3] & FLAG_NOT_CONVERGED) st->n_not_converged++;
       if (s4[3] & FLAG_FAILED) st->n_failed++;
     }
@@ -266,7 +267,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
 
 int assemble(mq_problem* p, const double* xi, int n, DevPtr<double>& tables) {
   const Geom& g = p->hm.g;
-  HIP_TRY(dev_alloc(tables, (size_t)n * T_NPLANES * g.RW * g.RH));
+  HIP_TRY(dev_alloc(tables, (size_t)n * tab_stride(g)));
   HIP_TRY(launch_assemble(g, p->hm.cr, p->dcond.get(), p->dkl.get(), p->hm.n_modes, p->d.material, xi,
                           p->n_xi, n, p->mat, tables.get(), p->stream));
   return MQ_OK;
@@ -319,7 +320,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
   const size_t RHW = (size_t)g.RW * g.RH;
   for (int s = 0; s < n; ++s) {
     Inst in{};
-    in.tab = lb.tables.get() + (size_t)s * T_NPLANES * RHW;
+    in.tab = lb.tables.get() + (size_t)s * tab_stride(g);
     in.src = lb.src_f.get();
     in.a_out = want_state ? lb.afull_ptr[s] : nullptr;
     in.q_out = qf + s;
@@ -389,6 +390,8 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   p->resident_ok = resident_supported(p->hm.g, have_mg ? &p->mg : nullptr, d->precision, p->lds_limit, &p->lds_bytes);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
     return fail(MQ_ERR_INVALID_ARG, "the resident path does not fit this mesh/precision");
+  if (d->material == MQ_MAT_NONLINEAR && (!p->resident_ok || d->path == MQ_PATH_STREAMING))
+    return fail(MQ_ERR_INVALID_ARG, "the nonlinear (Picard) material runs on the resident path only");
   p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
   const double m[10] = {d->sigma0, d->nu_cond, d->nu_air, d->s_sigma, d->s_nu, d->s_kl, d->k1, d->k2, d->k3, d->s_k};
   std::memcpy(p->mat, m, sizeof(m));
@@ -560,7 +563,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
     std::vector<Inst> insts;
     for (size_t a = 0; a < smp.size(); ++a) {
       Inst in{};
-      in.tab = tables.get() + (size_t)smp[a] * T_NPLANES * RHW;
+      in.tab = tables.get() + (size_t)smp[a] * tab_stride(g);
       in.src = dsc.get();
       in.a_init = U(smp[a], first - 1);
       in.dt = dtc;
@@ -587,7 +590,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
     for (int s : active)
       for (int nn = j; nn <= M; ++nn) {
         Inst in{};
-        in.tab = tables.get() + (size_t)s * T_NPLANES * RHW;
+        in.tab = tables.get() + (size_t)s * tab_stride(g);
         in.src = dsf.get();
         in.a_init = U(s, nn - 1);
         in.a_out = F(s, nn);

@@ -67,7 +67,16 @@ __global__ void k_assemble(Geom g, CellRegion cr, const uint8_t* __restrict__ co
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int smp = blockIdx.y;
   if (t >= RHW || smp >= n_samples) return;
-  double* T = tables + (size_t)smp * T_NPLANES * RHW;
+  double* T = tables + (size_t)smp * tab_stride(g);
+  if (t == 0) {
+    const double* x0 = xi + (size_t)smp * n_xi;
+    double* kp = T + T_NPLANES * RHW;
+    const bool nl = material == MQ_MAT_NONLINEAR;
+    kp[0] = nl ? mp.k1 * exp(mp.s_k * x0[0]) : 0.0;
+    kp[1] = nl ? mp.k2 * exp(mp.s_k * x0[1]) : 0.0;
+    kp[2] = nl ? mp.k3 * exp(mp.s_k * x0[2]) : 0.0;
+    kp[3] = 0.0;
+  }
   const int i = g.bx0 - 1 + t % g.RW;
   const int j = g.by0 - 1 + t / g.RW;
   const bool inbox = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
@@ -463,11 +472,12 @@ __device__ inline void galerkin_entries(CF cf, int nf, int nc, int ic, int jc, d
 // LDS pitches are compile-time constants (LP = CW + 2 for the grid, TP for
 // the tables) so that every per-node LDS offset folds into the instruction's
 // immediate offset instead of occupying a register.
-template <typename VT, int CW, int SH, int NS, int TP, bool MG>
+template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL>
 __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solver sv,
                                                         const Inst* __restrict__ insts, int n_inst,
                                                         int* counter, double* work,
-                                                        const double* __restrict__ S) {
+                                                        const double* __restrict__ S,
+                                                        const uint8_t* __restrict__ cond, CellRegion cr) {
   constexpr int NT = CW * NS;
   constexpr int NWAVES = NT / 64;
   constexpr int LP = CW + 2;
@@ -492,8 +502,10 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   double* Av = work + (size_t)blockIdx.x * 5 * FS;
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
-  VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate (full grid)
+  VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate, thread-private [k][tid] layout
   double* Pv = Bv + 2 * FS;                  // previous increment (extrapolated start)
+  double* Qv = Pv + FS;                      // Picard: increment of the last fixed-point iterate
+  double* Tslot = Qv + FS;                   // Picard: this instance's FP64 tables (K re-assembled)
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   int slot = 0;
 
@@ -528,6 +540,13 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     const double* tab = in.tab;
     const double inv_dt = 1.0 / in.dt;
     const unsigned long long t_begin = wall_clock64();
+    if constexpr (NL) {
+      // private copy of the sample's tables; K planes are re-assembled per Picard iteration
+      for (int t = tid; t < T_NPLANES * RHW + 3; t += NT) Tslot[t] = in.tab[t];
+      __syncthreads();
+      tab = Tslot;
+    }
+    double dmin = 0.0, floor_fac = 0.0;
 
     // scaled couplings D^{-1/2} A D^{-1/2} over the table region, FP64 -> VT
     auto dscale = [&](int i, int j) -> double {
@@ -537,6 +556,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       }
       return d_air;
     };
+    auto build_tables = [&]() {
     if (tid == 0) s_dmin = __float_as_int((float)d_air);
     __syncthreads();
     for (int t = tid; t < RHW; t += NT) {
@@ -555,21 +575,11 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       tN[ts] = vt<VT>(nn);
       tNE[ts] = vt<VT>(ne);
     }
-    for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
-#pragma unroll 1
-    for (int k = 0; k < SH; ++k) {
-      if (ACT(k)) {
-        const int gi = gi0 + k * g.P;
-        Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
-        Xv[gi] = 0.0;
-        Pv[gi] = 0.0;
-      }
-    }
     __syncthreads();
     // inner solves stop once the scaled residual guarantees the outer test:
     // ||b - A x|| <= D_max^{1/2} ||r_scaled|| (half the outer tolerance)
-    const double dmin = (double)__int_as_float(s_dmin) * 0.999;
-    const double floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
+    dmin = (double)__int_as_float(s_dmin) * 0.999;
+    floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
     if constexpr (MG) {
       // Galerkin coarse operators A_l = P^T A_{l-1} P of the scaled system
       for (int l = 1; l <= mg.nlev; ++l) {
@@ -616,6 +626,54 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         __syncthreads();
       }
     }
+    };
+    for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
+#pragma unroll 1
+    for (int k = 0; k < SH; ++k) {
+      if (ACT(k)) {
+        const int gi = gi0 + k * g.P;
+        Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
+        Xv[gi] = 0.0;
+        Pv[gi] = 0.0;
+        Qv[gi] = 0.0;
+      }
+    }
+    __syncthreads();
+    // Picard: K(nu(|grad a|^2)) on the box from the state a_k + Q (FP64)
+    auto assemble_K = [&]() {
+      const double* kp = in.tab + T_NPLANES * RHW;  // k1', k2', k3' of the sample
+      const double k1 = kp[0], k2 = kp[1], k3 = kp[2], hinv2 = 1.0 / g.h2;
+      auto st_at = [&](int I, int J) -> double {  // full-grid node value of a_k + Q
+        const int q = J * g.P + I;
+        return Av[q] + Qv[q];
+      };
+      auto nu_el = [&](int ci_, int cj_, int tt) -> double {
+        const int e = ((cj_ - cr.cy0) * cr.cw + (ci_ - cr.cx0)) * 2 + tt;
+        if (!cond[e]) return g.nu_air;
+        double gx, gy;
+        if (tt == 0) {
+          gx = st_at(ci_ + 1, cj_) - st_at(ci_, cj_);
+          gy = st_at(ci_ + 1, cj_ + 1) - st_at(ci_ + 1, cj_);
+        } else {
+          gx = st_at(ci_ + 1, cj_ + 1) - st_at(ci_, cj_ + 1);
+          gy = st_at(ci_, cj_ + 1) - st_at(ci_, cj_);
+        }
+        return k1 * exp(k2 * (gx * gx + gy * gy) * hinv2) + k3;
+      };
+      double* T = Tslot;
+      for (int t = tid; t < RHW; t += NT) {
+        const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
+        if (!(i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1)) continue;
+        const int I = i + 1, J = j + 1;
+        const double na0 = nu_el(I, J, 0), na1 = nu_el(I, J, 1), nb0 = nu_el(I - 1, J, 0);
+        const double nc1 = nu_el(I, J - 1, 1), nd0 = nu_el(I - 1, J - 1, 0), nd1 = nu_el(I - 1, J - 1, 1);
+        T[T_KC * RHW + t] = 0.5 * (na0 + na1 + nd0 + nd1) + nb0 + nc1;
+        T[T_KE * RHW + t] = -0.5 * (na0 + nc1);
+        T[T_KN * RHW + t] = -0.5 * (na1 + nb0);
+      }
+      __syncthreads();
+    };
+    if constexpr (!NL) build_tables();
     // per-node D^{-1/2} (box: from the FP64 tables; elsewhere the air value),
     // rounded to VT like the scaled system it multiplies
     auto DN = [&](int k) -> double {
@@ -625,7 +683,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     };
 
     double qsum = 0.0;
-    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
+    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0, pic_total = 0;
     // per-phase device wall-clock ticks (thread 0): fine V-cycle descent,
     // coarse levels, fine ascent, CG apply + reductions
     unsigned long long ph[4] = {0, 0, 0, 0};
@@ -642,6 +700,12 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       const int kseg0 = in.k0 + seg * in.n_steps;
       for (int step = 0; step < in.n_steps; ++step) {
         const double Jt = in.src[kseg0 + step + 1];
+        int pic_it = 0;
+        for (;;) {  // Picard iterations (a single pass for linear materials)
+        if constexpr (NL) {
+          assemble_K();
+          build_tables();
+        }
         // b = J(t_{k+1}) S - K a and ||b||^2
         double part[1] = {0.0};
 #pragma unroll 1
@@ -825,7 +889,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               for (int k = 0; k < SH; ++k) {
                 r[k] = ACT(k) ? rl[l0 + k * LP] : VT(0);
                 p[k] = VT(0);
-                if (ACT(k)) Yv[gi0 + k * g.P] = VT(0);
+                if (ACT(k)) Yv[k * NT + tid] = VT(0);
               }
               double rho = 1.0, stop = 0.0;
               int it = 0;
@@ -872,7 +936,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 const VT a_ = vt<VT>(rho / pq[0]);
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
-                  if (ACT(k)) Yv[gi0 + k * g.P] += a_ * p[k];
+                  if (ACT(k)) Yv[k * NT + tid] += a_ * p[k];
                   r[k] = r[k] - a_ * z[k];
                 }
                 tick(3);
@@ -880,7 +944,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               it_step += it;
 #pragma unroll
               for (int k = 0; k < SH; ++k)
-                if (ACT(k)) rl[l0 + k * LP] = Yv[gi0 + k * g.P];
+                if (ACT(k)) rl[l0 + k * LP] = Yv[k * NT + tid];
             } else {
             // ---- inner CG on the scaled system, y0 = 0, r0 = g ----
             // Chronopoulos-Gear ordering: the reduction of r.r shares its
@@ -978,6 +1042,28 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         }
         it_total += it_step;
         it_max_step = it_step > it_max_step ? it_step : it_max_step;
+        if constexpr (!NL) break;
+        // fixed-point test ||a^(i+1) - a^(i)|| <= tol ||a^(i+1)|| with a^(i) = a_k + Q
+        double dn2[2] = {0.0, 0.0};
+#pragma unroll 1
+        for (int k = 0; k < SH; ++k) {
+          if (ACT(k)) {
+            const int gi = gi0 + k * g.P;
+            const double x = Xv[gi], dq = x - Qv[gi], an = Av[gi] + x;
+            dn2[0] += dq * dq;
+            dn2[1] += an * an;
+            Qv[gi] = x;
+          }
+        }
+        block_sum<2, NWAVES>(dn2, red, slot);
+        ++pic_it;
+        if (dn2[0] <= sv.picard_tol * sv.picard_tol * dn2[1]) break;
+        if (pic_it >= sv.picard_max) {
+          flags |= FLAG_PICARD_CAP;
+          break;
+        }
+        }
+        pic_total += pic_it;
         // Joule-loss term d^T M d / dt and the state update a += d
         double qq[1] = {0.0};
 #pragma unroll 1
@@ -996,6 +1082,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
             Av[gi] += d;
             Xv[gi] = 2.0 * d - Pv[gi];
             Pv[gi] = d;
+            Qv[gi] = 0.0;
           }
         }
         __syncthreads();
@@ -1037,6 +1124,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         in.stat[6] = (int)(t_end & 0xffffffffull);
         in.stat[7] = (int)(t_end >> 32);
         for (int q = 0; q < 4; ++q) in.stat[8 + q] = (int)(ph[q] >> 4);  // units of 16 ticks
+        in.stat[12] = pic_total;
       }
     }
     __syncthreads();
@@ -1148,33 +1236,38 @@ int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_l
   return b <= (size_t)lds_limit ? 1 : 0;
 }
 
-size_t ie_work_doubles(const Geom& g) { return 5 * (size_t)g.N * g.P; }
+size_t ie_work_doubles(const Geom& g) {
+  return 6 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
+}
 
-template <typename VT, int CW, int SH, int NS, int TP, bool MG>
+template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL>
 static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
                              int n_inst, int* counter, double* work, int max_grid, const double* S,
+                             const uint8_t* cond, const CellRegion& cr,
                              int* grid_out, int* block_out, hipStream_t st) {
   constexpr int NT = CW * NS;
   const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP}, MG ? &mg : nullptr);
-  auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG>;
+  auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG, NL>;
   hipError_t e0 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e0 != hipSuccess) return e0;
   const int grid = max_grid < n_inst ? max_grid : n_inst;
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = NT;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst, counter, work, S);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst, counter, work, S,
+                     cond, cr);
   return hipGetLastError();
 }
 
-template <typename VT, bool MG>
+template <typename VT, bool MG, bool NL>
 static hipError_t dispatch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
                                int n_inst, int* counter, double* work, int max_grid, const double* S,
+                               const uint8_t* cond, const CellRegion& cr,
                                int* grid_out, int* block_out, hipStream_t st) {
   ResCfg c;
   if (!pick_resident(g, &c)) return hipErrorInvalidValue;
-  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-  return launch_res<VT, 128, 16, 8, 64, MG>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  return launch_res<VT, 128, 16, 8, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
 }
 
 template <typename VT, bool MG>
@@ -1183,9 +1276,9 @@ static int occupancy_res(const Geom& g, const MGGeom* mg, const ResCfg& c) {
   const int nt = c.cw * c.ns;
   const size_t lds = resident_lds<VT>(g, c, MG ? mg : nullptr);
   hipError_t e;
-  if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG>, nt, lds);
-  else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG>, nt, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG>, nt, lds);
+  if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG, false>, nt, lds);
+  else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG, false>, nt, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG, false>, nt, lds);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
@@ -1212,17 +1305,20 @@ hipError_t launch_ie(const Geom& g, const MGGeom& mg, const Solver& sv, const In
                      int* counter, double* work, int n_slots, int max_grid, const double* S, int path,
                      int precision, const CellRegion& cr, const uint8_t* cond, const double* nl_params,
                      int* grid_out, int* block_out, hipStream_t st) {
-  (void)cr;
-  (void)cond;
   (void)nl_params;
   if (max_grid > n_slots) max_grid = n_slots;
   if (path == MQ_PATH_RESIDENT) {
     const bool usemg = sv.precond == 1 && mg.nlev > 0;
-    if (precision == MQ_PREC_FP64)
-      return usemg ? dispatch_res<double, true>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st)
-                   : dispatch_res<double, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
-    return usemg ? dispatch_res<float, true>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st)
-                 : dispatch_res<float, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, grid_out, block_out, st);
+    const bool nl = sv.nonlinear != 0;
+#define MQ_DISPATCH(VT_, MG_, NL_) \
+  dispatch_res<VT_, MG_, NL_>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st)
+    if (precision == MQ_PREC_FP64) {
+      if (nl) return usemg ? MQ_DISPATCH(double, true, true) : MQ_DISPATCH(double, false, true);
+      return usemg ? MQ_DISPATCH(double, true, false) : MQ_DISPATCH(double, false, false);
+    }
+    if (nl) return usemg ? MQ_DISPATCH(float, true, true) : MQ_DISPATCH(float, false, true);
+    return usemg ? MQ_DISPATCH(float, true, false) : MQ_DISPATCH(float, false, false);
+#undef MQ_DISPATCH
   }
   return launch_ie_stream(g, sv, insts, n_inst, counter, work, n_slots, max_grid, S, grid_out, block_out, st);
 }
@@ -1239,7 +1335,7 @@ __global__ void k_apply(Geom g, int which, double inv_dt, const double* __restri
   if (idx >= nd || smp >= nsmp) return;
   const size_t FS = (size_t)g.N * g.P;
   const double* v = scratch + smp * FS;
-  const double* tab = tables + (size_t)smp * T_NPLANES * g.RW * g.RH;
+  const double* tab = tables + (size_t)smp * tab_stride(g);
   const int i = idx % g.n, j = idx / g.n;
   const NodeRef nr = node_ref(g, i, j);
   double out;

@@ -34,8 +34,10 @@ struct Geom {
   double h, h2, nu_air;
 };
 
-// FP64 coefficient planes of one sample over the table region R.
+// FP64 coefficient planes of one sample over the table region R, followed by
+// the sample's nonlinear curve coefficients k1', k2', k3' (and one pad).
 enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
+__host__ __device__ inline size_t tab_stride(const Geom& g) { return (size_t)T_NPLANES * g.RW * g.RH + 4; }
 
 // Element data over the cells that touch the box: full-grid cells
 // [bx0, bx1 + 1) x [by0, by1 + 1), two triangles per cell
@@ -55,7 +57,8 @@ struct Inst {
   double q_scale;
   int* stat;             // [STAT_N]: inner iterations, sweeps, max inner per step, flags,
                          // device wall-clock start (lo, hi) and end (lo, hi), four
-                         // phase-time counters (units of 16 wall-clock ticks)
+                         // phase-time counters (units of 16 wall-clock ticks), Picard
+                         // iterations
   double dt;
   int n_steps;           // steps per chain segment
   int k0;                // global index of the first step
@@ -99,7 +102,7 @@ struct Solver {
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
-enum { STAT_N = 12 };
+enum { STAT_N = 13 };
 
 // Launch helpers implemented in the .hip translation units.
 int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes);

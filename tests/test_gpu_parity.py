@@ -199,3 +199,30 @@ def test_single_dof_mesh():
     qref, aref = oracle_q(prob, xi, 16, 1)
     assert float(qf[0]) == pytest.approx(qref[0], rel=1e-12)
     p.close()
+
+
+@pytest.mark.parametrize("n,prec,k2", [(33, 0, 1.0e3), (33, 1, 1.0e3), (65, 1, 2.17)])
+def test_picard_nonlinear_matches_oracle(n, prec, k2):
+    """Nonlinear reluctivity nu(|B|) solved per step by Picard iteration in the
+    kernel; Q and the Picard iteration totals against the oracle."""
+    from oracle import picard as opic
+    mq, L = mqmod()
+    prob = W.Problem(n, W.Material(kind=W.MAT_NONLINEAR, k2=k2))
+    xi = W.normals(0, 31, 0, range(3), 3)
+    say(f"picard n={n} prec={prec} k2={k2}")
+    solver = dict(tol=1e-12, inner_rtol=1e-9) if prec == 0 else dict(tol=1e-10, inner_rtol=1e-5)
+    p = mq.Problem(prob, prec, **solver)
+    qf, _, _, rc, st = mq.mlmc_level_run(p, 16, 0, 1, xi)
+    assert rc == 0
+    m = omesh.build(n)
+    ref_q, ref_its = [], 0
+    for x in xi:
+        Q, a, counts, flagged = opic.solve_sample(prob, x, 16, 1, m=m, return_counts=True)
+        assert not flagged
+        ref_q.append(Q)
+        ref_its += int(counts.sum())
+    err = np.max(np.abs(qf.cpu().numpy() - np.array(ref_q)) / np.abs(ref_q))
+    say("picard iterations gpu", st["picard_iters"], "oracle", ref_its, "max rel err", err)
+    assert err <= (1e-9 if prec == 0 else 1e-6)
+    assert abs(st["picard_iters"] - ref_its) <= len(xi) * 16 // 4
+    p.close()
