@@ -578,8 +578,10 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     __syncthreads();
     // inner solves stop once the scaled residual guarantees the outer test:
     // ||b - A x|| <= D_max^{1/2} ||r_scaled|| (half the outer tolerance)
+    // (mixed precision only: FP64 inner solves run to inner_rtol, which keeps the
+    // FP64 path well below its outer tolerance)
     dmin = (double)__int_as_float(s_dmin) * 0.999;
-    floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
+    floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
     if constexpr (MG) {
       // Galerkin coarse operators A_l = P^T A_{l-1} P of the scaled system
       for (int l = 1; l <= mg.nlev; ++l) {
@@ -1626,7 +1628,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
     }
     __syncthreads();
     const double dmin = (double)__int_as_float(s_dmin) * 0.999;
-    const double floor_fac = 0.25 * sv.tol * sv.tol * dmin * dmin;
+    const double floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
     auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       return box ? tD[nr.t] : (VT)d_air;
