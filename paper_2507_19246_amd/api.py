@@ -11,7 +11,7 @@ from . import _lib as L
 # Solver defaults per precision: (outer FP64 tolerance on ||b - A d|| / ||b||,
 # inner CG relative tolerance, inner iteration cap, refinement sweep cap).
 SOLVER_DEFAULTS = {
-    L.MQ_PREC_FP64: dict(tol=1e-12, inner_rtol=1e-9, max_iter=20000, max_sweeps=10),
+    L.MQ_PREC_FP64: dict(tol=1e-13, inner_rtol=1e-10, max_iter=20000, max_sweeps=10),
     L.MQ_PREC_MIXED: dict(tol=1e-7, inner_rtol=1e-5, max_iter=20000, max_sweeps=10),
 }
 
