@@ -499,7 +499,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   const bool colok = ci < n;
   const bool strip_ok = colok && j0 < n;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 5 * FS;
+  double* Av = work + (size_t)blockIdx.x * ie_work_doubles(g);
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate, thread-private [k][tid] layout
@@ -1238,10 +1238,6 @@ int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_l
   return b <= (size_t)lds_limit ? 1 : 0;
 }
 
-size_t ie_work_doubles(const Geom& g) {
-  return 6 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
-}
-
 template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL>
 static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
                              int n_inst, int* counter, double* work, int max_grid, const double* S,
@@ -1568,7 +1564,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
   const int tid = threadIdx.x;
   const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
   const size_t FS = (size_t)g.N * g.P;
-  double* Av = work + (size_t)blockIdx.x * 5 * FS;
+  double* Av = work + (size_t)blockIdx.x * ie_work_doubles(g);
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   double* Xprev = Bv + 2 * FS;

@@ -38,6 +38,12 @@ struct Geom {
 // the sample's nonlinear curve coefficients k1', k2', k3' (and one pad).
 enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
 __host__ __device__ inline size_t tab_stride(const Geom& g) { return (size_t)T_NPLANES * g.RW * g.RH + 4; }
+// doubles per slot of the time-stepping work buffer: state a, increment x,
+// right-hand side b, one plane for the VT iterate, previous increment,
+// Picard increment, then the instance's FP64 tables (planes + k1', k2', k3')
+__host__ __device__ inline size_t ie_work_doubles(const Geom& g) {
+  return 6 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
+}
 
 // Element data over the cells that touch the box: full-grid cells
 // [bx0, bx1 + 1) x [by0, by1 + 1), two triangles per cell
@@ -128,7 +134,6 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);
 int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision);
-size_t ie_work_doubles(const Geom& g);
 size_t stream_vwork_elems(const Geom& g);
 
 }  // namespace mq
