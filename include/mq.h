@@ -209,19 +209,28 @@ int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const dou
                    const double* x, double* y);
 
 /* ---------------------------------------------------------------- serving
- * Continuous batching of independent sample solves (linear materials, mixed
- * meshes).  A request names its mesh (n_nodes), time grid and KL input.  The
- * server admits requests in arrival order while their device footprint fits
- * hbm_budget_bytes and fewer than max_inflight are running; admitted requests
- * are launched at once on one of its streams and overlap with those already
- * on the device; finished ones are reported by mq_poll. */
+ * Continuous batching of independent sample solves (the time integration of
+ * Section II-A for one KL input on its own mesh and time grid; linear
+ * materials).  The server has a scheduler thread of its own.  Requests are
+ * admitted in arrival order while the device memory they need fits
+ * hbm_budget_bytes and fewer than max_inflight are admitted; an admitted
+ * request keeps its tables, state and QoI on the device until it completes.
+ * Each mesh size has n_streams lanes (a HIP stream each); whenever a lane is
+ * idle, the next chunk_steps steps of every admitted request of its mesh size
+ * that is not running elsewhere go into one persistent launch on it, so
+ * requests that arrive while others run join the next launch and overlap on
+ * the device with those already running.  Launches split a request at fixed
+ * request-relative steps and resume it exactly, so its result is the same bit
+ * for bit whatever else the server runs, and equal to mlmc_level_run of the
+ * same input at level 0.  Device memory (per-mesh work buffers, request slots)
+ * is kept for reuse until mq_server_destroy and counts against the budget. */
 typedef struct mq_server_desc {
-  mq_problem_desc base;      /* material/precision/tolerances; n_nodes ignored */
-  int64_t hbm_budget_bytes;
-  int32_t max_inflight;
-  int32_t n_streams;
-  int32_t max_batch;         /* requests fused into one launch at most */
-  int32_t reserved;
+  mq_problem_desc base;      /* material/precision/tolerances; n_nodes ignored; linear */
+  int64_t hbm_budget_bytes;  /* > 0 */
+  int32_t max_inflight;      /* >= 1 admitted requests at most */
+  int32_t n_streams;         /* lanes per mesh size, 0..8 (0: 2) */
+  int32_t max_batch;         /* requests in one launch at most (0: 4096) */
+  int32_t chunk_steps;       /* steps per request per launch (0: 32) */
 } mq_server_desc;
 
 typedef struct mq_request {
@@ -232,22 +241,29 @@ typedef struct mq_request {
 
 typedef struct mq_result {
   uint64_t ticket, user_id;
-  double q;
-  int32_t status;            /* MQ_OK, MQ_WARN_NOT_CONVERGED or a negative error */
+  double q;                  /* Eq. (26) mean Joule loss over n_periods / freq */
+  int32_t status;            /* MQ_OK, MQ_WARN_NOT_CONVERGED, or an error: MQ_ERR_BUSY when the
+                                request alone does not fit the budget, MQ_ERR_NONFINITE when
+                                the solve produced NaN/Inf, MQ_ERR_DEVICE / _OUT_OF_MEMORY */
   int32_t inner_iters;
-  int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock ns */
+  int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock ns: mq_submit, first launch,
+                                                 QoI copied to the host */
 } mq_result;
 
 typedef struct mq_server mq_server;
+/* Create a server on the current device; stream is unused (the server owns its
+ * streams).  Errors: invalid limits or base description, nonlinear material. */
 int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out);
-/* Queue a request (host struct); *ticket identifies it in mq_poll.
- * MQ_ERR_BUSY if the request alone exceeds the HBM budget. */
+/* Queue a request (host struct, copied); *ticket identifies it in mq_poll.
+ * Validated at once (mesh size, steps, n_xi of the material, finite xi);
+ * callable from any thread. */
 int mq_submit(mq_server* s, const mq_request* rq, uint64_t* ticket);
-/* Launch what can be admitted, then copy up to cap finished results to out
- * (host) and set *n_out.  Non-blocking. */
+/* Copy up to cap finished results (host array) to out and set *n_out.
+ * Non-blocking; results come in completion order. */
 int mq_poll(mq_server* s, mq_result* out, int32_t cap, int32_t* n_out);
-/* Number of requests queued or running. */
+/* Number of requests queued or admitted and not yet finished. */
 int mq_server_pending(const mq_server* s, int32_t* n);
+/* Waits for the launches in flight, drops unfinished requests, frees everything. */
 int mq_server_destroy(mq_server* s);
 
 #ifdef __cplusplus

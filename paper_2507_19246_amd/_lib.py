@@ -84,7 +84,7 @@ class PararealDesc(C.Structure):
 
 class ServerDesc(C.Structure):
     _fields_ = [("base", ProblemDesc), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
-                ("n_streams", C.c_int32), ("max_batch", C.c_int32), ("reserved", C.c_int32)]
+                ("n_streams", C.c_int32), ("max_batch", C.c_int32), ("chunk_steps", C.c_int32)]
 
 
 class Request(C.Structure):

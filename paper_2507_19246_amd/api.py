@@ -172,7 +172,7 @@ class Server:
     """Continuous-batching request server (mq_server_*)."""
 
     def __init__(self, base_problem, precision: int, hbm_budget_bytes: int, max_inflight: int = 1024,
-                 n_streams: int = 4, max_batch: int = 64, **solver):
+                 n_streams: int = 2, max_batch: int = 0, chunk_steps: int = 0, **solver):
         self.lib = L.load()
         sd = L.ServerDesc()
         sd.base = default_desc(base_problem, precision, **solver)
@@ -180,6 +180,7 @@ class Server:
         sd.max_inflight = max_inflight
         sd.n_streams = n_streams
         sd.max_batch = max_batch
+        sd.chunk_steps = chunk_steps
         self.desc = sd
         h = C.c_void_p()
         L.check(self.lib.mq_server_create(C.byref(sd), _stream(), C.byref(h)))

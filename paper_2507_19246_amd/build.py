@@ -18,7 +18,7 @@ ARCH = os.environ.get("MQ_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip"]
 HOST_SOURCES = ["abi.cpp", "setup.cpp", "serve.cpp"]
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-mcode-object-version=5",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -62,7 +62,7 @@ def build(verbose: bool = False) -> str:
                 print(o)
     objs = [j[-1] for j in jobs]
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs])
+    _run([hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

@@ -11,75 +11,87 @@
 #include <string>
 #include <vector>
 
-#include "mq_internal.h"
-#include "setup.h"
+#include "problem.h"
 
 using namespace mq;
 
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
+namespace mq {
+std::string& last_error() {
+  thread_local std::string e;
+  return e;
 }
+}  // namespace mq
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e__ = (expr);                                                       \
-    if (e__ != hipSuccess)                                                         \
-      return fail(e__ == hipErrorOutOfMemory ? MQ_ERR_OUT_OF_MEMORY : MQ_ERR_DEVICE, \
-                  std::string(#expr) + ": " + hipGetErrorString(e__));             \
-  } while (0)
+namespace {
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device allocation owned by a unique_ptr.
-struct DevFree {
-  void operator()(void* p) const {
-    if (p) (void)hipFree(p);
-  }
-};
-template <class T>
-using DevPtr = std::unique_ptr<T, DevFree>;
-
-template <class T>
-hipError_t dev_alloc(DevPtr<T>& out, size_t count) {
-  T* p = nullptr;
-  hipError_t e = hipMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T));
-  if (e == hipSuccess) out.reset(p);
-  return e;
-}
-
 }  // namespace
 
-struct mq_problem {
-  mq_problem_desc d;
-  HostMesh hm;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int num_cu = 0;
-  int lds_limit = 0;
-  int n_xi = 0;
-  double wall_khz = 100000.0;
-  int resident_ok = 0;
-  int lds_bytes = 0;
-  int path = MQ_PATH_STREAMING;
-  int precond = MQ_PRECOND_JACOBI;
-  MGGeom mg{};
-  double mat[10];
-  DevPtr<double> dS;
-  DevPtr<uint8_t> dcond;
-  DevPtr<double> dkl;
-  DevPtr<int> dcounter;
-  DevPtr<int> dflag;
-  // per-slot work buffers (grown on demand, zeroed when allocated)
-  DevPtr<double> work;
-  size_t work_slots = 0;
-};
+namespace mq {
+
+Solver solver_of(const mq_problem* p) {
+  Solver sv;
+  sv.precond = p->precond == MQ_PRECOND_MULTIGRID ? 1 : 0;
+  sv.mg_omega = p->d.mg_omega > 0 ? p->d.mg_omega : 0.8;
+  sv.precision = p->d.precision;
+  sv.tol = p->d.tol;
+  sv.inner_rtol = p->d.inner_rtol;
+  sv.max_iter = p->d.max_iter;
+  sv.max_sweeps = p->d.max_sweeps;
+  sv.nonlinear = p->d.material == MQ_MAT_NONLINEAR;
+  sv.picard_tol = p->d.picard_tol;
+  sv.picard_max = p->d.picard_max;
+  return sv;
+}
+
+size_t slot_doubles(const Geom& g) {
+  // FP64 slot planes + the streaming path's vector workspace (8-byte upper bound)
+  return ie_work_doubles(g) + stream_vwork_elems(g);
+}
+
+int ensure_work(mq_problem* p, size_t slots) {
+  if (p->work_slots >= slots) return MQ_OK;
+  p->work.reset();
+  p->work_slots = 0;
+  const size_t nd = slots * slot_doubles(p->hm.g);
+  HIP_TRY(dev_alloc(p->work, nd));
+  HIP_TRY(launch_fill_zero(p->work.get(), nd, p->stream));
+  p->work_slots = slots;
+  return MQ_OK;
+}
+
+size_t work_bytes(const mq_problem* p, size_t slots) { return slots * slot_doubles(p->hm.g) * sizeof(double); }
+
+size_t max_slots(const mq_problem* p) {
+  const int per_cu = ie_slots_per_cu(p->hm.g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision);
+  return (size_t)p->num_cu * per_cu;
+}
+
+int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block) {
+  const size_t slots = std::min<size_t>((size_t)n, max_slots(p));
+  if (p->work_slots < slots) return fail(MQ_ERR_INVALID_ARG, "work buffer smaller than the launch");
+  HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
+  const Solver sv = solver_of(p);
+  // the slot layout of the work buffer is fixed by its allocation (work_slots);
+  // the grid is the occupancy-limited slot count
+  hipError_t le = launch_ie(p->hm.g, p->mg, sv, dinst, n, p->dcounter.get(), p->work.get(), (int)p->work_slots,
+                            (int)slots, p->dS.get(), p->path, p->d.precision, p->hm.cr, p->dcond.get(), p->mat,
+                            grid, block, p->stream);
+  if (le != hipSuccess) return fail(MQ_ERR_DEVICE, std::string("time-stepping launch: ") + hipGetErrorString(le));
+  return MQ_OK;
+}
+
+// J(t_k) = J0 sin(2 pi f k dt), k = 0..n_total (FP64 on the host).
+std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_total) {
+  std::vector<double> s(n_total + 1);
+  for (int k = 0; k <= n_total; ++k) s[k] = d.J0 * std::sin(2.0 * M_PI * d.freq * (k * dt));
+  return s;
+}
+
+}  // namespace mq
 
 namespace {
 
@@ -114,21 +126,6 @@ int validate_desc(const mq_problem_desc* d) {
   return MQ_OK;
 }
 
-Solver solver_of(const mq_problem* p) {
-  Solver sv;
-  sv.precond = p->precond == MQ_PRECOND_MULTIGRID ? 1 : 0;
-  sv.mg_omega = p->d.mg_omega > 0 ? p->d.mg_omega : 0.8;
-  sv.precision = p->d.precision;
-  sv.tol = p->d.tol;
-  sv.inner_rtol = p->d.inner_rtol;
-  sv.max_iter = p->d.max_iter;
-  sv.max_sweeps = p->d.max_sweeps;
-  sv.nonlinear = p->d.material == MQ_MAT_NONLINEAR;
-  sv.picard_tol = p->d.picard_tol;
-  sv.picard_max = p->d.picard_max;
-  return sv;
-}
-
 int check_finite(mq_problem* p, const double* x, size_t n) {
   HIP_TRY(launch_fill_zero_i(p->dflag.get(), 1, p->stream));
   HIP_TRY(launch_check_finite(x, n, p->dflag.get(), p->stream));
@@ -137,29 +134,6 @@ int check_finite(mq_problem* p, const double* x, size_t n) {
   HIP_TRY(hipStreamSynchronize(p->stream));
   if (bad) return fail(MQ_ERR_NONFINITE, "xi contains NaN or Inf");
   return MQ_OK;
-}
-
-size_t slot_doubles(const Geom& g) {
-  // FP64 state (3 full grids) + the streaming path's vector workspace (8-byte upper bound)
-  return ie_work_doubles(g) + stream_vwork_elems(g);
-}
-
-int ensure_work(mq_problem* p, size_t slots) {
-  if (p->work_slots >= slots) return MQ_OK;
-  p->work.reset();
-  p->work_slots = 0;
-  const size_t nd = slots * slot_doubles(p->hm.g);
-  HIP_TRY(dev_alloc(p->work, nd));
-  HIP_TRY(launch_fill_zero(p->work.get(), nd, p->stream));
-  p->work_slots = slots;
-  return MQ_OK;
-}
-
-// J(t_k) = J0 sin(2 pi f k dt), k = 0..n_total (FP64 on the host).
-std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_total) {
-  std::vector<double> s(n_total + 1);
-  for (int k = 0; k <= n_total; ++k) s[k] = d.J0 * std::sin(2.0 * M_PI * d.freq * (k * dt));
-  return s;
 }
 
 struct RunOut {
@@ -180,26 +154,18 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   DevPtr<Inst> dinst;
   HIP_TRY(dev_alloc(dinst, n));
   HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
-  const Geom& g = p->hm.g;
-  const int per_cu = ie_slots_per_cu(g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision);
-  const size_t slots = std::min<size_t>((size_t)n, (size_t)p->num_cu * per_cu);
+  const size_t slots = std::min<size_t>((size_t)n, max_slots(p));
   int rc = ensure_work(p, slots);
   if (rc) return rc;
-  HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  Solver sv = solver_of(p);
   HIP_TRY(hipEventRecord(e0, p->stream));
-  // the slot layout of the work buffer is fixed by its allocation (work_slots);
-  // the grid is the occupancy-limited slot count
-  hipError_t le = launch_ie(g, p->mg, sv, dinst.get(), n, p->dcounter.get(), p->work.get(), (int)p->work_slots, (int)slots,
-                            p->dS.get(), p->path, p->d.precision, p->hm.cr, p->dcond.get(), p->mat,
-                            &ro->grid, &ro->block, p->stream);
-  if (le != hipSuccess) {
+  rc = launch_persistent(p, dinst.get(), n, &ro->grid, &ro->block);
+  if (rc) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return fail(MQ_ERR_DEVICE, std::string("time-stepping launch: ") + hipGetErrorString(le));
+    return rc;
   }
   HIP_TRY(hipEventRecord(e1, p->stream));
   std::vector<int> sh((size_t)n * STAT_N);
@@ -317,7 +283,6 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
     lb.afull_ptr.resize(n);
     for (int s = 0; s < n; ++s) lb.afull_ptr[s] = lb.afull.get() + FS * s;
   }
-  const size_t RHW = (size_t)g.RW * g.RH;
   for (int s = 0; s < n; ++s) {
     Inst in{};
     in.tab = lb.tables.get() + (size_t)s * tab_stride(g);
@@ -347,7 +312,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
 
 extern "C" {
 
-const char* mq_last_error(void) { return g_err.c_str(); }
+const char* mq_last_error(void) { return last_error().c_str(); }
 
 int mq_version(void) { return 1; }
 
@@ -514,7 +479,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
   int rc = check_finite(p, xi, (size_t)n_samples * p->n_xi);
   if (rc) return rc;
   const Geom& g = p->hm.g;
-  const size_t FS = (size_t)g.N * g.P, RHW = (size_t)g.RW * g.RH;
+  const size_t FS = (size_t)g.N * g.P;
   DevPtr<double> tables;
   rc = assemble(p, xi, n_samples, tables);
   if (rc) return rc;
@@ -675,7 +640,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
   }
   if (st) st->total_ms = now_ms() - t_start;
   if (warn) {
-    g_err = "Parareal reached k_max above the tolerance for some samples";
+    last_error() = "Parareal reached k_max above the tolerance for some samples";
     return MQ_WARN_NOT_CONVERGED;
   }
   return ro.status;

@@ -635,8 +635,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       if (ACT(k)) {
         const int gi = gi0 + k * g.P;
         Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
-        Xv[gi] = 0.0;
-        Pv[gi] = 0.0;
+        Xv[gi] = in.carry_in ? in.carry[gi] : 0.0;
+        Pv[gi] = in.carry_in ? in.carry[FS + gi] : 0.0;
         Qv[gi] = 0.0;
       }
     }
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       return (double)vt<VT>(1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]));
     };
 
-    double qsum = 0.0;
+    double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0, pic_total = 0;
     // per-phase device wall-clock ticks (thread 0): fine V-cycle descent,
     // coarse levels, fine ascent, CG apply + reductions
@@ -1112,6 +1112,17 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
 #pragma unroll 1
       for (int k = 0; k < SH; ++k)
         if (ACT(k)) in.a_out[gi0 + k * g.P] = Av[gi0 + k * g.P];
+    }
+    if (in.carry) {
+#pragma unroll 1
+      for (int k = 0; k < SH; ++k) {
+        if (ACT(k)) {
+          const int gi = gi0 + k * g.P;
+          in.carry[gi] = Xv[gi];
+          in.carry[FS + gi] = Pv[gi];
+        }
+      }
+      if (tid == 0) in.carry[2 * FS] = qsum;
     }
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;
@@ -1619,8 +1630,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
     for (int idx = tid; idx < nd; idx += NT) {
       const int gi = (idx / n + 1) * g.P + idx % n + 1;
       Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
-      Xv[gi] = 0.0;
-      Xprev[gi] = 0.0;
+      Xv[gi] = in.carry_in ? in.carry[gi] : 0.0;
+      Xprev[gi] = in.carry_in ? in.carry[FS + gi] : 0.0;
     }
     __syncthreads();
     const double dmin = (double)__int_as_float(s_dmin) * 0.999;
@@ -1630,7 +1641,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
       return box ? tD[nr.t] : (VT)d_air;
     };
 
-    double qsum = 0.0;
+    double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
     const int n_seg = in.n_chain > 0 ? in.n_chain : 1;
     for (int seg = 0; seg < n_seg; ++seg) {
@@ -1769,6 +1780,14 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
         const int gi = (idx / n + 1) * g.P + idx % n + 1;
         in.a_out[gi] = Av[gi];
       }
+    }
+    if (in.carry) {
+      for (int idx = tid; idx < nd; idx += NT) {
+        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        in.carry[gi] = Xv[gi];
+        in.carry[FS + gi] = Xprev[gi];
+      }
+      if (tid == 0) in.carry[2 * FS] = qsum;
     }
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;

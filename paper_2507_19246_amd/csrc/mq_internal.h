@@ -76,6 +76,12 @@ struct Inst {
   double* const* chain_c;       // C_old_n coarse values (in/out)
   int sample;                   // sample index (nonlinear coefficients)
   int group;                    // latency group (host bookkeeping: one per sample)
+  // Resumable runs (null: none): full-grid start of the next increment solve,
+  // [0, FS); previous increment, [FS, 2 FS); unscaled running QoI sum, [2 FS].
+  // Written at the end of the launch; read at its start when carry_in != 0,
+  // so a run split into launches at any step gives the unsplit result bit for bit.
+  double* carry;
+  int carry_in;
 };
 
 // Geometric multigrid hierarchy of the resident path (fine interior n = 2^k - 1;

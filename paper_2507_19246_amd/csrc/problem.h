@@ -1,0 +1,91 @@
+// Internal: the problem handle and the host helpers shared by the C ABI
+// (abi.cpp) and the request server (serve.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mq_internal.h"
+#include "setup.h"
+
+namespace mq {
+
+// Message of the last non-zero status on the calling thread.
+std::string& last_error();
+
+inline int fail(int code, const std::string& msg) {
+  last_error() = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e__ = (expr);                                                       \
+    if (e__ != hipSuccess)                                                         \
+      return ::mq::fail(e__ == hipErrorOutOfMemory ? MQ_ERR_OUT_OF_MEMORY : MQ_ERR_DEVICE, \
+                        std::string(#expr) + ": " + hipGetErrorString(e__));       \
+  } while (0)
+
+// Device allocation owned by a unique_ptr.
+struct DevFree {
+  void operator()(void* p) const {
+    if (p) (void)hipFree(p);
+  }
+};
+template <class T>
+using DevPtr = std::unique_ptr<T, DevFree>;
+
+template <class T>
+hipError_t dev_alloc(DevPtr<T>& out, size_t count) {
+  T* p = nullptr;
+  hipError_t e = hipMalloc((void**)&p, (count > 0 ? count : 1) * sizeof(T));
+  if (e == hipSuccess) out.reset(p);
+  return e;
+}
+
+}  // namespace mq
+
+struct mq_problem {
+  mq_problem_desc d;
+  mq::HostMesh hm;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  int lds_limit = 0;
+  int n_xi = 0;
+  double wall_khz = 100000.0;
+  int resident_ok = 0;
+  int lds_bytes = 0;
+  int path = MQ_PATH_STREAMING;
+  int precond = MQ_PRECOND_JACOBI;
+  mq::MGGeom mg{};
+  double mat[10];
+  mq::DevPtr<double> dS;
+  mq::DevPtr<uint8_t> dcond;
+  mq::DevPtr<double> dkl;
+  mq::DevPtr<int> dcounter;
+  mq::DevPtr<int> dflag;
+  // per-slot work buffers (grown on demand, zeroed when allocated)
+  mq::DevPtr<double> work;
+  size_t work_slots = 0;
+};
+
+namespace mq {
+
+Solver solver_of(const mq_problem* p);
+// Persistent-kernel slots the device holds at once for this problem.
+size_t max_slots(const mq_problem* p);
+// Grow the work buffer to `slots` slots (allocation; call while the stream is idle).
+int ensure_work(mq_problem* p, size_t slots);
+// Device bytes of `slots` work slots.
+size_t work_bytes(const mq_problem* p, size_t slots);
+// J(t_k) = J0 sin(2 pi f k dt), k = 0..n_total (FP64 on the host).
+std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_total);
+// Launch one persistent time-stepping kernel over the device instance table
+// `dinst` on p->stream without waiting.  The work buffer must already hold
+// min(n, max_slots(p)) slots.
+int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block);
+
+}  // namespace mq
