@@ -41,7 +41,7 @@ class ProblemDesc(C.Structure):
         ("picard_tol", C.c_double),
         ("tol", C.c_double), ("inner_rtol", C.c_double),
         ("max_iter", C.c_int32), ("max_sweeps", C.c_int32),
-        ("precond", C.c_int32), ("reserved0", C.c_int32), ("mg_omega", C.c_double),
+        ("precond", C.c_int32), ("tile", C.c_int32), ("mg_omega", C.c_double),
     ]
 
 
@@ -51,6 +51,7 @@ class ProblemInfo(C.Structure):
         ("box", C.c_int32 * 4), ("resident_ok", C.c_int32), ("lds_bytes", C.c_int32),
         ("precond", C.c_int32), ("mg_levels", C.c_int32),
         ("n_modes_used", C.c_int32), ("kl_lambda", C.c_double * 16),
+        ("tile", C.c_int32), ("block", C.c_int32),
     ]
 
 

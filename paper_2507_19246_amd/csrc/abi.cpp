@@ -44,6 +44,7 @@ Solver solver_of(const mq_problem* p) {
   sv.nonlinear = p->d.material == MQ_MAT_NONLINEAR;
   sv.picard_tol = p->d.picard_tol;
   sv.picard_max = p->d.picard_max;
+  sv.tile = p->tile;
   return sv;
 }
 
@@ -66,7 +67,7 @@ int ensure_work(mq_problem* p, size_t slots) {
 size_t work_bytes(const mq_problem* p, size_t slots) { return slots * slot_doubles(p->hm.g) * sizeof(double); }
 
 size_t max_slots(const mq_problem* p) {
-  const int per_cu = ie_slots_per_cu(p->hm.g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision);
+  const int per_cu = ie_slots_per_cu(p->hm.g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision, p->tile);
   return (size_t)p->num_cu * per_cu;
 }
 
@@ -123,6 +124,7 @@ int validate_desc(const mq_problem_desc* d) {
     return fail(MQ_ERR_INVALID_ARG, "bad Picard parameters");
   if (d->precond < 0 || d->precond > 2) return fail(MQ_ERR_INVALID_ARG, "unknown preconditioner");
   if (!(d->mg_omega >= 0) || !(d->mg_omega < 1)) return fail(MQ_ERR_INVALID_ARG, "mg_omega must be in [0, 1)");
+  if (d->tile < 0 || d->tile > 2) return fail(MQ_ERR_INVALID_ARG, "tile must be 0, 1 or 2");
   return MQ_OK;
 }
 
@@ -344,15 +346,16 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
     p->wall_khz = wk;
   p->n_xi = n_xi_of(*d);
   // multigrid hierarchy (resident path only); fall back to Jacobi if it does not fit
-  const int lp = p->hm.g.n <= 31 ? 34 : (p->hm.g.n <= 63 ? 66 : 130);
-  const bool want_mg = d->precond != MQ_PRECOND_JACOBI && d->path != MQ_PATH_STREAMING;
+  p->tile = d->tile > 0 ? d->tile : 1;
+  const int lp = resident_lp(p->hm.g, p->tile);
+  const bool want_mg = d->precond != MQ_PRECOND_JACOBI && d->path != MQ_PATH_STREAMING && lp > 0;
   bool have_mg = want_mg && build_mg(p->hm.g, lp, &p->mg);
-  if (have_mg && !resident_supported(p->hm.g, &p->mg, d->precision, p->lds_limit, nullptr)) have_mg = false;
+  if (have_mg && !resident_supported(p->hm.g, &p->mg, d->precision, p->lds_limit, nullptr, p->tile)) have_mg = false;
   if (d->precond == MQ_PRECOND_MULTIGRID && !have_mg)
     return fail(MQ_ERR_INVALID_ARG, "multigrid needs the resident path and n_nodes = 2^k + 1");
   if (!have_mg) p->mg.nlev = 0;
   p->precond = have_mg ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
-  p->resident_ok = resident_supported(p->hm.g, have_mg ? &p->mg : nullptr, d->precision, p->lds_limit, &p->lds_bytes);
+  p->resident_ok = resident_supported(p->hm.g, have_mg ? &p->mg : nullptr, d->precision, p->lds_limit, &p->lds_bytes, p->tile);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
     return fail(MQ_ERR_INVALID_ARG, "the resident path does not fit this mesh/precision");
   if (d->material == MQ_MAT_NONLINEAR && (!p->resident_ok || d->path == MQ_PATH_STREAMING))
@@ -408,6 +411,8 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   info->mg_levels = p->path == MQ_PATH_RESIDENT ? p->mg.nlev : 0;
   info->n_modes_used = p->hm.n_modes;
   for (int k = 0; k < p->hm.n_modes && k < 16; ++k) info->kl_lambda[k] = p->hm.kl_lambda[k];
+  info->tile = p->path == MQ_PATH_RESIDENT ? p->tile : 0;
+  info->block = ie_block_threads(p->hm.g, p->path, p->tile);
   return MQ_OK;
 }
 

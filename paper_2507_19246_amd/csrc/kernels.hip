@@ -481,6 +481,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   constexpr int NT = CW * NS;
   constexpr int NWAVES = NT / 64;
   constexpr int LP = CW + 2;
+  constexpr int CR = SH / 4;  // first-coarse-level rows per thread in the restriction
   extern __shared__ double smem_d[];
   const int n = g.n, RHW = g.RW * g.RH, TRH = g.RH * TP;
   double* red = smem_d;                                  // 2 * NWAVES * 4 doubles
@@ -495,7 +496,10 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
 
   const int tid = threadIdx.x;
   const int ci = tid % CW;
-  const int j0 = (tid / CW) * SH;
+  // a wave lies in one row slice when CW is a multiple of 64: the slice index is
+  // then wave-uniform, and so is every per-row test below (scalar branches)
+  const int slice = CW % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / CW) : tid / CW;
+  int j0 = slice * SH;
   const bool colok = ci < n;
   const bool strip_ok = colok && j0 < n;
   const size_t FS = (size_t)g.N * g.P;
@@ -512,8 +516,17 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   // node k of this thread is row j0 + k of column ci; indices are affine in k
   const int gi0 = (j0 + 1) * g.P + ci + 1;
   const int t0 = (j0 - g.by0 + 1) * g.RW + (ci - g.bx0 + 1);  // FP64 tables (pitch RW)
-  const int s0 = (j0 - g.by0 + 1) * TP + (ci - g.bx0 + 1);    // LDS tables (pitch TP)
-  const int l0 = (j0 + 1) * LP + ci + 1;
+  int s0 = (j0 - g.by0 + 1) * TP + (ci - g.bx0 + 1);    // LDS tables (pitch TP)
+  int l0 = (j0 + 1) * LP + ci + 1;
+  // Called at the top of each inner iteration: the row index and the LDS bases
+  // become opaque there, so the per-row tests and offsets derived from them are
+  // recomputed in the iteration (a few scalar operations) instead of being kept
+  // live across the whole loop, which exhausts the scalar register file.
+  auto refresh = [&]() __attribute__((always_inline)) {
+    if constexpr (CW % 64 == 0) asm volatile("" : "+s"(j0));
+    else asm volatile("" : "+v"(j0));
+    asm volatile("" : "+v"(l0), "+v"(s0));
+  };
   const bool col_L = ci >= g.bx0 && ci < g.lx1;
   const bool col_box = ci >= g.bx0 && ci < g.bx1;
   auto ACT = [&](int k) { return colok && (j0 + k) < n; };
@@ -839,9 +852,9 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 const CLev<VT> L1 = clev<VT>(mg, 1, rl, ctab, NT);
                 const int n1 = L1.n;
                 const int tx1 = tid & ((1 << L1.txs) - 1), ty1 = NT >> L1.txs, jb1 = tid >> L1.txs;
-                VT rc[4];
+                VT rc[CR];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
+                for (int m = 0; m < CR; ++m) {
                   const int j = jb1 + m * ty1;
                   rc[m] = (tx1 < n1 && j < n1) ? restrict_at(rl, LP, tx1, j) : VT(0);
                   __builtin_amdgcn_sched_barrier(0);
@@ -850,7 +863,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, rl, ctab, NT), tid, NT);
                 const bool exact1 = mg.nlev == 1;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
+                for (int m = 0; m < CR; ++m) {
                   const int j = jb1 + m * ty1;
                   if (tx1 < n1 && j < n1) {
                     const int q = (j + 1) * L1.np + tx1 + 1;
@@ -896,6 +909,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               double rho = 1.0, stop = 0.0;
               int it = 0;
               for (;;) {
+                refresh();
                 vcycle(r, z);
                 double rz[2];
                 {
@@ -964,6 +978,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
             double gam_prev = 1.0, alpha = 1.0, stop = 0.0;
             int it = 0;
             for (;; ++it) {
+              refresh();
               double gv[1];
               {
                 VT pg = VT(0);
@@ -1219,30 +1234,46 @@ static size_t resident_lds(const Geom& g, const ResCfg& c, const MGGeom* mg) {
   return 2 * nw * 4 * sizeof(double) + (region + 3 * (size_t)g.RH * c.tp + ctab) * sizeof(VT);
 }
 
-static bool pick_resident(const Geom& g, ResCfg* c) {
+// Resident tile: CW columns (one per thread of a slice), NS slices of SH rows.
+// tile 1: 16 rows per thread; tile 2 (meshes of 64..127 interior nodes per
+// side): 32 rows per thread in 512-thread workgroups, which leaves 256
+// registers per lane instead of 128.
+static bool pick_resident(const Geom& g, int tile, ResCfg* c) {
   if (g.n <= 31) {
     *c = {32, 16, 2, 32};
   } else if (g.n <= 63) {
     *c = {64, 16, 4, 64};
   } else if (g.n <= 127) {
-    *c = {128, 16, 8, 64};
+    *c = tile == 2 ? ResCfg{128, 32, 4, 64} : ResCfg{128, 16, 8, 64};
   } else {
     return false;
   }
   return g.n <= c->sh * c->ns && g.RW <= c->tp;
 }
 
-int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes) {
+int ie_block_threads(const Geom& g, int path, int tile) {
   ResCfg c;
-  if (!pick_resident(g, &c)) return 0;
+  if (path == MQ_PATH_RESIDENT && pick_resident(g, tile, &c)) return c.cw * c.ns;
+  return 1024;
+}
+
+int resident_lp(const Geom& g, int tile) {
+  ResCfg c;
+  if (!pick_resident(g, tile, &c)) return 0;
+  return c.cw + 2;
+}
+
+int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes, int tile) {
+  ResCfg c;
+  if (!pick_resident(g, tile, &c)) return 0;
   // 1024-thread FP64 workgroups would need more than 128 VGPRs per lane
   if (precision == MQ_PREC_FP64 && c.cw * c.ns > 256) return 0;
-  // the restriction to the first coarse level keeps 4 coarse rows per thread
+  // the restriction to the first coarse level keeps SH/4 coarse rows per thread
   if (mg && mg->nlev > 0) {
     int tx = 1;
     while (tx < mg->lv[1].n && 2 * tx <= c.cw * c.ns) tx *= 2;
     const int ty = c.cw * c.ns / tx;
-    if ((mg->lv[1].n + ty - 1) / ty > 4) return 0;
+    if ((mg->lv[1].n + ty - 1) / ty > c.sh / 4) return 0;
   }
   size_t b = precision == MQ_PREC_FP64 ? resident_lds<double>(g, c, mg) : resident_lds<float>(g, c, mg);
   if (lds_bytes) *lds_bytes = (int)b;
@@ -1273,9 +1304,10 @@ static hipError_t dispatch_res(const Geom& g, const MGGeom& mg, const Solver& sv
                                const uint8_t* cond, const CellRegion& cr,
                                int* grid_out, int* block_out, hipStream_t st) {
   ResCfg c;
-  if (!pick_resident(g, &c)) return hipErrorInvalidValue;
+  if (!pick_resident(g, sv.tile, &c)) return hipErrorInvalidValue;
   if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
   if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  if (c.sh == 32) return launch_res<VT, 128, 32, 4, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
   return launch_res<VT, 128, 16, 8, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
 }
 
@@ -1287,14 +1319,15 @@ static int occupancy_res(const Geom& g, const MGGeom* mg, const ResCfg& c) {
   hipError_t e;
   if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG, false>, nt, lds);
   else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG, false>, nt, lds);
+  else if (c.sh == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 32, 4, 64, MG, false>, nt, lds);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG, false>, nt, lds);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
-int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision) {
+int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision, int tile) {
   ResCfg c;
-  if (path == MQ_PATH_RESIDENT && pick_resident(g, &c)) {
+  if (path == MQ_PATH_RESIDENT && pick_resident(g, tile, &c)) {
     const bool usemg = mg && mg->nlev > 0;
     if (precision == MQ_PREC_FP64)
       return usemg ? occupancy_res<double, true>(g, mg, c) : occupancy_res<double, false>(g, mg, c);

@@ -111,13 +111,17 @@ struct Solver {
   int nonlinear;
   double picard_tol;
   int picard_max;
+  int tile;        // resident workgroup shape (host-side dispatch)
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
 enum { STAT_N = 13 };
 
 // Launch helpers implemented in the .hip translation units.
-int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes);
+// tile: resident workgroup shape (1: 16 rows per thread, 2: 32 rows per thread)
+int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes, int tile);
+int resident_lp(const Geom& g, int tile);
+int ie_block_threads(const Geom& g, int path, int tile);
 hipError_t launch_assemble(const Geom& g, const CellRegion& cr, const uint8_t* cond,
                            const double* kltab, int n_modes, int material, const double* xi,
                            int n_xi, int n_samples, const double* mat_params, double* tables,
@@ -139,7 +143,7 @@ hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);
-int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision);
+int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision, int tile);
 size_t stream_vwork_elems(const Geom& g);
 
 }  // namespace mq

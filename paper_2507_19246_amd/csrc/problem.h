@@ -60,6 +60,7 @@ struct mq_problem {
   int lds_bytes = 0;
   int path = MQ_PATH_STREAMING;
   int precond = MQ_PRECOND_JACOBI;
+  int tile = 1;
   mq::MGGeom mg{};
   double mat[10];
   mq::DevPtr<double> dS;

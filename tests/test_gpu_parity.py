@@ -92,17 +92,21 @@ def test_plain_fp64_33_full_parity(pc):
     p.close()
 
 
-@pytest.mark.parametrize("n,path,pc", [(33, 1, 1), (33, 1, 2), (33, 2, 1), (65, 1, 1), (65, 1, 2),
-                                       (65, 2, 1), (129, 1, 2)])
-def test_mixed_kl_coupled_level(n, path, pc):
+@pytest.mark.parametrize("n,path,pc,tile", [(33, 1, 1, 0), (33, 1, 2, 0), (33, 2, 1, 0), (65, 1, 1, 0),
+                                            (65, 1, 2, 0), (65, 2, 1, 0), (129, 1, 2, 1), (129, 1, 2, 2),
+                                            (129, 1, 1, 2)])
+def test_mixed_kl_coupled_level(n, path, pc, tile):
     """Mixed precision, KL field, coupled fine/coarse run: Q within 1e-6
-    (resident/streaming path, Jacobi/multigrid preconditioner)."""
+    (resident/streaming path, Jacobi/multigrid preconditioner, both resident
+    workgroup shapes at 129 x 129)."""
     mq, L = mqmod()
     prob = W.Problem(n, W.Material(kind=W.MAT_KL))
     xi = W.normals(0, 21, 1, range(6 if n < 129 else 3), 8)
-    say(f"mixed kl n={n} path={path} precond={pc}")
-    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path, precond=pc)
+    say(f"mixed kl n={n} path={path} precond={pc} tile={tile}")
+    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path, precond=pc, tile=tile)
     assert p.info.precond == pc
+    if tile:
+        assert p.info.tile == tile and p.info.block == (1024 if tile == 1 else 512)
     qf, qc, _, rc, st = mq.mlmc_level_run(p, 32, 16, 2, xi)
     assert rc == 0
     say("stats", st)
