@@ -100,7 +100,8 @@ typedef struct mq_problem_desc {
   double k1, k2, k3, s_k, picard_tol;
   double tol, inner_rtol;
   int32_t max_iter, max_sweeps;
-  int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available, else Jacobi */
+  int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available (n_nodes = 2^k + 1; on the
+                        resident path if its LDS holds the hierarchy), else Jacobi */
   int32_t tile;      /* resident workgroup shape: 0 auto (the built-in default, 1), 1 = 16 rows per
                         thread, 2 = 32 rows per thread in 512-thread workgroups (meshes with 64..127
                         interior nodes per side; others use 1) */

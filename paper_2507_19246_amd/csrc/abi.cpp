@@ -48,23 +48,24 @@ Solver solver_of(const mq_problem* p) {
   return sv;
 }
 
-size_t slot_doubles(const Geom& g) {
+size_t slot_doubles(const mq_problem* p) {
   // FP64 slot planes + the streaming path's vector workspace (8-byte upper bound)
-  return ie_work_doubles(g) + stream_vwork_elems(g);
+  const bool smg = p->path == MQ_PATH_STREAMING && p->mg.nlev > 0;
+  return ie_work_doubles(p->hm.g) + stream_vwork_elems(p->hm.g, smg ? &p->mg : nullptr);
 }
 
 int ensure_work(mq_problem* p, size_t slots) {
   if (p->work_slots >= slots) return MQ_OK;
   p->work.reset();
   p->work_slots = 0;
-  const size_t nd = slots * slot_doubles(p->hm.g);
+  const size_t nd = slots * slot_doubles(p);
   HIP_TRY(dev_alloc(p->work, nd));
   HIP_TRY(launch_fill_zero(p->work.get(), nd, p->stream));
   p->work_slots = slots;
   return MQ_OK;
 }
 
-size_t work_bytes(const mq_problem* p, size_t slots) { return slots * slot_doubles(p->hm.g) * sizeof(double); }
+size_t work_bytes(const mq_problem* p, size_t slots) { return slots * slot_doubles(p) * sizeof(double); }
 
 size_t max_slots(const mq_problem* p) {
   const int per_cu = ie_slots_per_cu(p->hm.g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision, p->tile);
@@ -346,21 +347,31 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
     p->wall_khz = wk;
   p->n_xi = n_xi_of(*d);
   // multigrid hierarchy (resident path only); fall back to Jacobi if it does not fit
+  // path and preconditioner: the resident path (with multigrid if its LDS
+  // holds the hierarchy, else Jacobi) where it fits, else the streaming path
+  // (with multigrid on 2^k + 1 meshes)
   p->tile = d->tile > 0 ? d->tile : 1;
-  const int lp = resident_lp(p->hm.g, p->tile);
-  const bool want_mg = d->precond != MQ_PRECOND_JACOBI && d->path != MQ_PATH_STREAMING && lp > 0;
-  bool have_mg = want_mg && build_mg(p->hm.g, lp, &p->mg);
-  if (have_mg && !resident_supported(p->hm.g, &p->mg, d->precision, p->lds_limit, nullptr, p->tile)) have_mg = false;
-  if (d->precond == MQ_PRECOND_MULTIGRID && !have_mg)
-    return fail(MQ_ERR_INVALID_ARG, "multigrid needs the resident path and n_nodes = 2^k + 1");
-  if (!have_mg) p->mg.nlev = 0;
-  p->precond = have_mg ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
-  p->resident_ok = resident_supported(p->hm.g, have_mg ? &p->mg : nullptr, d->precision, p->lds_limit, &p->lds_bytes, p->tile);
+  const Geom& g0 = p->hm.g;
+  const bool want_mg = d->precond != MQ_PRECOND_JACOBI;
+  const int lp = resident_lp(g0, p->tile);
+  MGGeom rmg{};
+  const bool res_mg = want_mg && lp > 0 && d->path != MQ_PATH_STREAMING && build_mg(g0, lp, &rmg) &&
+                      resident_supported(g0, &rmg, d->precision, p->lds_limit, nullptr, p->tile);
+  p->resident_ok = resident_supported(g0, res_mg ? &rmg : nullptr, d->precision, p->lds_limit, &p->lds_bytes, p->tile);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
     return fail(MQ_ERR_INVALID_ARG, "the resident path does not fit this mesh/precision");
   if (d->material == MQ_MAT_NONLINEAR && (!p->resident_ok || d->path == MQ_PATH_STREAMING))
     return fail(MQ_ERR_INVALID_ARG, "the nonlinear (Picard) material runs on the resident path only");
   p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
+  p->mg = MGGeom{};
+  if (p->path == MQ_PATH_RESIDENT) {
+    if (res_mg) p->mg = rmg;
+  } else if (want_mg && !build_mg(g0, 0, &p->mg)) {
+    p->mg = MGGeom{};
+  }
+  if (d->precond == MQ_PRECOND_MULTIGRID && p->mg.nlev == 0)
+    return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS)");
+  p->precond = p->mg.nlev > 0 ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
   const double m[10] = {d->sigma0, d->nu_cond, d->nu_air, d->s_sigma, d->s_nu, d->s_kl, d->k1, d->k2, d->k3, d->s_k};
   std::memcpy(p->mat, m, sizeof(m));
   const Geom& g = p->hm.g;
@@ -407,8 +418,8 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   info->box[3] = g.by1;
   info->resident_ok = p->resident_ok;
   info->lds_bytes = p->lds_bytes;
-  info->precond = p->path == MQ_PATH_RESIDENT ? p->precond : MQ_PRECOND_JACOBI;
-  info->mg_levels = p->path == MQ_PATH_RESIDENT ? p->mg.nlev : 0;
+  info->precond = p->precond;
+  info->mg_levels = p->mg.nlev;
   info->n_modes_used = p->hm.n_modes;
   for (int k = 0; k < p->hm.n_modes && k < 16; ++k) info->kl_lambda[k] = p->hm.kl_lambda[k];
   info->tile = p->path == MQ_PATH_RESIDENT ? p->tile : 0;

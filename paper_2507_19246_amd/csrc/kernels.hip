@@ -243,17 +243,24 @@ __device__ inline VT vt(double x) { return (VT)x; }
 // Galerkin tables C, E, N, NE and the inverse diagonal ID over the box +- 1
 // ring (pitch RW).  Threads map to nodes as a TX x TY grid (TX = 2^txs >= n),
 // so no integer division appears in the level loops.
+// Outside its table region a level's operator is the air stencil
+// air * [1, -1/4, -1/4, -1/4, -1/4] (air = 1 for a hierarchy of the scaled
+// system, 4 nu_air for one of the unscaled operator).
 template <typename VT>
 struct CLev {
   int n, np, bx0, by0, lx1, ly1, RW, txs;
+  VT air, air_id;
   VT *R, *Z, *T;
   const VT *C, *E, *N, *NE, *ID;
 };
 
 template <typename VT>
-__device__ inline CLev<VT> clev(const MGGeom& mg, int l, VT* region, const VT* ctab, int nthr) {
+__device__ inline CLev<VT> clev(const MGGeom& mg, int l, VT* region, const VT* ctab, int nthr,
+                                VT air = VT(1)) {
   const MGLevel& M = mg.lv[l];
   CLev<VT> L;
+  L.air = air;
+  L.air_id = VT(1) / air;
   L.n = M.n;
   L.np = M.n + 2;
   L.bx0 = M.bx0;
@@ -293,13 +300,13 @@ __device__ inline VT capp(const CLev<VT>& L, const VT* v, int i, int j, VT* idg)
     return L.C[t] * c + L.E[t] * e + L.E[t - 1] * w + L.N[t] * nn + L.N[t - L.RW] * s +
            L.NE[t] * v[p + np + 1] + L.NE[t - L.RW - 1] * v[p - np - 1];
   }
-  *idg = VT(1);
-  return c - VT(0.25) * ((e + w) + (nn + s));
+  *idg = L.air_id;
+  return L.air * (c - VT(0.25) * ((e + w) + (nn + s)));
 }
 
 template <typename VT>
 __device__ inline VT clev_id(const CLev<VT>& L, int i, int j) {
-  return clev_inL(L, i, j) ? L.ID[(j - L.by0 + 1) * L.RW + (i - L.bx0 + 1)] : VT(1);
+  return clev_inL(L, i, j) ? L.ID[(j - L.by0 + 1) * L.RW + (i - L.bx0 + 1)] : L.air_id;
 }
 
 // Restriction P^T t at coarse node (ic, jc): coarse c <-> fine 2c+1, weights 1
@@ -390,15 +397,16 @@ __device__ inline void c_zero_halo(const CLev<VT>& L, int me, int nthr) {
 // already in place.  Levels with n >= 31 use the whole workgroup, smaller
 // ones run on wave 0 alone.  Output: T_1 (or Z_1 if level 1 is the coarsest).
 template <typename VT, int NT>
-__device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid) {
+__device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
+                                    VT air = VT(1)) {
   const int L = mg.nlev;
   auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= 31; };
   int lb = 0;  // last block level
   while (lb + 1 <= L && is_block(lb + 1)) ++lb;
   // block levels: descent
   for (int l = 1; l <= lb && l < L; ++l) {
-    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT);
-    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT);
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
     c_resid(F, tid, NT);
     __syncthreads();
     c_restrict(F, Cc, om, l + 1 == L, tid, NT);
@@ -407,16 +415,16 @@ __device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab
   // wave levels
   if (lb < L && tid < 64) {
     for (int l = lb + 1; l < L; ++l) {
-      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64);
-      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64);
+      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
+      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
       c_resid(F, tid, 64);
       wave_sync();
       c_restrict(F, Cc, om, l + 1 == L, tid, 64);
       wave_sync();
     }
     for (int l = L - 1; l > lb; --l) {
-      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64);
-      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64);
+      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
+      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
       c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, 64);
       wave_sync();
       c_post(F, om, tid, 64);
@@ -426,8 +434,8 @@ __device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab
   if (lb < L) __syncthreads();
   // block levels: ascent
   for (int l = (lb < L ? lb : L - 1); l >= 1; --l) {
-    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT);
-    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT);
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
     c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, NT);
     __syncthreads();
     c_post(F, om, tid, NT);
@@ -1336,7 +1344,7 @@ int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision, in
   return 1;
 }
 
-hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                             int* counter, double* work, int n_slots, int max_grid, const double* S,
                             int* grid_out, int* block_out, hipStream_t st);
 
@@ -1362,7 +1370,7 @@ hipError_t launch_ie(const Geom& g, const MGGeom& mg, const Solver& sv, const In
     return usemg ? MQ_DISPATCH(float, true, false) : MQ_DISPATCH(float, false, false);
 #undef MQ_DISPATCH
   }
-  return launch_ie_stream(g, sv, insts, n_inst, counter, work, n_slots, max_grid, S, grid_out, block_out, st);
+  return launch_ie_stream(g, mg, sv, insts, n_inst, counter, work, n_slots, max_grid, S, grid_out, block_out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1597,8 +1605,87 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
          tNE[t - g.RW - 1] * R[gi - P - 1];
 }
 
-template <typename VT, int NT>
-__global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst* __restrict__ insts,
+// Galerkin coarse operators for levels 1..nlev into ctab (5 planes per level:
+// C, E, N, NE, 1/C).  The fine level's couplings are those of the scaled
+// system D^{-1/2} A D^{-1/2} (fE, fN, fNE, pitch fpitch, unit diagonal).
+// With fD (D^{-1/2} per node of the table region, pitch fpitch; d_air
+// elsewhere) level 1 is P^T A P of the unscaled A, i.e. the interpolation
+// from level 1 to the scaled fine level is D^{1/2} P: the coarse space then
+// holds the smooth functions of A rather than of the scaled system, whose
+// scaling jumps across the conductor boundary.  Without fD it is P^T Ahat P.
+template <typename VT>
+__device__ void build_galerkin(const MGGeom& mg, VT* ctab, const VT* tE, const VT* tN, const VT* tNE,
+                               const VT* fD, double d_air, int fpitch, int tid, int nthr) {
+  const double air = fD ? 1.0 / (d_air * d_air) : 1.0;  // air diagonal of the coarse levels
+  for (int l = 1; l <= mg.nlev; ++l) {
+    const MGLevel& M = mg.lv[l];
+    const MGLevel& F = mg.lv[l - 1];
+    const int pl = M.RW * M.RH;
+    VT* C = ctab + M.tab_off;
+    VT* E = C + pl;
+    VT* Nn = E + pl;
+    VT* NE = Nn + pl;
+    VT* ID = NE + pl;
+    const int fp = l == 1 ? fpitch : F.RW;
+    const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
+    const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
+    const VT* fN = l == 1 ? tN : fE + F.RW * F.RH;
+    const VT* fNE = l == 1 ? tNE : fN + F.RW * F.RH;
+    const double air_below = l == 1 ? 1.0 : air;
+    auto cs = [&](int fi, int fj, int d) -> double {  // coupling of the level below
+      if (!(fi >= F.bx0 && fi < F.lx1 && fj >= F.by0 && fj < F.ly1)) {
+        if (d == 0) return air_below;
+        return d <= 4 ? -0.25 * air_below : 0.0;
+      }
+      const int t = (fj - F.by0 + 1) * fp + (fi - F.bx0 + 1);
+      switch (d) {
+        case 0: return fC ? (double)fC[t] : 1.0;
+        case 1: return (double)fE[t];
+        case 2: return (double)fE[t - 1];
+        case 3: return (double)fN[t];
+        case 4: return (double)fN[t - fp];
+        case 5: return (double)fNE[t];
+        default: return (double)fNE[t - fp - 1];
+      }
+    };
+    const bool unscale = l == 1 && fD;
+    auto dn = [&](int fi, int fj) -> double {  // fine D^{-1/2}
+      if (fi >= F.bx0 - 1 && fi <= F.bx1 && fj >= F.by0 - 1 && fj <= F.by1)
+        return (double)fD[(fj - F.by0 + 1) * fp + (fi - F.bx0 + 1)];
+      return d_air;
+    };
+    auto cf = [&](int fi, int fj, int d) -> double {
+      const double c = cs(fi, fj, d);
+      if (!unscale) return c;
+      const int OXd[7] = {0, 1, -1, 0, 0, 1, -1}, OYd[7] = {0, 0, 0, 1, -1, 1, -1};
+      return c / (dn(fi, fj) * dn(fi + OXd[d], fj + OYd[d]));
+    };
+    for (int t = tid; t < pl; t += nthr) {
+      const int i = M.bx0 - 1 + t % M.RW, j = M.by0 - 1 + t / M.RW;
+      const bool box = i >= M.bx0 && i < M.bx1 && j >= M.by0 && j < M.by1;
+      double o[4] = {air, -0.25 * air, -0.25 * air, 0.0};
+      if (box) galerkin_entries(cf, F.n, M.n, i, j, o);
+      C[t] = vt<VT>(o[0]);
+      E[t] = vt<VT>(o[1]);
+      Nn[t] = vt<VT>(o[2]);
+      NE[t] = vt<VT>(o[3]);
+      ID[t] = vt<VT>(1.0 / o[0]);
+    }
+    __syncthreads();
+  }
+}
+
+// Per-slot VT workspace of the streaming kernel: six full-grid vectors, the
+// four scaled table planes over the box region and, with multigrid, the
+// coarse-level vectors and Galerkin tables.
+__host__ __device__ inline size_t stream_slot_elems(const Geom& g, const MGGeom& mg, bool use_mg) {
+  size_t e = 6 * (size_t)g.N * g.P + 4 * (size_t)g.RW * g.RH;
+  if (use_mg) e += (size_t)mg.region_elems + (size_t)mg.ctab_elems;
+  return e;
+}
+
+template <typename VT, int NT, bool MG>
+__global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, const Inst* __restrict__ insts,
                                                   int n_inst, int* counter, double* work,
                                                   const double* __restrict__ S, VT* vwork) {
   constexpr int NWAVES = NT / 64;
@@ -1612,15 +1699,22 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   double* Xprev = Bv + 2 * FS;
-  VT* Rv = vwork + (size_t)blockIdx.x * (5 * FS + 4 * (size_t)RHW);
+  VT* Rv = vwork + (size_t)blockIdx.x * stream_slot_elems(g, mg, MG);
   VT* Yv = Rv + FS;
   VT* Pv = Yv + FS;
   VT* Sv = Pv + FS;
   VT* Wv = Sv + FS;
-  VT* tE = Wv + FS;
+  VT* Vv = Wv + FS;  // multigrid: q = A p
+  VT* tE = Vv + FS;
   VT* tN = tE + RHW;
   VT* tNE = tN + RHW;
   VT* tD = tNE + RHW;
+  VT* mgreg = tD + RHW;              // multigrid: coarse vectors (zero halo)
+  VT* ctab = mgreg + mg.region_elems;  // multigrid: Galerkin tables
+  // fine-level thread grid: 2^fs columns x (NT >> fs) rows, no divisions
+  int fs = 0;
+  while ((1 << fs) < n && (2 << fs) <= NT) ++fs;
+  const int ftx = tid & ((1 << fs) - 1), fty = NT >> fs, fj0 = tid >> fs;
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   const int lw = g.lx1 - g.bx0, lh = g.ly1 - g.by0;
   int slot = 0;
@@ -1669,6 +1763,11 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
     __syncthreads();
     const double dmin = (double)__int_as_float(s_dmin) * 0.999;
     const double floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
+    if constexpr (MG) {
+      build_galerkin<VT>(mg, ctab, tE, tN, tNE, tD, d_air, g.RW, tid, NT);
+      for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, mgreg, ctab, NT), tid, NT);
+      __syncthreads();
+    }
     auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       return box ? tD[nr.t] : (VT)d_air;
@@ -1707,6 +1806,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
               Yv[nr.gi] = VT(0);
               Pv[nr.gi] = VT(0);
               Sv[nr.gi] = VT(0);
+              if constexpr (MG) Vv[nr.gi] = VT(0);
             }
             block_sum<1, NWAVES>(rr, red, slot);
             if (!(rr[0] == rr[0]) || isinf(rr[0])) {
@@ -1719,6 +1819,91 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
             }
             if (sweep == sv.max_sweeps) break;
             sw_total++;
+            int it = 0;
+            if constexpr (MG) {
+              // ---- CG preconditioned by a geometric multigrid V(1,1)-cycle ----
+              // (the resident kernel's cycle with every level in global memory)
+              const VT om = vt<VT>(sv.mg_omega);
+              auto nodes = [&](auto&& f) __attribute__((always_inline)) {
+                for (int j = fj0; j < n; j += fty)
+                  for (int i = ftx; i < n; i += (1 << fs)) f(i, j, node_ref(g, i, j));
+              };
+              VT* Zm = Sv;  // preconditioned residual
+              VT* Tm = Wv;  // fine residual t / smoothing output (swapped with Zm)
+              // coarse levels hold the unscaled operators: level 1 <-> scaled fine
+              // level through D^{1/2} P (air diagonal 4 nu_air = 1 / d_air^2)
+              const VT air = vt<VT>(1.0 / (d_air * d_air));
+              const CLev<VT> L1 = clev<VT>(mg, 1, mgreg, ctab, NT, air);
+              const bool exact1 = mg.nlev == 1;
+              double rho = 1.0, stop = 0.0;
+              for (;;) {
+                // z = B r: pre-smoothing from zero (z = om r) and t = r - A z
+                nodes([&](int i, int j, const NodeRef& nr) {
+                  const VT r = Rv[nr.gi];
+                  Zm[nr.gi] = om * r;
+                  Tm[nr.gi] = (r - om * stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr)) / dnode(i, j, nr);
+                });
+                __syncthreads();
+                {  // restriction to level 1
+                  const int tx = tid & ((1 << L1.txs) - 1), ty = NT >> L1.txs;
+                  if (tx < L1.n) {
+                    for (int j = tid >> L1.txs; j < L1.n; j += ty) {
+                      const VT rc = restrict_at(Tm, g.P, tx, j);
+                      const int q = (j + 1) * L1.np + tx + 1;
+                      L1.R[q] = rc;
+                      L1.Z[q] = (exact1 ? VT(1) : om) * clev_id(L1, tx, j) * rc;
+                    }
+                  }
+                }
+                __syncthreads();
+                coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air);
+                __syncthreads();
+                const VT* z1 = exact1 ? L1.Z : L1.T;
+                nodes([&](int i, int j, const NodeRef& nr) {
+                  Zm[nr.gi] += prolong_at(z1, L1.np, i, j) / dnode(i, j, nr);
+                });
+                __syncthreads();
+                // post-smoothing z <- z + om (r - A z); r.z and r.r of the new z
+                double rz[2] = {0.0, 0.0};
+                nodes([&](int, int, const NodeRef& nr) {
+                  const VT r = Rv[nr.gi], z = Zm[nr.gi];
+                  const VT zn = z + om * (r - stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr));
+                  Tm[nr.gi] = zn;
+                  rz[0] += (double)(r * zn);
+                  rz[1] += (double)(r * r);
+                });
+                block_sum<2, NWAVES>(rz, red, slot);
+                { VT* t_ = Zm; Zm = Tm; Tm = t_; }
+                double beta = 0.0;
+                if (it == 0) {
+                  stop = fmax(sv.inner_rtol * sv.inner_rtol * rz[1], floor_fac * bb);
+                  if (!(rz[1] > 0.0) || !(rz[0] > 0.0)) break;
+                } else {
+                  if (rz[1] <= stop || !(rz[1] == rz[1])) break;
+                  beta = rz[0] / rho;
+                }
+                rho = rz[0];
+                if (it == sv.max_iter) break;
+                ++it;
+                // p = z + beta p and q = A p = A z + beta q (one pass)
+                const VT b_ = vt<VT>(beta);
+                double pq[1] = {0.0};
+                nodes([&](int, int, const NodeRef& nr) {
+                  const VT p = Zm[nr.gi] + b_ * Pv[nr.gi];
+                  const VT q = stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr) + b_ * Vv[nr.gi];
+                  Pv[nr.gi] = p;
+                  Vv[nr.gi] = q;
+                  pq[0] += (double)(p * q);
+                });
+                block_sum<1, NWAVES>(pq, red, slot);
+                const VT a_ = vt<VT>(rho / pq[0]);
+                nodes([&](int, int, const NodeRef& nr) {
+                  Yv[nr.gi] += a_ * Pv[nr.gi];
+                  Rv[nr.gi] -= a_ * Vv[nr.gi];
+                });
+                __syncthreads();
+              }
+            } else {
             double gd[2] = {0.0, 0.0};
             for (int idx = tid; idx < nd; idx += NT) {
               const NodeRef nr = node_ref(g, idx % n, idx / n);
@@ -1732,7 +1917,6 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
             const double g0 = gd[0];
             double gam = gd[0], alpha = gd[0] / gd[1], beta = 0.0;
             const double stop = fmax(sv.inner_rtol * sv.inner_rtol * g0, floor_fac * bb);
-            int it = 0;
             if (g0 > 0.0) {
               for (it = 1; it <= sv.max_iter; ++it) {
                 const VT a_ = (VT)alpha, b_ = (VT)beta;
@@ -1764,6 +1948,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
                 gam = gd[0];
               }
               if (it > sv.max_iter) it = sv.max_iter;
+            }
             }
             it_step += it;
             for (int idx = tid; idx < nd; idx += NT) {
@@ -1842,11 +2027,11 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, Solver sv, const Inst*
 
 constexpr int STREAM_NT = 1024;
 
-size_t stream_vwork_elems(const Geom& g) {
-  return 5 * (size_t)g.N * g.P + 4 * (size_t)g.RW * g.RH;
+size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
+  return stream_slot_elems(g, mg ? *mg : MGGeom{}, mg && mg->nlev > 0);
 }
 
-hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, int n_inst,
+hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                             int* counter, double* work, int n_slots, int max_grid, const double* S,
                             int* grid_out, int* block_out, hipStream_t st) {
   // the VT workspace follows the FP64 work buffers of all n_slots slots
@@ -1854,12 +2039,22 @@ hipError_t launch_ie_stream(const Geom& g, const Solver& sv, const Inst* insts, 
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = STREAM_NT;
   double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
+  const bool usemg = sv.precond == 1 && mg.nlev > 0;
   if (sv.precision == MQ_PREC_FP64) {
-    hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT>), dim3(grid), dim3(STREAM_NT), 0, st, g, sv,
-                       insts, n_inst, counter, work, S, vbase);
+    if (usemg)
+      hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT, true>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
+                         insts, n_inst, counter, work, S, vbase);
+    else
+      hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT, false>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
+                         insts, n_inst, counter, work, S, vbase);
   } else {
-    hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT>), dim3(grid), dim3(STREAM_NT), 0, st, g, sv,
-                       insts, n_inst, counter, work, S, reinterpret_cast<float*>(vbase));
+    float* fb = reinterpret_cast<float*>(vbase);
+    if (usemg)
+      hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT, true>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
+                         insts, n_inst, counter, work, S, fb);
+    else
+      hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT, false>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
+                         insts, n_inst, counter, work, S, fb);
   }
   return hipGetLastError();
 }

@@ -144,6 +144,7 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);
 int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision, int tile);
-size_t stream_vwork_elems(const Geom& g);
+// VT elements per slot of the streaming kernel (mg: its multigrid hierarchy, or null)
+size_t stream_vwork_elems(const Geom& g, const MGGeom* mg);
 
 }  // namespace mq
