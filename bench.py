@@ -1,18 +1,31 @@
 #!/usr/bin/env python3
 """Throughput / latency benchmark of the batched MLMC hot path on one MI355X.
 
-Workload: MLMC with 3 time levels on the 129x129-node eddy-current model
-(KL-8 lognormal conductivity, 64/128/256 steps per period over 4 periods,
-512/128/32 samples, coupled level differences), FP32 CG inside FP64
-iterative refinement.  One benchmark step = one full MLMC estimate: device
-assembly of every sample, all implicit-Euler runs of all levels in one
-persistent launch, the Joule-loss QoIs and the estimator of Eq. (9).
-Inputs (xi) are resident in device memory before the timed region.
+Default workload (--workload mlmc3): MLMC with 3 time levels on the
+129x129-node eddy-current model (KL-8 lognormal conductivity, 64/128/256
+steps per period over 4 periods, 512/128/32 samples, coupled level
+differences), FP32 CG inside FP64 iterative refinement.  One benchmark step =
+one full MLMC estimate: device assembly of every sample, all implicit-Euler
+runs of all levels in one persistent launch, the Joule-loss QoIs and the
+estimator of Eq. (9).  Inputs (xi) are resident in device memory before the
+timed region.
 
 Printed: one JSON line with sample-steps/s (whole job), p50/p99 per-sample
 latency, QoI error against the FP64 oracle and against the plain FP64 GPU
-path (one sample per launch), the roofline of the dominant kernel and the
-oracle timed on the host cores.
+path (one sample per launch, Jacobi-preconditioned CG), the roofline of the
+dominant kernel and the oracle timed on the host cores.
+
+Other workloads, one JSON line each in the same shape:
+  --workload parareal   Parareal on the finest level (257x257, 64 samples,
+                        32 slices of 32 fine steps, 1 coarse step per slice,
+                        K <= 8, tol 1e-8); value = useful (serial-equivalent)
+                        sample-steps/s, beside the batched serial fine run.
+  --workload nonlinear  MLMC with 4 levels and the nonlinear reluctivity
+                        (Picard per step), 129x129, 1024/256/64/16 samples.
+  --workload serving    Poisson stream of sample-solve requests (mixed meshes
+                        65..513, 64..1024 steps per period, 2 periods) into the
+                        continuous-batching server; the first --requests of
+                        the stream at --rate requests/s.
 """
 from __future__ import annotations
 
@@ -36,6 +49,14 @@ CG_FLOPS_PER_DOF_ITER = 26          # 7-point scaled stencil (14) + CG vector up
 # plus the coarse levels (1/4 + 1/16 + ... of that work)
 MG_FLOPS_PER_DOF_ITER = 26 + (28 + 6 + 8) * 4.0 / 3.0
 CG_BYTES_PER_DOF_ITER_FP32 = 72     # modelled streaming traffic of one FP32 CG iteration
+# streaming multigrid CG, algorithmic HBM bytes per fine DoF and iteration (FP32
+# vectors, each vector element read/written once per pass): pre-smoothing and
+# residual 12, restriction 6, prolongation 9, post-smoothing 12, p/q update 20,
+# y/r update 24, coarse levels (1/4 + 1/16 + ...) x 40 = 13
+STREAM_MG_BYTES_PER_DOF_ITER = 96
+# outer FP64 work per fine DoF and time step (right-hand side 24, two
+# refinement residuals 2 x 36, two increment updates 2 x 20, state update 48, QoI)
+STREAM_OUTER_BYTES_PER_DOF_STEP = 220
 
 
 def _kernel_source_hash() -> str:
@@ -112,6 +133,240 @@ def cpu_baseline(w, xis, n_per_level=(4, 1, 1)):
     }, {keys[i]: res[i][0] for i in range(len(res))}
 
 
+def _cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_pool(tasks, fn):
+    """Run oracle tasks in a spawn pool with one BLAS thread per worker."""
+    import multiprocessing as mp
+    cores = max(1, min(_cores(), 16, len(tasks)))
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(fn, tasks)
+    wall = time.perf_counter() - t0
+    for k, v in env_threads.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    return res, wall, cores
+
+
+def _picard_task(args):
+    problem, xi, spp, nper = args
+    from oracle import picard
+    t = time.perf_counter()
+    q, _ = picard.solve_sample(problem, xi, spp, nper)
+    return q, spp * nper, time.perf_counter() - t
+
+
+def _contract(metric_unit, value, elapsed, args, config, dtype="f32+f64"):
+    return {
+        "metric": "sample-steps/s + p50/p99 sample latency vs plain FP64, QoI rel err <= 1e-6",
+        "value": value, "unit": metric_unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+    }
+
+
+def _hbm_roofline(kernel, bytes_per_launch, avg_launch_s, traffic=None, model=""):
+    gbs = bytes_per_launch / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": kernel, "avg_launch_ms": 1e3 * avg_launch_s,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "model": model}
+
+
+def bench_parareal(args, mq, L, W, np, torch):
+    """Parareal on the finest level (257x257, 64 samples); value = useful sample-steps/s."""
+    w = W.parareal_257()
+    pr = w.parareal
+    xi_np = W.level_xi(w, 0)
+    xi = torch.tensor(xi_np, dtype=torch.float64, device="cuda")
+    from paper_2507_19246_amd import autotune
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
+    nd = prob.n_dof
+    n_f = pr.n_slices * pr.fine_steps_per_slice
+    useful = xi.shape[0] * n_f
+
+    def step():
+        return mq.parareal_run(prob, pr.n_periods, pr.n_slices, pr.fine_steps_per_slice,
+                               pr.coarse_steps_per_slice, pr.k_max, pr.tol, xi)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, it, _, rc, st = step()
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the same samples as one batched serial fine run (no Parareal)
+    spp = n_f // pr.n_periods
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    qs, _, _, _, sts = mq.mlmc_level_run(prob, spp, 0, pr.n_periods, xi)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+    qp, qsr = q.cpu().numpy(), qs.cpu().numpy()
+    iters = it.cpu().numpy()
+    executed = stats[-1]["sample_steps"]
+    avg_kern_s = sum(s["kernel_ms"] for s in stats) / len(stats) / 1e3
+    inner = stats[-1]["inner_iters"]
+    bytes_launches = nd * (inner * STREAM_MG_BYTES_PER_DOF_ITER + executed * STREAM_OUTER_BYTES_PER_DOF_STEP)
+    res = _contract("sample-steps/s", useful * args.steps / elapsed, elapsed, args, {
+        "workload": w.name, "mesh": "257x257", "n_dof": nd, "samples": int(xi.shape[0]),
+        "fine_steps": n_f, "slices": pr.n_slices, "coarse_steps_per_slice": pr.coarse_steps_per_slice,
+        "k_max": pr.k_max, "tol": pr.tol, "path": "resident" if stats[-1]["path"] == 1 else "streaming",
+        "launch_block": stats[-1]["block"], "knobs": dict(knobs, precond=prob.info.precond)})
+    res.update({
+        "useful_sample_steps": useful, "executed_sample_steps": executed,
+        "extra_effort": executed / useful,
+        "parareal_iterations": {"min": int(iters.min()), "max": int(iters.max()), "mean": float(iters.mean())},
+        "status": rc, "latency_ms": 1e3 * elapsed / args.steps,
+        "serial_fine_batched": {"value": useful / serial_s, "unit": "sample-steps/s", "wall_ms": 1e3 * serial_s,
+                                "cg_iters_per_sample_step": sts["inner_iters"] / sts["sample_steps"]},
+        "q_max_rel_diff_parareal_vs_serial": float(np.max(np.abs(qp - qsr) / np.abs(qsr))),
+        "cg_iters_per_executed_step": inner / executed,
+        "roofline": _hbm_roofline("k_ie_stream<float,1024,multigrid>", bytes_launches, avg_kern_s, None,
+                                  f"{STREAM_MG_BYTES_PER_DOF_ITER} B per DoF-iteration + "
+                                  f"{STREAM_OUTER_BYTES_PER_DOF_STEP} B per DoF-step, summed over the "
+                                  "launches of one parareal_run"),
+    })
+    if not args.no_cpu_baseline:
+        tasks = [(w.problem, xi_np[s], spp, pr.n_periods) for s in range(2)]
+        out, wall, cores = _oracle_pool(tasks, _oracle_task)
+        errs = [abs(qsr[s] - out[s][0]) / abs(out[s][0]) for s in range(len(tasks))]
+        res["cpu_baseline"] = {"value": sum(o[1] for o in out) / wall, "unit": "sample-steps/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"serial fine runs ({n_f} steps) of the first {len(tasks)} samples, "
+                                         "banded-Cholesky FP64"}
+        res["qoi_max_rel_err_serial_vs_fp64_oracle"] = max(errs)
+        res["qoi_max_rel_err_parareal_vs_fp64_oracle"] = max(
+            abs(qp[s] - out[s][0]) / abs(out[s][0]) for s in range(len(tasks)))
+    prob.close()
+    return res
+
+
+def bench_nonlinear(args, mq, L, W, np, torch):
+    """MLMC with 4 levels and the nonlinear reluctivity (Picard), 129x129."""
+    w = W.nonlinear_mlmc4_129()
+    levels = [(lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods) for lv in w.levels]
+    xis_np = [W.level_xi(w, l) for l in range(len(w.levels))]
+    xis = [torch.tensor(x, dtype=torch.float64, device="cuda") for x in xis_np]
+    from paper_2507_19246_amd import autotune
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
+    nd = prob.n_dof
+
+    def step():
+        qfs, qcs, rc, st = mq.mlmc_multilevel_run(prob, levels, xis)
+        e, y, v = mq.mlmc_estimate(qfs, qcs)
+        return qfs, qcs, e, rc, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        qfs, qcs, e, rc, st = step()
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sample_steps = sum(s["sample_steps"] for s in stats)
+    avg_kern_s = sum(s["kernel_ms"] for s in stats) / len(stats) / 1e3
+    units = nd * stats[-1]["inner_iters"]
+    flops_unit = MG_FLOPS_PER_DOF_ITER if prob.info.precond == L.MQ_PRECOND_MULTIGRID else CG_FLOPS_PER_DOF_ITER
+    tf = flops_unit * units / avg_kern_s / 1e12
+    res = _contract("sample-steps/s", sample_steps / elapsed, elapsed, args, {
+        "workload": w.name, "mesh": "129x129", "n_dof": nd,
+        "levels_steps_per_period": [lv.steps_per_period for lv in w.levels], "n_periods": w.levels[0].n_periods,
+        "samples_per_level": [lv.n_samples for lv in w.levels], "sample_steps_per_step": stats[-1]["sample_steps"],
+        "picard_tol": w.problem.material.picard_tol, "launch": [stats[-1]["grid"], stats[-1]["block"]],
+        "knobs": dict(knobs, tile=prob.info.tile, precond=prob.info.precond)})
+    res.update({
+        "p50_latency_ms": st["lat_p50_ms"], "p99_latency_ms": st["lat_p99_ms"], "status": rc,
+        "mlmc_estimate": float(e),
+        "picard_iters_per_sample_step": stats[-1]["picard_iters"] / stats[-1]["sample_steps"],
+        "cg_iters_per_sample_step": stats[-1]["inner_iters"] / stats[-1]["sample_steps"],
+        "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_ie_resident<float,128,16,8,64,%s,nonlinear>" % (
+                         "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi"),
+                     "avg_launch_ms": 1e3 * avg_kern_s, "flops_per_dof_iter": flops_unit},
+    })
+    if not args.no_cpu_baseline:
+        lv = w.levels[0]
+        tasks = [(w.problem, xis_np[0][s], lv.steps_per_period, lv.n_periods) for s in range(4)]
+        out, wall, cores = _oracle_pool(tasks, _picard_task)
+        q0 = qfs[0].cpu().numpy()
+        res["cpu_baseline"] = {"value": sum(o[1] for o in out) / wall, "unit": "sample-steps/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"first {len(tasks)} samples of level 0 ({lv.steps_per_period * lv.n_periods}"
+                                         " steps each, Picard with a banded-Cholesky refactorisation per iteration)"}
+        res["qoi_max_rel_err_vs_fp64_oracle"] = max(abs(q0[s] - out[s][0]) / abs(out[s][0]) for s in range(len(tasks)))
+    prob.close()
+    return res
+
+
+def bench_serving(args, mq, L, W, np, torch):
+    """Poisson request stream into the continuous-batching server."""
+    reqs = W.serving_stream(args.requests, rate_hz=args.rate)
+    base = W.Problem(65, W.Material(kind=W.MAT_KL))
+    srv = mq.Server(base, L.MQ_PREC_MIXED, hbm_budget_bytes=96 << 30, max_inflight=4096, n_streams=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets, done = {}, {}
+    i = 0
+    t_report = t0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i].arrival_s <= now:
+            r = reqs[i]
+            tickets[srv.submit(r.n_nodes, r.steps_per_period, r.n_periods, r.xi, user_id=i)] = i
+            i += 1
+        for r in srv.poll(1024):
+            done[r.ticket] = r
+        if time.perf_counter() - t_report > 10.0:
+            t_report = time.perf_counter()
+            print(f"serving: {i} submitted, {len(done)} done, {t_report - t0:.0f} s", file=sys.stderr, flush=True)
+        if time.perf_counter() - t0 > args.serving_limit_s:
+            srv.close()
+            raise RuntimeError(f"serving run exceeded {args.serving_limit_s} s ({len(done)} of {len(reqs)} done)")
+        time.sleep(0.0005)
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([(r.t_done_ns - r.t_submit_ns) / 1e6 for r in done.values()])
+    steps = sum(reqs[r.user_id].steps_per_period * reqs[r.user_id].n_periods for r in done.values())
+    by_mesh = {}
+    for r in done.values():
+        q = reqs[r.user_id]
+        by_mesh.setdefault(q.n_nodes, []).append((r.t_done_ns - r.t_submit_ns) / 1e6)
+    bad = sum(1 for r in done.values() if r.status < 0)
+    args.steps, args.warmup = 1, 0
+    res = _contract("sample-steps/s", steps / elapsed, elapsed, args, {
+        "workload": f"serving-kl8-mixed-{len(reqs)}req-{args.rate:g}rps",
+        "meshes": list(W.SERVING_MESHES), "mesh_weights": list(W.SERVING_MESH_WEIGHTS),
+        "steps_per_period": list(W.SERVING_STEPS), "n_periods": 2, "requests": len(reqs),
+        "rate_req_per_s": args.rate, "lanes_per_mesh": 2, "chunk_steps": 32})
+    res.update({
+        "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+        "requests_per_s": len(done) / elapsed, "failed": bad,
+        "latency_ms_by_mesh": {str(k): {"n": len(v), "p50": float(np.percentile(v, 50)),
+                                        "p99": float(np.percentile(v, 99))} for k, v in sorted(by_mesh.items())},
+        "roofline": None, "cpu_baseline": None,
+    })
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +376,10 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--workload", default="mlmc3", choices=["mlmc3", "parareal", "nonlinear", "serving"])
+    ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
+    ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -148,11 +407,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}}))
         return
+    if args.workload != "mlmc3":
+        fn = {"parareal": bench_parareal, "nonlinear": bench_nonlinear, "serving": bench_serving}[args.workload]
+        print(json.dumps(fn(args, mq, L, W, np, torch)), flush=True)
+        return
     w = W.mlmc3_mixed_129()
     levels = [(lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods) for lv in w.levels]
     xis_np = [W.level_xi(w, l) for l in range(len(w.levels))]
     xis = [torch.tensor(x, dtype=torch.float64, device="cuda") for x in xis_np]
-    prob = mq.Problem(w.problem, L.MQ_PREC_MIXED)
+    # launch/solver knobs measured by the autotuner for this device (committed cache), else defaults
+    from paper_2507_19246_amd import autotune
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
     nd = prob.n_dof
 
     def step():
@@ -186,8 +451,9 @@ def main():
     result = {}
     fp64 = None
     if not args.no_fp64_baseline:
-        # plain FP64 GPU path: one sample per launch, FP64 CG (streaming kernel, S = 1)
-        p64 = mq.Problem(w.problem, L.MQ_PREC_FP64)
+        # plain FP64 GPU path: one sample per launch, Jacobi-preconditioned FP64 CG
+        # (streaming kernel, S = 1)
+        p64 = mq.Problem(w.problem, L.MQ_PREC_FP64, precond=L.MQ_PRECOND_JACOBI)
         lv = w.levels[0]
         nb = 4
         lat, errs, steps64 = [], [], 0
@@ -205,7 +471,7 @@ def main():
         fp64 = {"value": steps64 / wall64, "unit": "sample-steps/s",
                 "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
                 "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
-                "samples": nb, "path": "FP64 CG, one sample per launch, streaming kernel",
+                "samples": nb, "path": "FP64 Jacobi-CG, one sample per launch, streaming kernel",
                 "qoi_max_rel_err_mixed_vs_fp64": max(errs)}
         result["plain_fp64_gpu"] = fp64
 
@@ -238,7 +504,8 @@ def main():
                    "samples_per_level": [lv.n_samples for lv in w.levels],
                    "sample_steps_per_step": stats[-1]["sample_steps"],
                    "path": "resident" if stats[-1]["path"] == 1 else "streaming",
-                   "launch": [stats[-1]["grid"], stats[-1]["block"]]},
+                   "launch": [stats[-1]["grid"], stats[-1]["block"]],
+                   "knobs": dict(knobs, tile=prob.info.tile, precond=prob.info.precond)},
         "p50_latency_ms": st["lat_p50_ms"],
         "p99_latency_ms": st["lat_p99_ms"],
         "qoi_max_rel_err_vs_fp64_oracle": qerr_oracle,
@@ -247,7 +514,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_ie_resident<float,128,16,8,64,multigrid>",
+                     "kernel": ("k_ie_resident<float,128,%d,%d,64,%s>" % (
+                         16 if prob.info.tile != 2 else 32, 8 if prob.info.tile != 2 else 4,
+                         "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi")),
                      "avg_launch_ms": 1e3 * avg_kern_s,
                      "flops_per_dof_iter": flops_unit,
                      "precond": "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi",

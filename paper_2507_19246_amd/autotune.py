@@ -1,0 +1,144 @@
+"""Measured selection of the launch and solver knobs of one problem (autotuner).
+
+For a mesh/material/precision the tuner times short level runs that fill the
+device (one instance per resident slot, a few steps each) under every
+candidate of:
+
+* ``tile``: the resident workgroup shape (16 or 32 rows per thread) where both exist,
+* ``precond``: Jacobi scaling alone or the multigrid V-cycle,
+* ``mg_omega``: the damped-Jacobi weight of the multigrid smoother,
+* ``inner_rtol``: the relative tolerance of the inner CG (mixed precision),
+
+and keeps the fastest candidate whose QoIs agree with the default
+configuration's within the precision's tolerance (1e-6 mixed, 1e-10 FP64).
+The outer tolerance, and so the accuracy of every result, is never tuned.
+
+Results are cached in a JSON file keyed by device name, mesh, material and
+precision (``MQ_AUTOTUNE_CACHE``, default ``tuned.json`` beside this module).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from typing import Dict, List, Optional
+
+from . import _lib as L
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
+
+QOI_AGREEMENT = {L.MQ_PREC_MIXED: 1e-6, L.MQ_PREC_FP64: 1e-10}
+
+
+def cache_path() -> str:
+    return os.environ.get("MQ_AUTOTUNE_CACHE", DEFAULT_CACHE)
+
+
+def cache_key(device: str, problem, precision: int) -> str:
+    m = problem.material
+    return f"{device}|n{problem.n_nodes}|mat{m.kind}|prec{precision}"
+
+
+def _is_pow2_mesh(n_nodes: int) -> bool:
+    n = n_nodes - 2
+    return n >= 1 and ((n + 1) & n) == 0
+
+
+def candidates(problem, precision: int) -> List[Dict]:
+    """Knob combinations worth timing for this problem (host logic only)."""
+    n = problem.n_nodes - 2
+    tiles = [1, 2] if 64 <= n <= 127 else [1]
+    preconds = [L.MQ_PRECOND_JACOBI]
+    if _is_pow2_mesh(problem.n_nodes):
+        preconds.append(L.MQ_PRECOND_MULTIGRID)
+    rtols = [1e-5, 3e-6, 1e-6] if precision == L.MQ_PREC_MIXED else [1e-10]
+    out = []
+    for tile, pc, rt in itertools.product(tiles, preconds, rtols):
+        omegas = [0.7, 0.8, 0.9] if pc == L.MQ_PRECOND_MULTIGRID else [0.0]
+        for om in omegas:
+            out.append({"tile": tile, "precond": pc, "mg_omega": om, "inner_rtol": rt})
+    return out
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(problem, precision: int, device: Optional[str] = None, path: Optional[str] = None) -> Optional[Dict]:
+    """Cached knobs for this problem, or None."""
+    import torch
+    device = device or torch.cuda.get_device_name(0)
+    return _load(path or cache_path()).get(cache_key(device, problem, precision), {}).get("knobs")
+
+
+def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int = 1,
+             n_samples: Optional[int] = None, force: bool = False, path: Optional[str] = None,
+             verbose: bool = False) -> Dict:
+    """Return the fastest agreeing knobs (from the cache unless force)."""
+    import numpy as np
+    import torch
+
+    from . import api as mq
+
+    path = path or cache_path()
+    device = torch.cuda.get_device_name(0)
+    key = cache_key(device, problem, precision)
+    db = _load(path)
+    if not force and key in db:
+        return db[key]["knobs"]
+    base = mq.Problem(problem, precision)
+    n_xi = base.n_xi
+    base.close()
+    if n_samples is None:
+        # fill the device: one instance per compute unit
+        n_samples = torch.cuda.get_device_properties(0).multi_processor_count
+    gen = torch.Generator().manual_seed(99)
+    xi = torch.randn(n_samples, n_xi, generator=gen, dtype=torch.float64).to("cuda")
+    tol = QOI_AGREEMENT[precision]
+    ref_q = None
+    trials = []
+    for knobs in [{}] + candidates(problem, precision):
+        try:
+            p = mq.Problem(problem, precision, **knobs)
+        except L.MQError:
+            continue  # this combination does not exist for the mesh (e.g. no room in LDS)
+        mq.mlmc_level_run(p, steps_per_period, 0, n_periods, xi[:8])  # warm-up (code objects)
+        dt = float("inf")
+        for _ in range(2):  # best kernel time of two runs
+            q, _, _, rc, st = mq.mlmc_level_run(p, steps_per_period, 0, n_periods, xi)
+            dt = min(dt, st["kernel_ms"] / 1e3)
+        qh = q.cpu().numpy()
+        info = {"tile": p.info.tile, "precond": p.info.precond, "block": p.info.block}
+        p.close()
+        if ref_q is None:
+            ref_q = qh
+        agree = bool(np.all(np.abs(qh - ref_q) <= tol * np.abs(ref_q))) and rc == 0
+        rate = st["sample_steps"] / dt
+        trials.append({"knobs": knobs, "rate": rate, "agree": agree, "resolved": info})
+        if verbose:
+            print(f"autotune {key} {knobs} -> {rate:.0f} sample-steps/s agree={agree}", flush=True)
+    ok = [t for t in trials if t["agree"]]
+    best = max(ok, key=lambda t: t["rate"])
+    db = _load(path)
+    db[key] = {"knobs": best["knobs"], "rate": best["rate"], "default_rate": trials[0]["rate"],
+               "resolved": best["resolved"], "trials": len(trials),
+               "probe": {"samples": n_samples, "steps_per_period": steps_per_period, "n_periods": n_periods}}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return best["knobs"]
+
+
+def tuned_problem(problem, precision: int, tune: bool = False, **override):
+    """A Problem with the cached knobs (tuning first when asked and not cached)."""
+    from . import api as mq
+    knobs = autotune(problem, precision) if tune else (lookup(problem, precision) or {})
+    knobs = dict(knobs)
+    knobs.update(override)
+    return mq.Problem(problem, precision, **knobs), knobs

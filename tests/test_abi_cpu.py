@@ -89,3 +89,21 @@ def test_no_device_and_invalid_arguments(lib):
     null = (C.c_void_p * 2)()
     assert lib.mlmc_estimate(2, ns, null, null, None, None) == _lib.MQ_ERR_INVALID_ARG
     assert lib.mq_problem_destroy(None) == _lib.MQ_OK
+
+
+def test_autotune_candidates_and_cache_key():
+    """Host logic of the autotuner: candidate sets per mesh and precision."""
+    import workloads as W
+    from paper_2507_19246_amd import _lib, autotune
+    c129 = autotune.candidates(W.Problem(129, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
+    assert {c["tile"] for c in c129} == {1, 2}
+    assert {c["precond"] for c in c129} == {_lib.MQ_PRECOND_JACOBI, _lib.MQ_PRECOND_MULTIGRID}
+    assert all(c["mg_omega"] == 0.0 for c in c129 if c["precond"] == _lib.MQ_PRECOND_JACOBI)
+    # 100 x 100 nodes: no multigrid (98 interior nodes is not 2^k - 1), both tiles
+    c100 = autotune.candidates(W.Problem(100, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_FP64)
+    assert {c["precond"] for c in c100} == {_lib.MQ_PRECOND_JACOBI}
+    assert {c["inner_rtol"] for c in c100} == {1e-10}
+    c33 = autotune.candidates(W.Problem(33, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
+    assert {c["tile"] for c in c33} == {1}
+    k = autotune.cache_key("dev", W.Problem(33, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
+    assert k == "dev|n33|mat1|prec1"
