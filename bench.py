@@ -211,12 +211,16 @@ def bench_parareal(args, mq, L, W, np, torch):
     elapsed = time.perf_counter() - t0
     # the same samples as one batched serial fine run (no Parareal)
     spp = n_f // pr.n_periods
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    qs, _, _, _, sts = mq.mlmc_level_run(prob, spp, 0, pr.n_periods, xi)
-    torch.cuda.synchronize()
-    serial_s = time.perf_counter() - ts
-    qp, qsr = q.cpu().numpy(), qs.cpu().numpy()
+    qp = q.cpu().numpy()
+    if args.no_serial:
+        qsr, sts, serial_s = qp, None, None
+    else:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        qs, _, _, _, sts = mq.mlmc_level_run(prob, spp, 0, pr.n_periods, xi)
+        torch.cuda.synchronize()
+        serial_s = time.perf_counter() - ts
+        qsr = qs.cpu().numpy()
     iters = it.cpu().numpy()
     executed = stats[-1]["sample_steps"]
     avg_kern_s = sum(s["kernel_ms"] for s in stats) / len(stats) / 1e3
@@ -232,16 +236,17 @@ def bench_parareal(args, mq, L, W, np, torch):
         "extra_effort": executed / useful,
         "parareal_iterations": {"min": int(iters.min()), "max": int(iters.max()), "mean": float(iters.mean())},
         "status": rc, "latency_ms": 1e3 * elapsed / args.steps,
-        "serial_fine_batched": {"value": useful / serial_s, "unit": "sample-steps/s", "wall_ms": 1e3 * serial_s,
-                                "cg_iters_per_sample_step": sts["inner_iters"] / sts["sample_steps"]},
-        "q_max_rel_diff_parareal_vs_serial": float(np.max(np.abs(qp - qsr) / np.abs(qsr))),
+        "serial_fine_batched": None if sts is None else {
+            "value": useful / serial_s, "unit": "sample-steps/s", "wall_ms": 1e3 * serial_s,
+            "cg_iters_per_sample_step": sts["inner_iters"] / sts["sample_steps"]},
+        "q_max_rel_diff_parareal_vs_serial": None if sts is None else float(np.max(np.abs(qp - qsr) / np.abs(qsr))),
         "cg_iters_per_executed_step": inner / executed,
         "roofline": _hbm_roofline("k_ie_stream<float,1024,multigrid>", bytes_launches, avg_kern_s, None,
                                   f"{STREAM_MG_BYTES_PER_DOF_ITER} B per DoF-iteration + "
                                   f"{STREAM_OUTER_BYTES_PER_DOF_STEP} B per DoF-step, summed over the "
                                   "launches of one parareal_run"),
     })
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and sts is not None:
         tasks = [(w.problem, xi_np[s], spp, pr.n_periods) for s in range(2)]
         out, wall, cores = _oracle_pool(tasks, _oracle_task)
         errs = [abs(qsr[s] - out[s][0]) / abs(out[s][0]) for s in range(len(tasks))]
@@ -380,6 +385,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
+    ap.add_argument("--no-serial", action="store_true", help="parareal: skip the batched serial comparison run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

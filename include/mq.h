@@ -102,9 +102,10 @@ typedef struct mq_problem_desc {
   int32_t max_iter, max_sweeps;
   int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available (n_nodes = 2^k + 1; on the
                         resident path if its LDS holds the hierarchy), else Jacobi */
-  int32_t tile;      /* resident workgroup shape: 0 auto (the built-in default, 1), 1 = 16 rows per
-                        thread, 2 = 32 rows per thread in 512-thread workgroups (meshes with 64..127
-                        interior nodes per side; others use 1) */
+  int32_t tile;      /* workgroup shape: 0 auto (the built-in default, 1).  Resident path: 1 = 16 rows
+                        per thread, 2 = 32 rows per thread in 512-thread workgroups (meshes with
+                        64..127 interior nodes per side; others use 1).  Streaming path: 1 = one
+                        1024-thread workgroup per compute unit, 2 = two 512-thread workgroups */
   double mg_omega;   /* damped-Jacobi weight of the multigrid smoother (0: 0.8) */
 } mq_problem_desc;
 
@@ -119,7 +120,7 @@ typedef struct mq_problem_info {
   int32_t mg_levels;     /* coarse levels of the multigrid hierarchy (0 if unused) */
   int32_t n_modes_used;
   double kl_lambda[16];  /* 2-D KL eigenvalues in use (KL material) */
-  int32_t tile;          /* resident workgroup shape in use (1 or 2; 0 on the streaming path) */
+  int32_t tile;          /* workgroup shape in use (1 or 2, see mq_problem_desc.tile) */
   int32_t block;         /* threads per workgroup of the time-stepping kernel */
 } mq_problem_info;
 

@@ -1,10 +1,11 @@
 """Measured selection of the launch and solver knobs of one problem (autotuner).
 
 For a mesh/material/precision the tuner times short level runs that fill the
-device (one instance per resident slot, a few steps each) under every
+device (two instances per compute unit, a few steps each) under every
 candidate of:
 
-* ``tile``: the resident workgroup shape (16 or 32 rows per thread) where both exist,
+* ``tile``: the workgroup shape (resident: 16 or 32 rows per thread where both
+  exist; streaming: one 1024-thread or two 512-thread workgroups per CU),
 * ``precond``: Jacobi scaling alone or the multigrid V-cycle,
 * ``mg_omega``: the damped-Jacobi weight of the multigrid smoother,
 * ``inner_rtol``: the relative tolerance of the inner CG (mixed precision),
@@ -48,10 +49,14 @@ def _is_pow2_mesh(n_nodes: int) -> bool:
 def candidates(problem, precision: int) -> List[Dict]:
     """Knob combinations worth timing for this problem (host logic only)."""
     n = problem.n_nodes - 2
-    tiles = [1, 2] if 64 <= n <= 127 else [1]
+    # tile 2: 32 rows per thread on the resident path (64..127 interior nodes per
+    # side), 512-thread workgroups (two per compute unit) on the streaming path
+    tiles = [1, 2] if (64 <= n <= 127 or n > 127) else [1]
     preconds = [L.MQ_PRECOND_JACOBI]
     if _is_pow2_mesh(problem.n_nodes):
-        preconds.append(L.MQ_PRECOND_MULTIGRID)
+        # Jacobi CG needs O(n) iterations per step: on the streaming meshes
+        # (n > 127) it is never competitive and only lengthens the tuning run
+        preconds = [L.MQ_PRECOND_MULTIGRID] if n > 127 else preconds + [L.MQ_PRECOND_MULTIGRID]
     rtols = [1e-5, 3e-6, 1e-6] if precision == L.MQ_PREC_MIXED else [1e-10]
     out = []
     for tile, pc, rt in itertools.product(tiles, preconds, rtols):
@@ -95,8 +100,8 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
     n_xi = base.n_xi
     base.close()
     if n_samples is None:
-        # fill the device: one instance per compute unit
-        n_samples = torch.cuda.get_device_properties(0).multi_processor_count
+        # fill the device: two instances per compute unit (the most slots any shape has)
+        n_samples = 2 * torch.cuda.get_device_properties(0).multi_processor_count
     gen = torch.Generator().manual_seed(99)
     xi = torch.randn(n_samples, n_xi, generator=gen, dtype=torch.float64).to("cuda")
     tol = QOI_AGREEMENT[precision]

@@ -422,7 +422,8 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   info->mg_levels = p->mg.nlev;
   info->n_modes_used = p->hm.n_modes;
   for (int k = 0; k < p->hm.n_modes && k < 16; ++k) info->kl_lambda[k] = p->hm.kl_lambda[k];
-  info->tile = p->path == MQ_PATH_RESIDENT ? p->tile : 0;
+  if (p->path == MQ_PATH_RESIDENT) info->tile = (p->tile == 2 && g.n >= 64 && g.n <= 127) ? 2 : 1;
+  else info->tile = p->tile;
   info->block = ie_block_threads(p->hm.g, p->path, p->tile);
   return MQ_OK;
 }

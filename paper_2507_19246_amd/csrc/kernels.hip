@@ -1259,10 +1259,12 @@ static bool pick_resident(const Geom& g, int tile, ResCfg* c) {
   return g.n <= c->sh * c->ns && g.RW <= c->tp;
 }
 
+int stream_threads(int tile);
+
 int ie_block_threads(const Geom& g, int path, int tile) {
   ResCfg c;
   if (path == MQ_PATH_RESIDENT && pick_resident(g, tile, &c)) return c.cw * c.ns;
-  return 1024;
+  return stream_threads(tile);
 }
 
 int resident_lp(const Geom& g, int tile) {
@@ -1341,7 +1343,7 @@ int ie_slots_per_cu(const Geom& g, const MGGeom* mg, int path, int precision, in
       return usemg ? occupancy_res<double, true>(g, mg, c) : occupancy_res<double, false>(g, mg, c);
     return usemg ? occupancy_res<float, true>(g, mg, c) : occupancy_res<float, false>(g, mg, c);
   }
-  return 1;
+  return tile == 2 ? 2 : 1;  // streaming: one 1024-thread or two 512-thread workgroups per CU
 }
 
 hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
@@ -2031,32 +2033,44 @@ size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
   return stream_slot_elems(g, mg ? *mg : MGGeom{}, mg && mg->nlev > 0);
 }
 
+template <int NT>
+static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
+                                  int* counter, double* work, int n_slots, int grid, const double* S, hipStream_t st) {
+  double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
+  const bool usemg = sv.precond == 1 && mg.nlev > 0;
+  if (sv.precision == MQ_PREC_FP64) {
+    if (usemg)
+      hipLaunchKernelGGL((k_ie_stream<double, NT, true>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+                         counter, work, S, vbase);
+    else
+      hipLaunchKernelGGL((k_ie_stream<double, NT, false>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+                         counter, work, S, vbase);
+  } else {
+    float* fb = reinterpret_cast<float*>(vbase);
+    if (usemg)
+      hipLaunchKernelGGL((k_ie_stream<float, NT, true>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+                         counter, work, S, fb);
+    else
+      hipLaunchKernelGGL((k_ie_stream<float, NT, false>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+                         counter, work, S, fb);
+  }
+  return hipGetLastError();
+}
+
+// Streaming workgroup size: 1024 threads (tile 1) or 512 threads (tile 2,
+// two workgroups per compute unit).
+int stream_threads(int tile) { return tile == 2 ? 512 : STREAM_NT; }
+
 hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                             int* counter, double* work, int n_slots, int max_grid, const double* S,
                             int* grid_out, int* block_out, hipStream_t st) {
   // the VT workspace follows the FP64 work buffers of all n_slots slots
   const int grid = max_grid < n_inst ? max_grid : n_inst;
+  const int nt = stream_threads(sv.tile);
   if (grid_out) *grid_out = grid;
-  if (block_out) *block_out = STREAM_NT;
-  double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
-  const bool usemg = sv.precond == 1 && mg.nlev > 0;
-  if (sv.precision == MQ_PREC_FP64) {
-    if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT, true>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
-                         insts, n_inst, counter, work, S, vbase);
-    else
-      hipLaunchKernelGGL((k_ie_stream<double, STREAM_NT, false>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
-                         insts, n_inst, counter, work, S, vbase);
-  } else {
-    float* fb = reinterpret_cast<float*>(vbase);
-    if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT, true>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
-                         insts, n_inst, counter, work, S, fb);
-    else
-      hipLaunchKernelGGL((k_ie_stream<float, STREAM_NT, false>), dim3(grid), dim3(STREAM_NT), 0, st, g, mg, sv,
-                         insts, n_inst, counter, work, S, fb);
-  }
-  return hipGetLastError();
+  if (block_out) *block_out = nt;
+  if (nt == 512) return launch_stream_nt<512>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
+  return launch_stream_nt<STREAM_NT>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
 }
 
 }  // namespace mq

@@ -105,5 +105,8 @@ def test_autotune_candidates_and_cache_key():
     assert {c["inner_rtol"] for c in c100} == {1e-10}
     c33 = autotune.candidates(W.Problem(33, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
     assert {c["tile"] for c in c33} == {1}
+    c257 = autotune.candidates(W.Problem(257, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
+    assert {c["tile"] for c in c257} == {1, 2}
+    assert {c["precond"] for c in c257} == {_lib.MQ_PRECOND_MULTIGRID}
     k = autotune.cache_key("dev", W.Problem(33, W.Material(kind=W.MAT_KL)), _lib.MQ_PREC_MIXED)
     assert k == "dev|n33|mat1|prec1"

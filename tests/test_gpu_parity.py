@@ -94,7 +94,8 @@ def test_plain_fp64_33_full_parity(pc):
 
 @pytest.mark.parametrize("n,path,pc,tile", [(33, 1, 1, 0), (33, 1, 2, 0), (33, 2, 1, 0), (33, 2, 2, 0),
                                             (65, 1, 1, 0), (65, 1, 2, 0), (65, 2, 1, 0), (65, 2, 2, 0),
-                                            (129, 1, 2, 1), (129, 1, 2, 2), (129, 1, 1, 2), (129, 2, 2, 0)])
+                                            (129, 1, 2, 1), (129, 1, 2, 2), (129, 1, 1, 2), (129, 2, 2, 0),
+                                            (65, 2, 2, 2), (65, 2, 1, 2)])
 def test_mixed_kl_coupled_level(n, path, pc, tile):
     """Mixed precision, KL field, coupled fine/coarse run: Q within 1e-6
     (resident/streaming path, Jacobi/multigrid preconditioner on either path,
@@ -107,6 +108,7 @@ def test_mixed_kl_coupled_level(n, path, pc, tile):
     assert p.info.precond == pc
     if tile:
         assert p.info.tile == tile and p.info.block == (1024 if tile == 1 else 512)
+        assert p.path == (L.MQ_PATH_STREAMING if path == 2 else L.MQ_PATH_RESIDENT)
     qf, qc, _, rc, st = mq.mlmc_level_run(p, 32, 16, 2, xi)
     assert rc == 0
     say("stats", st)
