@@ -66,9 +66,9 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str):
-    """HBM bytes per launch from the committed counter summary, or None when the
-    kernel source changed since the counters were taken."""
+def measured_traffic(name: str, key: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch (or per run: key) from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -80,7 +80,7 @@ def measured_traffic(name: str):
     if vals.get("traffic_source_sha256") != _kernel_source_hash():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -241,7 +241,8 @@ def bench_parareal(args, mq, L, W, np, torch):
             "cg_iters_per_sample_step": sts["inner_iters"] / sts["sample_steps"]},
         "q_max_rel_diff_parareal_vs_serial": None if sts is None else float(np.max(np.abs(qp - qsr) / np.abs(qsr))),
         "cg_iters_per_executed_step": inner / executed,
-        "roofline": _hbm_roofline("k_ie_stream<float,1024,multigrid>", bytes_launches, avg_kern_s, None,
+        "roofline": _hbm_roofline("k_ie_stream<float,%d,multigrid>" % stats[-1]["block"], bytes_launches, avg_kern_s,
+                                  measured_traffic("ie_stream_parareal_257_hbm_counters.md", "traffic_bytes_per_run"),
                                   f"{STREAM_MG_BYTES_PER_DOF_ITER} B per DoF-iteration + "
                                   f"{STREAM_OUTER_BYTES_PER_DOF_STEP} B per DoF-step, summed over the "
                                   "launches of one parareal_run"),
@@ -303,7 +304,8 @@ def bench_nonlinear(args, mq, L, W, np, torch):
         "picard_iters_per_sample_step": stats[-1]["picard_iters"] / stats[-1]["sample_steps"],
         "cg_iters_per_sample_step": stats[-1]["inner_iters"] / stats[-1]["sample_steps"],
         "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic("ie_resident_nonlinear_mlmc4_129_hbm_counters.md"),
                      "kernel": "k_ie_resident<float,128,16,8,64,%s,nonlinear>" % (
                          "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi"),
                      "avg_launch_ms": 1e3 * avg_kern_s, "flops_per_dof_iter": flops_unit},
