@@ -140,8 +140,11 @@ typedef struct mq_run_stats {
   double total_ms;             /* wall time of the call */
   double lat_p50_ms, lat_p99_ms, lat_max_ms; /* per-sample completion time after the first
                                                 instance started (device clock, last launch) */
-  double phase_ms[4];  /* multigrid phases summed over instances (one thread's clock):
-                          fine descent, coarse levels, fine ascent, CG apply + reductions */
+  double phase_ms[8];  /* resident-path phases summed over instances (one thread's clock):
+                          multigrid fine descent, coarse levels, fine ascent, CG apply +
+                          reductions; right-hand side, refinement residuals, increment
+                          updates, QoI + state update */
+  double busy_ms;      /* sum over instances of their device time (start to end) */
 } mq_run_stats;
 
 /* One MLMC level (Section II-B): every sample runs steps_per_period *

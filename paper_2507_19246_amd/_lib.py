@@ -63,7 +63,7 @@ class RunStats(C.Structure):
         ("path", C.c_int32), ("grid", C.c_int32), ("block", C.c_int32),
         ("kernel_ms", C.c_double), ("total_ms", C.c_double),
         ("lat_p50_ms", C.c_double), ("lat_p99_ms", C.c_double), ("lat_max_ms", C.c_double),
-        ("phase_ms", C.c_double * 4),
+        ("phase_ms", C.c_double * 8), ("busy_ms", C.c_double),
     ]
 
     def as_dict(self):

@@ -217,8 +217,9 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
       st->inner_iters += s4[0];
       st->sweeps += s4[1];
       st->max_inner_per_step = std::max(st->max_inner_per_step, s4[2]);
-      for (int q = 0; q < 4; ++q) st->phase_ms[q] += (double)(uint32_t)s4[8 + q] * 16.0 / p->wall_khz;
-      st->picard_iters += s4[12];
+      for (int q = 0; q < 8; ++q) st->phase_ms[q] += (double)(uint32_t)s4[8 + q] * 16.0 / p->wall_khz;
+      st->busy_ms += (double)(stamp(i, 1) - stamp(i, 0)) / p->wall_khz;
+      st->picard_iters += s4[16];
       if (s4[3] & FLAG_NOT_CONVERGED) st->n_not_converged++;
       if (s4[3] & FLAG_FAILED) st->n_failed++;
     }

@@ -477,6 +477,71 @@ __device__ inline void galerkin_entries(CF cf, int nf, int nc, int ic, int jc, d
 }
 
 
+// Galerkin coarse operators for levels 1..nlev into ctab (5 planes per level:
+// C, E, N, NE, 1/C).  The fine level's couplings are those of the scaled
+// system D^{-1/2} A D^{-1/2} (fE, fN, fNE, pitch fpitch, unit diagonal).
+// With `unscaled`, level 1 is P^T A P of the unscaled A (fine couplings
+// divided by d_i d_j, d = D^{-1/2} from dn(i, j)), i.e. the interpolation from
+// level 1 to the scaled fine level is D^{1/2} P: the coarse space then holds
+// the smooth functions of A rather than of the scaled system, whose scaling
+// jumps across the conductor boundary.  Otherwise it is P^T Ahat P.
+template <typename VT, class DN>
+__device__ void build_galerkin(const MGGeom& mg, VT* ctab, const VT* tE, const VT* tN, const VT* tNE,
+                               DN dn, bool unscaled, double d_air, int fpitch, int tid, int nthr) {
+  const double air = unscaled ? 1.0 / (d_air * d_air) : 1.0;  // air diagonal of the coarse levels
+  for (int l = 1; l <= mg.nlev; ++l) {
+    const MGLevel& M = mg.lv[l];
+    const MGLevel& F = mg.lv[l - 1];
+    const int pl = M.RW * M.RH;
+    VT* C = ctab + M.tab_off;
+    VT* E = C + pl;
+    VT* Nn = E + pl;
+    VT* NE = Nn + pl;
+    VT* ID = NE + pl;
+    const int fp = l == 1 ? fpitch : F.RW;
+    const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
+    const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
+    const VT* fN = l == 1 ? tN : fE + F.RW * F.RH;
+    const VT* fNE = l == 1 ? tNE : fN + F.RW * F.RH;
+    const double air_below = l == 1 ? 1.0 : air;
+    auto cs = [&](int fi, int fj, int d) -> double {  // coupling of the level below
+      if (!(fi >= F.bx0 && fi < F.lx1 && fj >= F.by0 && fj < F.ly1)) {
+        if (d == 0) return air_below;
+        return d <= 4 ? -0.25 * air_below : 0.0;
+      }
+      const int t = (fj - F.by0 + 1) * fp + (fi - F.bx0 + 1);
+      switch (d) {
+        case 0: return fC ? (double)fC[t] : 1.0;
+        case 1: return (double)fE[t];
+        case 2: return (double)fE[t - 1];
+        case 3: return (double)fN[t];
+        case 4: return (double)fN[t - fp];
+        case 5: return (double)fNE[t];
+        default: return (double)fNE[t - fp - 1];
+      }
+    };
+    const bool unscale = l == 1 && unscaled;
+    auto cf = [&](int fi, int fj, int d) -> double {
+      const double c = cs(fi, fj, d);
+      if (!unscale) return c;
+      const int OXd[7] = {0, 1, -1, 0, 0, 1, -1}, OYd[7] = {0, 0, 0, 1, -1, 1, -1};
+      return c / (dn(fi, fj) * dn(fi + OXd[d], fj + OYd[d]));
+    };
+    for (int t = tid; t < pl; t += nthr) {
+      const int i = M.bx0 - 1 + t % M.RW, j = M.by0 - 1 + t / M.RW;
+      const bool box = i >= M.bx0 && i < M.bx1 && j >= M.by0 && j < M.by1;
+      double o[4] = {air, -0.25 * air, -0.25 * air, 0.0};
+      if (box) galerkin_entries(cf, F.n, M.n, i, j, o);
+      C[t] = vt<VT>(o[0]);
+      E[t] = vt<VT>(o[1]);
+      Nn[t] = vt<VT>(o[2]);
+      NE[t] = vt<VT>(o[3]);
+      ID[t] = vt<VT>(1.0 / o[0]);
+    }
+    __syncthreads();
+  }
+}
+
 // LDS pitches are compile-time constants (LP = CW + 2 for the grid, TP for
 // the tables) so that every per-node LDS offset folds into the instruction's
 // immediate offset instead of occupying a register.
@@ -517,7 +582,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate, thread-private [k][tid] layout
   double* Pv = Bv + 2 * FS;                  // previous increment (extrapolated start)
   double* Qv = Pv + FS;                      // Picard: increment of the last fixed-point iterate
-  double* Tslot = Qv + FS;                   // Picard: this instance's FP64 tables (K re-assembled)
+  VT* Dv = reinterpret_cast<VT*>(Qv + FS);   // per-node D^{-1/2}, thread-private [k][tid] layout
+  double* Tslot = Qv + 2 * FS;               // Picard: this instance's FP64 tables (K re-assembled)
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   int slot = 0;
 
@@ -604,50 +670,11 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     dmin = (double)__int_as_float(s_dmin) * 0.999;
     floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
     if constexpr (MG) {
-      // Galerkin coarse operators A_l = P^T A_{l-1} P of the scaled system
-      for (int l = 1; l <= mg.nlev; ++l) {
-        const MGLevel& M = mg.lv[l];
-        const MGLevel& F = mg.lv[l - 1];
-        const int pl = M.RW * M.RH;
-        VT* C = ctab + M.tab_off;
-        VT* E = C + pl;
-        VT* Nn = E + pl;
-        VT* NE = Nn + pl;
-        VT* ID = NE + pl;
-        const int fp = l == 1 ? TP : F.RW;
-        const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
-        const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
-        const VT* fN = l == 1 ? tN : fE + F.RW * F.RH;
-        const VT* fNE = l == 1 ? tNE : fN + F.RW * F.RH;
-        auto cf = [&](int fi, int fj, int d) -> double {
-          if (!(fi >= F.bx0 && fi < F.lx1 && fj >= F.by0 && fj < F.ly1)) {
-            if (d == 0) return 1.0;
-            return d <= 4 ? -0.25 : 0.0;
-          }
-          const int t = (fj - F.by0 + 1) * fp + (fi - F.bx0 + 1);
-          switch (d) {
-            case 0: return fC ? (double)fC[t] : 1.0;
-            case 1: return (double)fE[t];
-            case 2: return (double)fE[t - 1];
-            case 3: return (double)fN[t];
-            case 4: return (double)fN[t - fp];
-            case 5: return (double)fNE[t];
-            default: return (double)fNE[t - fp - 1];
-          }
-        };
-        for (int t = tid; t < pl; t += NT) {
-          const int i = M.bx0 - 1 + t % M.RW, j = M.by0 - 1 + t / M.RW;
-          const bool box = i >= M.bx0 && i < M.bx1 && j >= M.by0 && j < M.by1;
-          double o[4] = {1.0, -0.25, -0.25, 0.0};
-          if (box) galerkin_entries(cf, F.n, M.n, i, j, o);
-          C[t] = vt<VT>(o[0]);
-          E[t] = vt<VT>(o[1]);
-          Nn[t] = vt<VT>(o[2]);
-          NE[t] = vt<VT>(o[3]);
-          ID[t] = vt<VT>(1.0 / o[0]);
-        }
-        __syncthreads();
-      }
+      // Galerkin hierarchy of the scaled system: the D^{1/2} P transfers of the
+      // streaming path need D per node inside the V-cycle, which costs more
+      // here (registers, global loads) than the ~5% of iterations it saves
+      auto dnf = [&](int i, int j) -> double { return (double)vt<VT>(dscale(i, j)); };
+      build_galerkin<VT>(mg, ctab, tE, tN, tNE, dnf, false, d_air, TP, tid, NT);
     }
     };
     for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
@@ -696,20 +723,33 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       }
       __syncthreads();
     };
-    if constexpr (!NL) build_tables();
     // per-node D^{-1/2} (box: from the FP64 tables; elsewhere the air value),
-    // rounded to VT like the scaled system it multiplies
-    auto DN = [&](int k) -> double {
-      if (!INBOX(k)) return (double)vt<VT>(d_air);
-      const int t = t0 + k * g.RW;
-      return (double)vt<VT>(1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]));
+    // rounded to VT like the scaled system it multiplies; computed once per
+    // table build into the thread's own entries of Dv
+    auto fill_dn = [&]() {
+#pragma unroll 1
+      for (int k = 0; k < SH; ++k) {
+        if (!ACT(k)) continue;
+        VT d = vt<VT>(d_air);
+        if (INBOX(k)) {
+          const int t = t0 + k * g.RW;
+          d = vt<VT>(1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]));
+        }
+        Dv[k * NT + tid] = d;
+      }
     };
+    if constexpr (!NL) {
+      build_tables();
+      fill_dn();
+    }
+    auto DN = [&](int k) -> double { return (double)Dv[k * NT + tid]; };
 
     double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0, pic_total = 0;
     // per-phase device wall-clock ticks (thread 0): fine V-cycle descent,
-    // coarse levels, fine ascent, CG apply + reductions
-    unsigned long long ph[4] = {0, 0, 0, 0};
+    // coarse levels, fine ascent, CG apply + reductions; right-hand side,
+    // refinement residuals, increment updates, QoI + state update
+    unsigned long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long tmark = 0;
     auto tick = [&](int q) __attribute__((always_inline)) {
       if (tid == 0) {
@@ -725,9 +765,11 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         const double Jt = in.src[kseg0 + step + 1];
         int pic_it = 0;
         for (;;) {  // Picard iterations (a single pass for linear materials)
+        tick(-1);
         if constexpr (NL) {
           assemble_K();
           build_tables();
+          fill_dn();
         }
         // b = J(t_{k+1}) S - K a and ||b||^2
         double part[1] = {0.0};
@@ -741,6 +783,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           }
         }
         block_sum<1, NWAVES>(part, red, slot);
+        tick(4);
         const double bb = part[0];
         int it_step = 0;
         if (bb == 0.0) {
@@ -752,6 +795,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           bool conv = false;
           for (int sweep = 0; sweep <= sv.max_sweeps; ++sweep) {
             // FP64 residual of the current increment; its scaled copy goes to LDS
+            tick(-1);
             double rr[1] = {0.0};
 #pragma unroll 1
             for (int k = 0; k < SH; ++k) {
@@ -763,6 +807,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
               }
             }
             block_sum<1, NWAVES>(rr, red, slot);  // barrier: LDS residual complete
+            tick(5);
             if (!(rr[0] == rr[0]) || isinf(rr[0])) {
               flags |= FLAG_FAILED;
               break;
@@ -1058,10 +1103,12 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
             for (int k = 0; k < SH; ++k)
               if (ACT(k)) rl[l0 + k * LP] = y[k];
             }
+            tick(-1);
 #pragma unroll 1
             for (int k = 0; k < SH; ++k)
               if (ACT(k)) Xv[gi0 + k * g.P] += DN(k) * (double)rl[l0 + k * LP];
             __syncthreads();
+            tick(6);
           }
           if (!conv) flags |= FLAG_NOT_CONVERGED;
         }
@@ -1090,6 +1137,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         }
         pic_total += pic_it;
         // Joule-loss term d^T M d / dt and the state update a += d
+        tick(-1);
         double qq[1] = {0.0};
 #pragma unroll 1
         for (int k = 0; k < SH; ++k) {
@@ -1111,6 +1159,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           }
         }
         __syncthreads();
+        tick(7);
       }
       if (in.n_chain > 0) {
         // Parareal coarse chain: A holds C(U_{n-1}); U_n = F_n + (C_new - C_old_n)
@@ -1159,8 +1208,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         in.stat[5] = (int)(t_begin >> 32);
         in.stat[6] = (int)(t_end & 0xffffffffull);
         in.stat[7] = (int)(t_end >> 32);
-        for (int q = 0; q < 4; ++q) in.stat[8 + q] = (int)(ph[q] >> 4);  // units of 16 ticks
-        in.stat[12] = pic_total;
+        for (int q = 0; q < 8; ++q) in.stat[8 + q] = (int)(ph[q] >> 4);  // units of 16 ticks
+        in.stat[16] = pic_total;
       }
     }
     __syncthreads();
@@ -1607,76 +1656,6 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
          tNE[t - g.RW - 1] * R[gi - P - 1];
 }
 
-// Galerkin coarse operators for levels 1..nlev into ctab (5 planes per level:
-// C, E, N, NE, 1/C).  The fine level's couplings are those of the scaled
-// system D^{-1/2} A D^{-1/2} (fE, fN, fNE, pitch fpitch, unit diagonal).
-// With fD (D^{-1/2} per node of the table region, pitch fpitch; d_air
-// elsewhere) level 1 is P^T A P of the unscaled A, i.e. the interpolation
-// from level 1 to the scaled fine level is D^{1/2} P: the coarse space then
-// holds the smooth functions of A rather than of the scaled system, whose
-// scaling jumps across the conductor boundary.  Without fD it is P^T Ahat P.
-template <typename VT>
-__device__ void build_galerkin(const MGGeom& mg, VT* ctab, const VT* tE, const VT* tN, const VT* tNE,
-                               const VT* fD, double d_air, int fpitch, int tid, int nthr) {
-  const double air = fD ? 1.0 / (d_air * d_air) : 1.0;  // air diagonal of the coarse levels
-  for (int l = 1; l <= mg.nlev; ++l) {
-    const MGLevel& M = mg.lv[l];
-    const MGLevel& F = mg.lv[l - 1];
-    const int pl = M.RW * M.RH;
-    VT* C = ctab + M.tab_off;
-    VT* E = C + pl;
-    VT* Nn = E + pl;
-    VT* NE = Nn + pl;
-    VT* ID = NE + pl;
-    const int fp = l == 1 ? fpitch : F.RW;
-    const VT* fC = l == 1 ? nullptr : ctab + F.tab_off;
-    const VT* fE = l == 1 ? tE : fC + F.RW * F.RH;
-    const VT* fN = l == 1 ? tN : fE + F.RW * F.RH;
-    const VT* fNE = l == 1 ? tNE : fN + F.RW * F.RH;
-    const double air_below = l == 1 ? 1.0 : air;
-    auto cs = [&](int fi, int fj, int d) -> double {  // coupling of the level below
-      if (!(fi >= F.bx0 && fi < F.lx1 && fj >= F.by0 && fj < F.ly1)) {
-        if (d == 0) return air_below;
-        return d <= 4 ? -0.25 * air_below : 0.0;
-      }
-      const int t = (fj - F.by0 + 1) * fp + (fi - F.bx0 + 1);
-      switch (d) {
-        case 0: return fC ? (double)fC[t] : 1.0;
-        case 1: return (double)fE[t];
-        case 2: return (double)fE[t - 1];
-        case 3: return (double)fN[t];
-        case 4: return (double)fN[t - fp];
-        case 5: return (double)fNE[t];
-        default: return (double)fNE[t - fp - 1];
-      }
-    };
-    const bool unscale = l == 1 && fD;
-    auto dn = [&](int fi, int fj) -> double {  // fine D^{-1/2}
-      if (fi >= F.bx0 - 1 && fi <= F.bx1 && fj >= F.by0 - 1 && fj <= F.by1)
-        return (double)fD[(fj - F.by0 + 1) * fp + (fi - F.bx0 + 1)];
-      return d_air;
-    };
-    auto cf = [&](int fi, int fj, int d) -> double {
-      const double c = cs(fi, fj, d);
-      if (!unscale) return c;
-      const int OXd[7] = {0, 1, -1, 0, 0, 1, -1}, OYd[7] = {0, 0, 0, 1, -1, 1, -1};
-      return c / (dn(fi, fj) * dn(fi + OXd[d], fj + OYd[d]));
-    };
-    for (int t = tid; t < pl; t += nthr) {
-      const int i = M.bx0 - 1 + t % M.RW, j = M.by0 - 1 + t / M.RW;
-      const bool box = i >= M.bx0 && i < M.bx1 && j >= M.by0 && j < M.by1;
-      double o[4] = {air, -0.25 * air, -0.25 * air, 0.0};
-      if (box) galerkin_entries(cf, F.n, M.n, i, j, o);
-      C[t] = vt<VT>(o[0]);
-      E[t] = vt<VT>(o[1]);
-      Nn[t] = vt<VT>(o[2]);
-      NE[t] = vt<VT>(o[3]);
-      ID[t] = vt<VT>(1.0 / o[0]);
-    }
-    __syncthreads();
-  }
-}
-
 // Per-slot VT workspace of the streaming kernel: six full-grid vectors, the
 // four scaled table planes over the box region and, with multigrid, the
 // coarse-level vectors and Galerkin tables.
@@ -1766,7 +1745,12 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
     const double dmin = (double)__int_as_float(s_dmin) * 0.999;
     const double floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
     if constexpr (MG) {
-      build_galerkin<VT>(mg, ctab, tE, tN, tNE, tD, d_air, g.RW, tid, NT);
+      auto dn = [&](int i, int j) -> double {  // fine D^{-1/2} (table region, else air)
+        if (i >= g.bx0 - 1 && i <= g.bx1 && j >= g.by0 - 1 && j <= g.by1)
+          return (double)tD[(j - g.by0 + 1) * g.RW + (i - g.bx0 + 1)];
+        return d_air;
+      };
+      build_galerkin<VT>(mg, ctab, tE, tN, tNE, dn, true, d_air, g.RW, tid, NT);
       for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, mgreg, ctab, NT), tid, NT);
       __syncthreads();
     }

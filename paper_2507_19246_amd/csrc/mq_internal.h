@@ -40,9 +40,10 @@ enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
 __host__ __device__ inline size_t tab_stride(const Geom& g) { return (size_t)T_NPLANES * g.RW * g.RH + 4; }
 // doubles per slot of the time-stepping work buffer: state a, increment x,
 // right-hand side b, one plane for the VT iterate, previous increment,
-// Picard increment, then the instance's FP64 tables (planes + k1', k2', k3')
+// Picard increment, per-node D^{-1/2}, then the instance's FP64 tables
+// (planes + k1', k2', k3')
 __host__ __device__ inline size_t ie_work_doubles(const Geom& g) {
-  return 6 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
+  return 7 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
 }
 
 // Element data over the cells that touch the box: full-grid cells
@@ -62,7 +63,7 @@ struct Inst {
   double* q_out;         // receives q_scale * sum_k d_k^T M d_k / dt
   double q_scale;
   int* stat;             // [STAT_N]: inner iterations, sweeps, max inner per step, flags,
-                         // device wall-clock start (lo, hi) and end (lo, hi), four
+                         // device wall-clock start (lo, hi) and end (lo, hi), eight
                          // phase-time counters (units of 16 wall-clock ticks), Picard
                          // iterations
   double dt;
@@ -115,7 +116,7 @@ struct Solver {
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
-enum { STAT_N = 13 };
+enum { STAT_N = 17 };
 
 // Launch helpers implemented in the .hip translation units.
 // tile: resident workgroup shape (1: 16 rows per thread, 2: 32 rows per thread)
