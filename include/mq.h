@@ -107,6 +107,9 @@ typedef struct mq_problem_desc {
                         64..127 interior nodes per side; others use 1).  Streaming path: 1 = one
                         1024-thread workgroup per compute unit, 2 = two 512-thread workgroups */
   double mg_omega;   /* damped-Jacobi weight of the multigrid smoother (0: 0.8) */
+  int32_t mg_levels; /* coarse levels in use (0: all, down to one node) */
+  int32_t mg_coarse_sweeps; /* damped-Jacobi sweeps after Z = diag^{-1} R at the coarsest level
+                               in use (0..64) */
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;

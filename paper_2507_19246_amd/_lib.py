@@ -42,6 +42,7 @@ class ProblemDesc(C.Structure):
         ("tol", C.c_double), ("inner_rtol", C.c_double),
         ("max_iter", C.c_int32), ("max_sweeps", C.c_int32),
         ("precond", C.c_int32), ("tile", C.c_int32), ("mg_omega", C.c_double),
+        ("mg_levels", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
     ]
 
 

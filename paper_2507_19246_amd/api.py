@@ -39,6 +39,8 @@ def default_desc(problem, precision: int, path: int = L.MQ_PATH_AUTO, **solver) 
     d.max_iter, d.max_sweeps = sv["max_iter"], sv["max_sweeps"]
     d.precond = sv.get("precond", L.MQ_PRECOND_AUTO)
     d.tile = sv.get("tile", 0)
+    d.mg_levels = sv.get("mg_levels", 0)
+    d.mg_coarse_sweeps = sv.get("mg_coarse_sweeps", 0)
     d.mg_omega = sv.get("mg_omega", 0.0)
     return d
 

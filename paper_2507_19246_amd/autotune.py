@@ -10,7 +10,9 @@ candidate of:
 * ``mg_omega``: the damped-Jacobi weight of the multigrid smoother,
 * ``inner_rtol``: the relative tolerance of the inner CG (mixed precision),
 
-and keeps the fastest candidate whose QoIs agree with the default
+then, for the best multigrid candidate, the depth of the coarse hierarchy
+(``mg_levels``) and the damped-Jacobi sweeps at its coarsest level
+(``mg_coarse_sweeps``), and keeps the fastest candidate whose QoIs agree with the default
 configuration's within the precision's tolerance (1e-6 mixed, 1e-10 FP64).
 The outer tolerance, and so the accuracy of every result, is never tuned.
 
@@ -66,6 +68,16 @@ def candidates(problem, precision: int) -> List[Dict]:
     return out
 
 
+# second stage: coarse-hierarchy variants (levels in use, coarsest sweeps)
+COARSE_VARIANTS = [(3, 4), (3, 6), (3, 8), (4, 2), (4, 4)]
+
+
+def coarse_candidates(best_knobs: Dict, resolved_precond: int) -> List[Dict]:
+    if resolved_precond != L.MQ_PRECOND_MULTIGRID:
+        return []
+    return [dict(best_knobs, mg_levels=lv, mg_coarse_sweeps=sw) for lv, sw in COARSE_VARIANTS]
+
+
 def _load(path: str) -> Dict:
     try:
         with open(path) as f:
@@ -105,13 +117,14 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
     gen = torch.Generator().manual_seed(99)
     xi = torch.randn(n_samples, n_xi, generator=gen, dtype=torch.float64).to("cuda")
     tol = QOI_AGREEMENT[precision]
-    ref_q = None
+    ref_q = [None]
     trials = []
-    for knobs in [{}] + candidates(problem, precision):
+
+    def trial(knobs):
         try:
             p = mq.Problem(problem, precision, **knobs)
         except L.MQError:
-            continue  # this combination does not exist for the mesh (e.g. no room in LDS)
+            return  # this combination does not exist for the mesh (e.g. no room in LDS)
         mq.mlmc_level_run(p, steps_per_period, 0, n_periods, xi[:8])  # warm-up (code objects)
         dt = float("inf")
         for _ in range(2):  # best kernel time of two runs
@@ -120,15 +133,20 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
         qh = q.cpu().numpy()
         info = {"tile": p.info.tile, "precond": p.info.precond, "block": p.info.block}
         p.close()
-        if ref_q is None:
-            ref_q = qh
-        agree = bool(np.all(np.abs(qh - ref_q) <= tol * np.abs(ref_q))) and rc == 0
+        if ref_q[0] is None:
+            ref_q[0] = qh
+        agree = bool(np.all(np.abs(qh - ref_q[0]) <= tol * np.abs(ref_q[0]))) and rc == 0
         rate = st["sample_steps"] / dt
         trials.append({"knobs": knobs, "rate": rate, "agree": agree, "resolved": info})
         if verbose:
             print(f"autotune {key} {knobs} -> {rate:.0f} sample-steps/s agree={agree}", flush=True)
-    ok = [t for t in trials if t["agree"]]
-    best = max(ok, key=lambda t: t["rate"])
+
+    for knobs in [{}] + candidates(problem, precision):
+        trial(knobs)
+    best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
+    for knobs in coarse_candidates(best["knobs"], best["resolved"]["precond"]):
+        trial(knobs)
+    best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
     db = _load(path)
     db[key] = {"knobs": best["knobs"], "rate": best["rate"], "default_rate": trials[0]["rate"],
                "resolved": best["resolved"], "trials": len(trials),

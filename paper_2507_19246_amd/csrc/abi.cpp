@@ -45,6 +45,8 @@ Solver solver_of(const mq_problem* p) {
   sv.picard_tol = p->d.picard_tol;
   sv.picard_max = p->d.picard_max;
   sv.tile = p->tile;
+  sv.mg_levels = p->d.mg_levels;
+  sv.mg_coarse_sweeps = p->d.mg_coarse_sweeps;
   return sv;
 }
 
@@ -126,6 +128,8 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->precond < 0 || d->precond > 2) return fail(MQ_ERR_INVALID_ARG, "unknown preconditioner");
   if (!(d->mg_omega >= 0) || !(d->mg_omega < 1)) return fail(MQ_ERR_INVALID_ARG, "mg_omega must be in [0, 1)");
   if (d->tile < 0 || d->tile > 2) return fail(MQ_ERR_INVALID_ARG, "tile must be 0, 1 or 2");
+  if (d->mg_levels < 0 || d->mg_coarse_sweeps < 0 || d->mg_coarse_sweeps > 64)
+    return fail(MQ_ERR_INVALID_ARG, "mg_levels >= 0 and 0 <= mg_coarse_sweeps <= 64 required");
   return MQ_OK;
 }
 

@@ -393,16 +393,35 @@ __device__ inline void c_zero_halo(const CLev<VT>& L, int me, int nthr) {
   }
 }
 
-// Coarse part of the V(1,1) cycle: levels 1..nlev, R_1 and Z_1 = om ID R_1
-// already in place.  Levels with n >= 31 use the whole workgroup, smaller
-// ones run on wave 0 alone.  Output: T_1 (or Z_1 if level 1 is the coarsest).
+// Damped-Jacobi sweeps Z <- Z + om ID (R - A Z) at the coarsest level in
+// use; returns the vector that holds the result (Z and T alternate).
+template <typename VT, class SYNC>
+__device__ __attribute__((always_inline)) inline const VT* c_coarsest(CLev<VT> C, VT om, int sweeps, int me, int nthr, SYNC sync) {
+  for (int s = 0; s < sweeps; ++s) {
+    c_post(C, om, me, nthr);
+    sync();
+    VT* t = C.Z;
+    C.Z = C.T;
+    C.T = t;
+  }
+  return C.Z;
+}
+
+// Coarse part of the V(1,1) cycle over levels 1..L (L = min(nlev, lmax) when
+// lmax > 0), R_1 and Z_1 = om ID R_1 (ID R_1 if L = 1) already in place.  At
+// level L, Z_L = ID R_L followed by `csweeps` damped-Jacobi sweeps (exact when
+// level L is the single-node level).  Levels with n >= 31 use the whole
+// workgroup, smaller ones run on wave 0 alone.  Returns level 1's corrected
+// vector.
 template <typename VT, int NT>
-__device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
-                                    VT air = VT(1)) {
-  const int L = mg.nlev;
+__device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
+                                         VT air = VT(1), int lmax = 0, int csweeps = 0) {
+  const int L = (lmax > 0 && lmax < mg.nlev) ? lmax : mg.nlev;
   auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= 31; };
+  auto bsync = [] { __syncthreads(); };
   int lb = 0;  // last block level
   while (lb + 1 <= L && is_block(lb + 1)) ++lb;
+  const VT* zL = nullptr;
   // block levels: descent
   for (int l = 1; l <= lb && l < L; ++l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
@@ -412,35 +431,44 @@ __device__ inline void coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab
     c_restrict(F, Cc, om, l + 1 == L, tid, NT);
     __syncthreads();
   }
+  if (lb == L) zL = c_coarsest(clev<VT>(mg, L, region, ctab, NT, air), om, csweeps, tid, NT, bsync);
   // wave levels
-  if (lb < L && tid < 64) {
-    for (int l = lb + 1; l < L; ++l) {
-      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
-      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
-      c_resid(F, tid, 64);
-      wave_sync();
-      c_restrict(F, Cc, om, l + 1 == L, tid, 64);
-      wave_sync();
+  if (lb < L) {
+    if (tid < 64) {
+      for (int l = lb + 1; l < L; ++l) {
+        const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
+        const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
+        c_resid(F, tid, 64);
+        wave_sync();
+        c_restrict(F, Cc, om, l + 1 == L, tid, 64);
+        wave_sync();
+      }
+      zL = c_coarsest(clev<VT>(mg, L, region, ctab, 64, air), om, csweeps, tid, 64, wave_sync);
+      for (int l = L - 1; l > lb; --l) {
+        const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
+        const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
+        c_prolong(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, 64);
+        wave_sync();
+        c_post(F, om, tid, 64);
+        wave_sync();
+      }
+    } else {
+      // the other waves only need the pointer: the same alternation as wave 0
+      CLev<VT> C = clev<VT>(mg, L, region, ctab, 64, air);
+      zL = (csweeps & 1) ? C.T : C.Z;
     }
-    for (int l = L - 1; l > lb; --l) {
-      const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
-      const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
-      c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, 64);
-      wave_sync();
-      c_post(F, om, tid, 64);
-      wave_sync();
-    }
+    __syncthreads();
   }
-  if (lb < L) __syncthreads();
   // block levels: ascent
   for (int l = (lb < L ? lb : L - 1); l >= 1; --l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
     const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
-    c_prolong(F, l + 1 == L ? Cc.Z : Cc.T, Cc.np, tid, NT);
+    c_prolong(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, NT);
     __syncthreads();
     c_post(F, om, tid, NT);
     __syncthreads();
   }
+  return L == 1 ? zL : clev<VT>(mg, 1, region, ctab, NT, air).T;
 }
 
 // Galerkin coarse entries A_c(c, c + D) = (P e_c)^T A_f (P e_{c+D}) for
@@ -914,7 +942,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 }
                 __syncthreads();
                 for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, rl, ctab, NT), tid, NT);
-                const bool exact1 = mg.nlev == 1;
+                const bool exact1 = mg.nlev == 1 || sv.mg_levels == 1;
 #pragma unroll
                 for (int m = 0; m < CR; ++m) {
                   const int j = jb1 + m * ty1;
@@ -926,9 +954,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 }
                 __syncthreads();
                 tick(0);
-                coarse_cycle<VT, NT>(mg, rl, ctab, om, tid);
+                const VT* z1 = coarse_cycle<VT, NT>(mg, rl, ctab, om, tid, VT(1), sv.mg_levels, sv.mg_coarse_sweeps);
                 tick(1);
-                const VT* z1 = exact1 ? L1.Z : L1.T;
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
                   zv[k] = ACT(k) ? om * rv[k] + prolong_at(z1, L1.np, ci, j0 + k) : VT(0);
@@ -1820,7 +1847,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
               // level through D^{1/2} P (air diagonal 4 nu_air = 1 / d_air^2)
               const VT air = vt<VT>(1.0 / (d_air * d_air));
               const CLev<VT> L1 = clev<VT>(mg, 1, mgreg, ctab, NT, air);
-              const bool exact1 = mg.nlev == 1;
+              const bool exact1 = mg.nlev == 1 || sv.mg_levels == 1;
               double rho = 1.0, stop = 0.0;
               for (;;) {
                 // z = B r: pre-smoothing from zero (z = om r) and t = r - A z
@@ -1842,9 +1869,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                   }
                 }
                 __syncthreads();
-                coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air);
+                const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps);
                 __syncthreads();
-                const VT* z1 = exact1 ? L1.Z : L1.T;
                 nodes([&](int i, int j, const NodeRef& nr) {
                   Zm[nr.gi] += prolong_at(z1, L1.np, i, j) / dnode(i, j, nr);
                 });

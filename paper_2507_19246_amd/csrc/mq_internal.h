@@ -113,6 +113,8 @@ struct Solver {
   double picard_tol;
   int picard_max;
   int tile;        // resident workgroup shape (host-side dispatch)
+  int mg_levels;   // coarse levels in use (0: all)
+  int mg_coarse_sweeps;  // damped-Jacobi sweeps at the coarsest level in use
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };

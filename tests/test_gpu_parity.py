@@ -121,6 +121,25 @@ def test_mixed_kl_coupled_level(n, path, pc, tile):
     p.close()
 
 
+@pytest.mark.parametrize("n,path,levels,sweeps", [(65, 1, 2, 4), (65, 1, 3, 0), (65, 2, 2, 6), (33, 1, 1, 8)])
+def test_mg_truncated_hierarchy(n, path, levels, sweeps):
+    """Multigrid with a capped coarse hierarchy and damped-Jacobi sweeps at its
+    coarsest level (both paths): Q within 1e-6 of the oracle."""
+    mq, L = mqmod()
+    prob = W.Problem(n, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 24, 1, range(4), 8)
+    say(f"truncated mg n={n} path={path} levels={levels} sweeps={sweeps}")
+    p = mq.Problem(prob, L.MQ_PREC_MIXED, path=path, precond=L.MQ_PRECOND_MULTIGRID,
+                   mg_levels=levels, mg_coarse_sweeps=sweeps)
+    qf, _, _, rc, st = mq.mlmc_level_run(p, 32, 0, 2, xi)
+    assert rc == 0
+    rf, _ = oracle_q(prob, xi, 32, 2)
+    err = np.max(np.abs(qf.cpu().numpy() - rf) / np.abs(rf))
+    say("max rel err", err, "iters/step", st["inner_iters"] / st["sample_steps"])
+    assert err <= 1e-6
+    p.close()
+
+
 def test_streaming_fp64_matches_oracle():
     mq, L = mqmod()
     w = W.plain_fp64_33()
