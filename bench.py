@@ -324,30 +324,30 @@ def bench_nonlinear(args, mq, L, W, np, torch):
     return res
 
 
-def bench_serving(args, mq, L, W, np, torch):
-    """Poisson request stream into the continuous-batching server."""
-    reqs = W.serving_stream(args.requests, rate_hz=args.rate)
+def _serve(mq, L, W, np, torch, reqs, limit_s, label):
+    """Submit `reqs` at their arrival times into a fresh server; wait for all results."""
     base = W.Problem(65, W.Material(kind=W.MAT_KL))
     srv = mq.Server(base, L.MQ_PREC_MIXED, hbm_budget_bytes=96 << 30, max_inflight=4096, n_streams=2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tickets, done = {}, {}
-    i = 0
     t_report = t0
+    done = {}
+    i = 0
     while len(done) < len(reqs):
         now = time.perf_counter() - t0
         while i < len(reqs) and reqs[i].arrival_s <= now:
             r = reqs[i]
-            tickets[srv.submit(r.n_nodes, r.steps_per_period, r.n_periods, r.xi, user_id=i)] = i
+            srv.submit(r.n_nodes, r.steps_per_period, r.n_periods, r.xi, user_id=i)
             i += 1
         for r in srv.poll(1024):
             done[r.ticket] = r
         if time.perf_counter() - t_report > 10.0:
             t_report = time.perf_counter()
-            print(f"serving: {i} submitted, {len(done)} done, {t_report - t0:.0f} s", file=sys.stderr, flush=True)
-        if time.perf_counter() - t0 > args.serving_limit_s:
+            print(f"serving ({label}): {i} submitted, {len(done)} done, {t_report - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+        if time.perf_counter() - t0 > limit_s:
             srv.close()
-            raise RuntimeError(f"serving run exceeded {args.serving_limit_s} s ({len(done)} of {len(reqs)} done)")
+            raise RuntimeError(f"serving run exceeded {limit_s} s ({len(done)} of {len(reqs)} done)")
         time.sleep(0.0005)
     elapsed = time.perf_counter() - t0
     srv.close()
@@ -355,22 +355,37 @@ def bench_serving(args, mq, L, W, np, torch):
     steps = sum(reqs[r.user_id].steps_per_period * reqs[r.user_id].n_periods for r in done.values())
     by_mesh = {}
     for r in done.values():
-        q = reqs[r.user_id]
-        by_mesh.setdefault(q.n_nodes, []).append((r.t_done_ns - r.t_submit_ns) / 1e6)
-    bad = sum(1 for r in done.values() if r.status < 0)
+        by_mesh.setdefault(reqs[r.user_id].n_nodes, []).append((r.t_done_ns - r.t_submit_ns) / 1e6)
+    return {
+        "sample_steps_per_s": steps / elapsed, "requests_per_s": len(done) / elapsed, "wall_s": elapsed,
+        "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+        "failed": sum(1 for r in done.values() if r.status < 0),
+        "latency_ms_by_mesh": {str(k): {"n": len(v), "p50": float(np.percentile(v, 50)),
+                                        "p99": float(np.percentile(v, 99))} for k, v in sorted(by_mesh.items())},
+    }
+
+
+def bench_serving(args, mq, L, W, np, torch):
+    """Poisson request stream into the continuous-batching server: the offered
+    rate (saturating), then a stable load at 0.7 x the measured capacity."""
+    reqs = W.serving_stream(args.requests, rate_hz=args.rate)
+    sat = _serve(mq, L, W, np, torch, reqs, args.serving_limit_s, "offered rate")
     args.steps, args.warmup = 1, 0
-    res = _contract("sample-steps/s", steps / elapsed, elapsed, args, {
+    res = _contract("sample-steps/s", sat["sample_steps_per_s"], sat["wall_s"], args, {
         "workload": f"serving-kl8-mixed-{len(reqs)}req-{args.rate:g}rps",
         "meshes": list(W.SERVING_MESHES), "mesh_weights": list(W.SERVING_MESH_WEIGHTS),
         "steps_per_period": list(W.SERVING_STEPS), "n_periods": 2, "requests": len(reqs),
         "rate_req_per_s": args.rate, "lanes_per_mesh": 2, "chunk_steps": 32})
-    res.update({
-        "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
-        "requests_per_s": len(done) / elapsed, "failed": bad,
-        "latency_ms_by_mesh": {str(k): {"n": len(v), "p50": float(np.percentile(v, 50)),
-                                        "p99": float(np.percentile(v, 99))} for k, v in sorted(by_mesh.items())},
-        "roofline": None, "cpu_baseline": None,
-    })
+    res.update({k: sat[k] for k in ("p50_latency_ms", "p99_latency_ms", "requests_per_s", "failed",
+                                    "latency_ms_by_mesh")})
+    if args.stable_requests > 0:
+        rate = 0.7 * sat["requests_per_s"]
+        st = _serve(mq, L, W, np, torch, W.serving_stream(args.stable_requests, rate_hz=rate),
+                    args.serving_limit_s, "stable load")
+        st["rate_req_per_s"] = rate
+        st["requests"] = args.stable_requests
+        res["stable_load"] = st
+    res.update({"roofline": None, "cpu_baseline": None})
     return res
 
 
@@ -388,6 +403,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
     ap.add_argument("--no-serial", action="store_true", help="parareal: skip the batched serial comparison run")
+    ap.add_argument("--stable-requests", type=int, default=64,
+                    help="serving: requests of the stable-load run at 0.7 x the measured capacity (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

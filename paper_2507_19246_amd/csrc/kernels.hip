@@ -1684,10 +1684,11 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
 }
 
 // Per-slot VT workspace of the streaming kernel: six full-grid vectors, the
-// four scaled table planes over the box region and, with multigrid, the
+// five table planes over the box region (scaled E, N, NE, D^{-1/2}, D^{1/2})
+// and, with multigrid, the
 // coarse-level vectors and Galerkin tables.
 __host__ __device__ inline size_t stream_slot_elems(const Geom& g, const MGGeom& mg, bool use_mg) {
-  size_t e = 6 * (size_t)g.N * g.P + 4 * (size_t)g.RW * g.RH;
+  size_t e = 6 * (size_t)g.N * g.P + 5 * (size_t)g.RW * g.RH;
   if (use_mg) e += (size_t)mg.region_elems + (size_t)mg.ctab_elems;
   return e;
 }
@@ -1717,7 +1718,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
   VT* tN = tE + RHW;
   VT* tNE = tN + RHW;
   VT* tD = tNE + RHW;
-  VT* mgreg = tD + RHW;              // multigrid: coarse vectors (zero halo)
+  VT* tDi = tD + RHW;                // D^{1/2}
+  VT* mgreg = tDi + RHW;             // multigrid: coarse vectors (zero halo)
   VT* ctab = mgreg + mg.region_elems;  // multigrid: Galerkin tables
   // fine-level thread grid: 2^fs columns x (NT >> fs) rows, no divisions
   int fs = 0;
@@ -1761,9 +1763,10 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
       tN[t] = (VT)nn;
       tNE[t] = (VT)ne;
       tD[t] = (VT)di;
+      tDi[t] = (VT)(1.0 / di);
     }
-    for (int idx = tid; idx < nd; idx += NT) {
-      const int gi = (idx / n + 1) * g.P + idx % n + 1;
+    for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+      const int gi = (j + 1) * g.P + i + 1;
       Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
       Xv[gi] = in.carry_in ? in.carry[gi] : 0.0;
       Xprev[gi] = in.carry_in ? in.carry[FS + gi] : 0.0;
@@ -1785,6 +1788,10 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
       return box ? tD[nr.t] : (VT)d_air;
     };
+    auto dnode_inv = [&](int i, int j, const NodeRef& nr) -> VT {  // D^{1/2}
+      const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+      return box ? tDi[nr.t] : (VT)(1.0 / d_air);
+    };
 
     double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
     int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
@@ -1794,8 +1801,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
       for (int step = 0; step < in.n_steps; ++step) {
         const double Jt = in.src[kseg0 + step + 1];
         double part[1] = {0.0};
-        for (int idx = tid; idx < nd; idx += NT) {
-          const NodeRef nr = node_ref(g, idx % n, idx / n);
+        for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+          const NodeRef nr = node_ref(g, i, j);
           const double b = Jt * S[nr.gi] - K_apply(g, tab, Av, nr);
           Bv[nr.gi] = b;
           part[0] += b * b;
@@ -1804,14 +1811,13 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
         const double bb = part[0];
         int it_step = 0;
         if (bb == 0.0) {
-          for (int idx = tid; idx < nd; idx += NT) Xv[(idx / n + 1) * g.P + idx % n + 1] = 0.0;
+          for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) Xv[(j + 1) * g.P + i + 1] = 0.0;
           __syncthreads();
         } else {
           bool conv = false;
           for (int sweep = 0; sweep <= sv.max_sweeps; ++sweep) {
             double rr[1] = {0.0};
-            for (int idx = tid; idx < nd; idx += NT) {
-              const int i = idx % n, j = idx / n;
+            for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
               const NodeRef nr = node_ref(g, i, j);
               const double res = Bv[nr.gi] - A_apply(g, tab, Xv, nr, inv_dt);
               rr[0] += res * res;
@@ -1854,7 +1860,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 nodes([&](int i, int j, const NodeRef& nr) {
                   const VT r = Rv[nr.gi];
                   Zm[nr.gi] = om * r;
-                  Tm[nr.gi] = (r - om * stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr)) / dnode(i, j, nr);
+                  Tm[nr.gi] = (r - om * stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr)) * dnode_inv(i, j, nr);
                 });
                 __syncthreads();
                 {  // restriction to level 1
@@ -1872,7 +1878,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps);
                 __syncthreads();
                 nodes([&](int i, int j, const NodeRef& nr) {
-                  Zm[nr.gi] += prolong_at(z1, L1.np, i, j) / dnode(i, j, nr);
+                  Zm[nr.gi] += prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr);
                 });
                 __syncthreads();
                 // post-smoothing z <- z + om (r - A z); r.z and r.r of the new z
@@ -1917,8 +1923,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
               }
             } else {
             double gd[2] = {0.0, 0.0};
-            for (int idx = tid; idx < nd; idx += NT) {
-              const NodeRef nr = node_ref(g, idx % n, idx / n);
+            for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+              const NodeRef nr = node_ref(g, i, j);
               const VT w = stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr);
               const VT r = Rv[nr.gi];
               Wv[nr.gi] = w;
@@ -1932,8 +1938,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
             if (g0 > 0.0) {
               for (it = 1; it <= sv.max_iter; ++it) {
                 const VT a_ = (VT)alpha, b_ = (VT)beta;
-                for (int idx = tid; idx < nd; idx += NT) {
-                  const int gi = (idx / n + 1) * g.P + idx % n + 1;
+                for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+                  const int gi = (j + 1) * g.P + i + 1;
                   const VT p = Rv[gi] + b_ * Pv[gi];
                   const VT s = Wv[gi] + b_ * Sv[gi];
                   Pv[gi] = p;
@@ -1944,8 +1950,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 __syncthreads();
                 gd[0] = 0.0;
                 gd[1] = 0.0;
-                for (int idx = tid; idx < nd; idx += NT) {
-                  const NodeRef nr = node_ref(g, idx % n, idx / n);
+                for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+                  const NodeRef nr = node_ref(g, i, j);
                   const VT w = stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr);
                   const VT r = Rv[nr.gi];
                   Wv[nr.gi] = w;
@@ -1963,8 +1969,7 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
             }
             }
             it_step += it;
-            for (int idx = tid; idx < nd; idx += NT) {
-              const int i = idx % n, j = idx / n;
+            for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
               const NodeRef nr = node_ref(g, i, j);
               Xv[nr.gi] += (double)dnode(i, j, nr) * (double)Yv[nr.gi];
             }
@@ -1981,8 +1986,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
         }
         block_sum<1, NWAVES>(qq, red, slot);
         qsum += qq[0] * inv_dt;
-        for (int idx = tid; idx < nd; idx += NT) {
-          const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+          const int gi = (j + 1) * g.P + i + 1;
           const double d = Xv[gi];
           Av[gi] += d;
           Xv[gi] = 2.0 * d - Xprev[gi];
@@ -1994,8 +1999,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
         const double* Fn = in.chain_f[seg];
         double* Cn = in.chain_c[seg];
         double* Un = in.chain_u[seg];
-        for (int idx = tid; idx < nd; idx += NT) {
-          const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+          const int gi = (j + 1) * g.P + i + 1;
           const double cn = Av[gi];
           const double u = Fn ? Fn[gi] + (cn - Cn[gi]) : cn;
           Cn[gi] = cn;
@@ -2006,14 +2011,14 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
       }
     }
     if (in.a_out) {
-      for (int idx = tid; idx < nd; idx += NT) {
-        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+      for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+        const int gi = (j + 1) * g.P + i + 1;
         in.a_out[gi] = Av[gi];
       }
     }
     if (in.carry) {
-      for (int idx = tid; idx < nd; idx += NT) {
-        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+      for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
+        const int gi = (j + 1) * g.P + i + 1;
         in.carry[gi] = Xv[gi];
         in.carry[FS + gi] = Xprev[gi];
       }
