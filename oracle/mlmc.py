@@ -50,3 +50,52 @@ def estimate(q_fine, q_coarse):
     for y in means:
         e += y
     return e, np.asarray(means), np.asarray(var)
+
+
+def optimal_samples(V, C, eps: float, theta: float = 0.5):
+    """Eq. (11): N_l proportional to sqrt(V_l / C_l).
+
+    The constant comes from the optimisation the paper cites: minimise the
+    cost sum_l N_l C_l subject to the estimator variance sum_l V_l / N_l =
+    theta eps^2 (theta: share of the squared RMSE eps^2 given to the
+    statistical error).  The Lagrange conditions give
+        N_l = sqrt(V_l / C_l) * sum_k sqrt(V_k C_k) / (theta eps^2),
+    returned rounded up (0 where V_l = 0)."""
+    V = np.asarray(V, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    s = 0.0
+    for v, c in zip(V, C):
+        s += np.sqrt(v * c)
+    return np.array([int(np.ceil(np.sqrt(v / c) * s / (theta * eps * eps))) if v > 0 else 0
+                     for v, c in zip(V, C)], dtype=np.int64)
+
+
+def adaptive(q_of, C, eps: float, n_pilot: int, n_max, theta: float = 0.5, max_rounds: int = 10):
+    """Adaptive MLMC (Section II-B): the level variances are estimated at run
+    time.  Start with n_pilot samples per level; each round adds, on every
+    level at once, the samples that Eq. (11) asks for given the current
+    variance estimates (never fewer than already taken, at most n_max[l]);
+    stop when no level asks for more.
+
+    q_of(l, k0, k1) returns (q_fine, q_coarse or None) for samples k0..k1-1 of
+    level l.  Returns (E, Y, V, N, rounds)."""
+    L = len(C)
+    qf = [np.empty(0) for _ in range(L)]
+    qc = [None if l == 0 else np.empty(0) for l in range(L)]
+    have = [0] * L
+    need = [min(n_pilot, n_max[l]) for l in range(L)]
+    rounds = 0
+    while True:
+        rounds += 1
+        for l in range(L):
+            if need[l] > have[l]:
+                f, c = q_of(l, have[l], need[l])
+                qf[l] = np.concatenate([qf[l], f])
+                if l > 0:
+                    qc[l] = np.concatenate([qc[l], c])
+                have[l] = need[l]
+        e, y, v = estimate(qf, qc)
+        opt = optimal_samples(v, C, eps, theta)
+        need = [max(have[l], min(int(opt[l]), n_max[l])) for l in range(L)]
+        if need == have or rounds >= max_rounds:
+            return e, y, v, np.array(have), rounds

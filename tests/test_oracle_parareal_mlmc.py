@@ -201,3 +201,54 @@ def test_table2_overall_speedup_parity_unpinned():
     model = sum(bl * c for bl, c in zip(b, C)) / (b[0] * C[0] + b[1] * C[1] + g["parareal_runtime_s"])
     assert model == pytest.approx(1.32, abs=0.01)
     assert model > g["printed"]["overall_speedup_measured"]
+
+
+def test_optimal_samples_solves_the_cost_minimisation():
+    """Eq. (11) with its constant: the closed form agrees with a numerical
+    minimisation of sum N C subject to sum V / N = theta eps^2."""
+    from scipy.optimize import minimize
+    V = np.array([4.0, 0.5, 0.03])
+    C = np.array([1.0, 3.0, 9.0])
+    eps, theta = 0.05, 0.5
+    n = mlmc.optimal_samples(V, C, eps, theta)
+    budget = theta * eps * eps
+    # constraint met after rounding up, and not by a wide margin
+    assert np.sum(V / n) <= budget
+    assert np.sum(V / (n - 1)) > budget
+    # real-valued optimum by SLSQP on log N
+    res = minimize(lambda z: float(np.sum(np.exp(z) * C)), np.log(n.astype(float)),
+                   constraints=[{"type": "eq", "fun": lambda z: float(np.sum(V / np.exp(z)) - budget)}],
+                   method="SLSQP", options={"ftol": 1e-14, "maxiter": 500})
+    assert res.success
+    assert np.allclose(np.exp(res.x), np.sqrt(V / C) * np.sum(np.sqrt(V * C)) / budget, rtol=1e-5)
+    assert np.all(np.abs(np.exp(res.x) - n) <= 1.0 + 1e-6)
+    # proportionality N_l ~ sqrt(V_l / C_l)
+    raw = np.sqrt(V / C) * np.sum(np.sqrt(V * C)) / budget
+    assert np.allclose(raw / np.sqrt(V / C), raw[0] / np.sqrt(V[0] / C[0]))
+    # a level with no variance takes no extra samples
+    assert mlmc.optimal_samples([1.0, 0.0], [1.0, 2.0], 0.1)[1] == 0
+
+
+def test_adaptive_mlmc_on_a_scalar_surrogate():
+    """Adaptive rounds on a surrogate with known level variances: the final
+    sample counts are Eq. (11) at the true variances (within sampling error),
+    the estimator variance meets theta eps^2, and the estimate is unbiased
+    within 4 standard errors of the finest-level mean."""
+    rng = np.random.default_rng(7)
+    xs = [rng.standard_normal(40000) for _ in range(3)]
+    # Q_l(x) = x + 2^-l x^2: Q_0 = x + x^2, level differences -2^-l x^2 / 2
+    def q(l, x):
+        return x + 2.0 ** (-l) * x * x
+    def q_of(l, k0, k1):
+        x = xs[l][k0:k1]
+        return q(l, x), (q(l - 1, x) if l > 0 else None)
+    C = np.array([1.0, 2.0, 4.0])
+    eps = 0.03
+    e, y, v, n, rounds = mlmc.adaptive(q_of, C, eps, 64, [40000] * 3)
+    assert np.all(n < 40000)
+    v_true = np.array([1.0 + 2.0, 2.0 * 0.25, 2.0 * 0.0625])  # Var(x + x^2) = 3, Var(x^2 / 2^l) = 2 / 4^l
+    assert rounds >= 2
+    assert np.sum(v / n) <= 0.5 * eps * eps * (1 + 1e-12)
+    n_true = mlmc.optimal_samples(v_true, C, eps)
+    assert np.all(np.abs(n - n_true) <= 0.35 * n_true)
+    assert abs(e - 1.0 * 0.25) <= 4.0 * np.sqrt(np.sum(v / n))  # E[Q_2] = E[x] + E[x^2] / 4
