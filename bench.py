@@ -22,6 +22,8 @@ Other workloads, one JSON line each in the same shape:
                         sample-steps/s, beside the batched serial fine run.
   --workload nonlinear  MLMC with 4 levels and the nonlinear reluctivity
                         (Picard per step), 129x129, 1024/256/64/16 samples.
+  --workload adaptive   adaptive MLMC (Eq. (11)) on the 129x129 model to
+                        --target-rmse, level variances estimated at run time.
   --workload serving    Poisson stream of sample-solve requests (mixed meshes
                         65..513, 64..1024 steps per period, 2 periods) into the
                         continuous-batching server; the first --requests of
@@ -324,6 +326,34 @@ def bench_nonlinear(args, mq, L, W, np, torch):
     return res
 
 
+def bench_adaptive(args, mq, L, W, np, torch):
+    """Adaptive MLMC (Eq. (11)) on the 129x129 three-level model: pilot samples,
+    then rounds of one launch each until the sample counts meet the target RMSE."""
+    from paper_2507_19246_amd import autotune
+    w = W.mlmc3_mixed_129()
+    levels = [(lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods) for lv in w.levels]
+    n_max = [4096, 1024, 512]
+    pools = [torch.tensor(W.level_xi(w, l, n=n_max[l]), dtype=torch.float64, device="cuda") for l in range(3)]
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, y, v, n, _, _, rc, st = mq.mlmc_adaptive_run(prob, levels, pools, args.target_rmse, n_pilot=32)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    args.steps, args.warmup = 1, 0
+    res = _contract("sample-steps/s", st["sample_steps"] / elapsed, elapsed, args, {
+        "workload": "adaptive-mlmc3-mixed-129x129-kl8", "mesh": "129x129",
+        "levels_steps_per_period": [lv.steps_per_period for lv in w.levels], "n_periods": w.levels[0].n_periods,
+        "target_rmse": args.target_rmse, "var_fraction": 0.5, "n_pilot": 32, "n_max": n_max,
+        "knobs": dict(knobs, precond=prob.info.precond)})
+    res.update({"status": rc, "mlmc_estimate": e, "samples_per_level": n, "level_means": y,
+                "level_variances": v, "estimator_std": float(np.sqrt(sum(vi / ni for vi, ni in zip(v, n)))),
+                "sample_steps": st["sample_steps"], "kernel_ms": st["kernel_ms"], "roofline": None,
+                "cpu_baseline": None})
+    prob.close()
+    return res
+
+
 def _serve(mq, L, W, np, torch, reqs, limit_s, label):
     """Submit `reqs` at their arrival times into a fresh server; wait for all results."""
     base = W.Problem(65, W.Material(kind=W.MAT_KL))
@@ -398,7 +428,8 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
-    ap.add_argument("--workload", default="mlmc3", choices=["mlmc3", "parareal", "nonlinear", "serving"])
+    ap.add_argument("--workload", default="mlmc3", choices=["mlmc3", "parareal", "nonlinear", "serving", "adaptive"])
+    ap.add_argument("--target-rmse", type=float, default=30.0, help="adaptive: target RMSE of the estimate (W/m)")
     ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
@@ -433,7 +464,8 @@ def main():
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}}))
         return
     if args.workload != "mlmc3":
-        fn = {"parareal": bench_parareal, "nonlinear": bench_nonlinear, "serving": bench_serving}[args.workload]
+        fn = {"parareal": bench_parareal, "nonlinear": bench_nonlinear, "serving": bench_serving,
+              "adaptive": bench_adaptive}[args.workload]
         print(json.dumps(fn(args, mq, L, W, np, torch)), flush=True)
         return
     w = W.mlmc3_mixed_129()

@@ -200,6 +200,32 @@ int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv
                         const int32_t* n_samples, const double* const* xi,
                         double* const* q_fine, double* const* q_coarse, mq_run_stats* st);
 
+/* Adaptive MLMC (Section II-B, Eq. (11)): the level variances V_l are
+ * estimated at run time.  Every level first runs n_pilot samples; each round
+ * then runs, in one persistent launch, the additional samples that
+ *   N_l = ceil( sqrt(V_l / C_l) * sum_k sqrt(V_k C_k) / (var_fraction * target_rmse^2) )
+ * asks for (the minimiser of sum N_l C_l under sum V_l / N_l = var_fraction *
+ * target_rmse^2), with C_l the steps of one sample of level l (fine + coarse)
+ * and V_l the current unbiased variance of Q_l - Q_{l-1}; N_l never decreases
+ * and is capped at n_max[l].  Stops when no level asks for more samples or
+ * after max_rounds rounds.
+ * xi: host array of device pointers, [n_max[l]][n_xi] each (the inputs of
+ * sample k of level l are row k); q_fine, q_coarse: host arrays of device
+ * pointers, [n_max[l]] each (q_coarse[0] ignored); sample k's results land in
+ * row k.  n_used: host [n_levels] (samples taken); out: host [1 + 2 n_levels] =
+ * {E, Y_0..Y_{L-1}, V_0..V_{L-1}} of the final samples.  Returns
+ * MQ_WARN_NOT_CONVERGED when a cap (n_max or max_rounds) stopped the
+ * allocation short of Eq. (11), or when an instance hit a solver cap. */
+typedef struct mq_adaptive_desc {
+  double target_rmse;    /* > 0 */
+  double var_fraction;   /* share of target_rmse^2 for the estimator variance (0: 0.5) */
+  int32_t n_pilot;       /* >= 2 */
+  int32_t max_rounds;    /* 0: 10 */
+} mq_adaptive_desc;
+int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_max,
+                      const double* const* xi, double* const* q_fine, double* const* q_coarse,
+                      const mq_adaptive_desc* ad, int32_t* n_used, double* out, mq_run_stats* st);
+
 /* Parareal for n_samples samples at once (samples x slices batched).
  * xi: device [n_samples][n_xi]; q: device [n_samples] (Q from the final
  * per-slice fine sums); iters: device int32 [n_samples] (K per sample);

@@ -84,6 +84,11 @@ class PararealDesc(C.Structure):
                 ("k_max", C.c_int32), ("fixed_k", C.c_int32), ("tol", C.c_double)]
 
 
+class AdaptiveDesc(C.Structure):
+    _fields_ = [("target_rmse", C.c_double), ("var_fraction", C.c_double), ("n_pilot", C.c_int32),
+                ("max_rounds", C.c_int32)]
+
+
 class ServerDesc(C.Structure):
     _fields_ = [("base", ProblemDesc), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
                 ("n_streams", C.c_int32), ("max_batch", C.c_int32), ("chunk_steps", C.c_int32)]
@@ -115,6 +120,9 @@ SIGNATURES = {
     "mlmc_multilevel_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32),
                                       C.POINTER(VP), C.POINTER(VP), C.POINTER(VP), C.POINTER(RunStats)]),
     "parareal_run": (C.c_int, [VP, C.POINTER(PararealDesc), C.c_int32, VP, VP, VP, VP, C.POINTER(RunStats)]),
+    "mlmc_adaptive_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32), C.POINTER(VP),
+                                    C.POINTER(VP), C.POINTER(VP), C.POINTER(AdaptiveDesc), C.POINTER(C.c_int32),
+                                    PD, C.POINTER(RunStats)]),
     "mlmc_estimate": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(VP), C.POINTER(VP), VP, VP]),
     "mq_debug_apply": (C.c_int, [VP, C.c_int32, C.c_double, C.c_int32, VP, VP, VP]),
     "mq_server_create": (C.c_int, [C.POINTER(ServerDesc), VP, C.POINTER(VP)]),

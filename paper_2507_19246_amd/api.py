@@ -133,6 +133,30 @@ def mlmc_multilevel_run(prob: Problem, levels: Sequence, xis: Sequence):
     return qfs, qcs, rc, st.as_dict()
 
 
+def mlmc_adaptive_run(prob: Problem, levels: Sequence, xi_pools: Sequence, target_rmse: float,
+                      n_pilot: int = 32, var_fraction: float = 0.5, max_rounds: int = 10):
+    """Adaptive MLMC (Eq. (11)) over per-level input pools xi_pools[l] ([n_max_l, n_xi]).
+    Returns (E, level means, level variances, samples used per level, q_fine, q_coarse, status, stats)."""
+    nl = len(levels)
+    lvs = (L.LevelDesc * nl)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    xs = [_dev_f64(x).reshape(-1, prob.n_xi).contiguous() for x in xi_pools]
+    nmax = (C.c_int32 * nl)(*[x.shape[0] for x in xs])
+    qfs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") for x in xs]
+    qcs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") for x in xs]
+    px = (C.c_void_p * nl)(*[x.data_ptr() for x in xs])
+    pf = (C.c_void_p * nl)(*[q.data_ptr() for q in qfs])
+    pc = (C.c_void_p * nl)(*[q.data_ptr() for q in qcs])
+    ad = L.AdaptiveDesc(target_rmse, var_fraction, n_pilot, max_rounds)
+    used = (C.c_int32 * nl)()
+    out = (C.c_double * (1 + 2 * nl))()
+    st = L.RunStats()
+    rc = L.check(prob.lib.mlmc_adaptive_run(prob.h, nl, lvs, nmax, px, pf, pc, C.byref(ad), used, out,
+                                            C.byref(st)))
+    n = [used[i] for i in range(nl)]
+    return (out[0], list(out[1:1 + nl]), list(out[1 + nl:]), n, [q[:k] for q, k in zip(qfs, n)],
+            [q[:k] if l > 0 else None for l, (q, k) in enumerate(zip(qcs, n))], rc, st.as_dict())
+
+
 def parareal_run(prob: Problem, n_periods: int, n_slices: int, fine_steps_per_slice: int,
                  coarse_steps_per_slice: int, k_max: int, tol: float, xi, fixed_k: int = 0,
                  want_state: bool = False):

@@ -487,6 +487,110 @@ int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv
   return ro.status;
 }
 
+int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_max,
+                      const double* const* xi, double* const* q_fine, double* const* q_coarse,
+                      const mq_adaptive_desc* ad, int32_t* n_used, double* out, mq_run_stats* st) {
+  if (!p || !lv || !n_max || !xi || !q_fine || !q_coarse || !ad || !n_used || !out)
+    return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
+  if (!(ad->target_rmse > 0) || ad->n_pilot < 2 || ad->max_rounds < 0 || !(ad->var_fraction >= 0) ||
+      !(ad->var_fraction < 1))
+    return fail(MQ_ERR_INVALID_ARG, "target_rmse > 0, n_pilot >= 2, 0 <= var_fraction < 1 required");
+  for (int l = 0; l < n_levels; ++l) {
+    if (n_max[l] < ad->n_pilot) return fail(MQ_ERR_INVALID_ARG, "n_max must be >= n_pilot on every level");
+    if (!xi[l] || !q_fine[l] || (l > 0 && !q_coarse[l]))
+      return fail(MQ_ERR_INVALID_ARG, "null per-level pointer");
+    if (lv[l].steps_per_period < 1 || lv[l].n_periods < 1 || lv[l].coarse_steps_per_period < 0 ||
+        (l > 0 && lv[l].coarse_steps_per_period < 1))
+      return fail(MQ_ERR_INVALID_ARG, "levels above 0 need a coupled coarse run");
+  }
+  const double t0 = now_ms();
+  const double theta = ad->var_fraction > 0 ? ad->var_fraction : 0.5;
+  const double budget = theta * ad->target_rmse * ad->target_rmse;
+  const int max_rounds = ad->max_rounds > 0 ? ad->max_rounds : 10;
+  const int L = n_levels;
+  std::vector<int32_t> have(L, 0), need(L);
+  std::vector<double> cost(L);
+  for (int l = 0; l < L; ++l) {
+    need[l] = ad->n_pilot;
+    cost[l] = (double)lv[l].n_periods * (lv[l].steps_per_period + lv[l].coarse_steps_per_period);
+  }
+  if (st) std::memset(st, 0, sizeof(*st));
+  DevPtr<double> dout;
+  HIP_TRY(dev_alloc(dout, 1 + 2 * (size_t)L));
+  std::vector<double> host(1 + 2 * (size_t)L);
+  int status = MQ_OK;
+  for (int round = 1;; ++round) {
+    // the new samples of every level that asks for more, in one launch
+    std::vector<mq_level_desc> lvs;
+    std::vector<int32_t> ns;
+    std::vector<const double*> xs;
+    std::vector<double*> qf, qc;
+    for (int l = 0; l < L; ++l) {
+      if (need[l] <= have[l]) continue;
+      lvs.push_back(lv[l]);
+      ns.push_back(need[l] - have[l]);
+      xs.push_back(xi[l] + (size_t)have[l] * p->n_xi);
+      qf.push_back(q_fine[l] + have[l]);
+      qc.push_back(lv[l].coarse_steps_per_period > 0 ? q_coarse[l] + have[l] : nullptr);
+    }
+    if (!lvs.empty()) {
+      mq_run_stats s{};
+      const int rc = mlmc_multilevel_run(p, (int32_t)lvs.size(), lvs.data(), ns.data(), xs.data(), qf.data(),
+                                         qc.data(), &s);
+      if (rc < 0) return rc;
+      if (rc > 0) status = rc;
+      if (st) {
+        st->n_instances += s.n_instances;
+        st->sample_steps += s.sample_steps;
+        st->inner_iters += s.inner_iters;
+        st->sweeps += s.sweeps;
+        st->picard_iters += s.picard_iters;
+        st->max_inner_per_step = std::max(st->max_inner_per_step, s.max_inner_per_step);
+        st->n_not_converged += s.n_not_converged;
+        st->n_failed += s.n_failed;
+        st->path = s.path;
+        st->grid = s.grid;
+        st->block = s.block;
+        st->kernel_ms += s.kernel_ms;
+        st->busy_ms += s.busy_ms;
+        for (int q = 0; q < 8; ++q) st->phase_ms[q] += s.phase_ms[q];
+      }
+      for (int l = 0; l < L; ++l) have[l] = std::max(have[l], need[l]);
+    }
+    // level means and variances of all samples so far (device, fixed order)
+    const int rc = mlmc_estimate(L, have.data(), q_fine, q_coarse, dout.get(), p->stream);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(host.data(), dout.get(), host.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // Eq. (11) at the current variance estimates
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) s += std::sqrt(host[1 + L + l] * cost[l]);
+    bool more = false, capped = false;
+    for (int l = 0; l < L; ++l) {
+      const double v = host[1 + L + l];
+      const double opt = v > 0 ? std::ceil(std::sqrt(v / cost[l]) * s / budget) : 0.0;
+      int32_t target = have[l];
+      if (opt > (double)have[l]) {
+        if (opt > (double)n_max[l]) capped = true;
+        target = (int32_t)std::min<double>(opt, (double)n_max[l]);
+      }
+      need[l] = target;
+      more |= need[l] > have[l];
+    }
+    if (!more || round >= max_rounds) {
+      if (more || capped) {
+        status = std::max(status, (int)MQ_WARN_NOT_CONVERGED);
+        last_error() = "adaptive MLMC stopped at n_max or max_rounds before Eq. (11) was met";
+      }
+      break;
+    }
+  }
+  for (int l = 0; l < L; ++l) n_used[l] = have[l];
+  std::memcpy(out, host.data(), host.size() * sizeof(double));
+  if (st) st->total_ms = now_ms() - t0;
+  return status;
+}
+
 int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
                  double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
   if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");

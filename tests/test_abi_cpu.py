@@ -29,7 +29,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     fns = header_functions()
-    for name in ["fem_setup", "mlmc_level_run", "parareal_run", "mlmc_estimate", "mq_debug_apply",
+    for name in ["fem_setup", "mlmc_level_run", "parareal_run", "mlmc_estimate", "mlmc_adaptive_run", "mq_debug_apply",
                  "mq_server_create", "mq_submit", "mq_poll", "mq_server_destroy", "mq_last_error"]:
         assert name in fns
 
@@ -47,7 +47,7 @@ def test_struct_layout_matches_c(tmp_path):
     structs = {"mq_problem_desc": _lib.ProblemDesc, "mq_problem_info": _lib.ProblemInfo,
                "mq_run_stats": _lib.RunStats, "mq_level_desc": _lib.LevelDesc,
                "mq_parareal_desc": _lib.PararealDesc, "mq_server_desc": _lib.ServerDesc,
-               "mq_request": _lib.Request, "mq_result": _lib.Result}
+               "mq_request": _lib.Request, "mq_result": _lib.Result, "mq_adaptive_desc": _lib.AdaptiveDesc}
     src = tmp_path / "sz.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void){']
     for cname in structs:
@@ -55,6 +55,8 @@ def test_struct_layout_matches_c(tmp_path):
     lines.append('printf("off_tol %zu\\n", offsetof(mq_problem_desc, tol));')
     lines.append('printf("off_kernel_ms %zu\\n", offsetof(mq_run_stats, kernel_ms));')
     lines.append('printf("off_t_done %zu\\n", offsetof(mq_result, t_done_ns));')
+    lines.append('printf("off_mg_sweeps %zu\\n", offsetof(mq_problem_desc, mg_coarse_sweeps));')
+    lines.append('printf("off_busy %zu\\n", offsetof(mq_run_stats, busy_ms));')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -65,6 +67,8 @@ def test_struct_layout_matches_c(tmp_path):
     assert int(out["off_tol"]) == _lib.ProblemDesc.tol.offset
     assert int(out["off_kernel_ms"]) == _lib.RunStats.kernel_ms.offset
     assert int(out["off_t_done"]) == _lib.Result.t_done_ns.offset
+    assert int(out["off_mg_sweeps"]) == _lib.ProblemDesc.mg_coarse_sweeps.offset
+    assert int(out["off_busy"]) == _lib.RunStats.busy_ms.offset
 
 
 def test_no_device_and_invalid_arguments(lib):

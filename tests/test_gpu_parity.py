@@ -251,3 +251,37 @@ def test_picard_nonlinear_matches_oracle(n, prec, k2):
     assert err <= (1e-9 if prec == 0 else 1e-6)
     assert abs(st["picard_iters"] - ref_its) <= len(xi) * 16 // 4
     p.close()
+
+
+def test_adaptive_mlmc_matches_oracle():
+    """Adaptive MLMC (Eq. (11), run-time level variances): the sample counts
+    the device run settles on equal the oracle driver's on the same input
+    pools, and the estimate agrees to the FP64 tolerance."""
+    mq, L = mqmod()
+    prob = W.Problem(33, W.Material(kind=W.MAT_KL))
+    levels = [(16, 0, 1), (32, 16, 1), (64, 32, 1)]
+    n_max = [3000, 200, 200]
+    pools = [W.normals(0, 40, l, range(n_max[l]), 8) for l in range(3)]
+    eps, pilot = 20.0, 16
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    e, y, v, n, qf, qc, rc, st = mq.mlmc_adaptive_run(p, levels, pools, eps, n_pilot=pilot)
+    assert rc == 0
+    say("device: E", e, "N", n, "V", v)
+    m = omesh.build(33)
+    tab = ots.kl_table_for(prob, m)
+
+    def q_of(l, k0, k1):
+        spp, cs, nper = levels[l]
+        xs = pools[l][k0:k1]
+        f = np.array([ots.solve_sample(prob, x, spp, nper, m=m, kl_table=tab)[0] for x in xs])
+        c = np.array([ots.solve_sample(prob, x, cs, nper, m=m, kl_table=tab)[0] for x in xs]) if cs else None
+        return f, c
+
+    C = [nper * (spp + cs) for spp, cs, nper in levels]
+    e_o, y_o, v_o, n_o, rounds = omlmc.adaptive(q_of, C, eps, pilot, n_max)
+    say("oracle: E", e_o, "N", list(n_o), "rounds", rounds)
+    assert list(n) == list(n_o)
+    assert abs(e - e_o) <= 1e-10 * abs(e_o)
+    assert np.allclose(v, v_o, rtol=1e-8)
+    assert sum(vi / ni for vi, ni in zip(v, n)) <= 0.5 * eps * eps
+    p.close()
