@@ -189,6 +189,9 @@ def bench_parareal(args, mq, L, W, np, torch):
     """Parareal on the finest level (257x257, 64 samples); value = useful sample-steps/s."""
     w = W.parareal_257()
     pr = w.parareal
+    if args.coarse_steps > 0:
+        import dataclasses
+        pr = dataclasses.replace(pr, coarse_steps_per_slice=args.coarse_steps)
     xi_np = W.level_xi(w, 0)
     xi = torch.tensor(xi_np, dtype=torch.float64, device="cuda")
     from paper_2507_19246_amd import autotune
@@ -332,7 +335,7 @@ def bench_adaptive(args, mq, L, W, np, torch):
     from paper_2507_19246_amd import autotune
     w = W.mlmc3_mixed_129()
     levels = [(lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods) for lv in w.levels]
-    n_max = [4096, 1024, 512]
+    n_max = [8192, 2048, 1024]
     pools = [torch.tensor(W.level_xi(w, l, n=n_max[l]), dtype=torch.float64, device="cuda") for l in range(3)]
     prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
     torch.cuda.synchronize()
@@ -429,11 +432,13 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--workload", default="mlmc3", choices=["mlmc3", "parareal", "nonlinear", "serving", "adaptive"])
-    ap.add_argument("--target-rmse", type=float, default=30.0, help="adaptive: target RMSE of the estimate (W/m)")
+    ap.add_argument("--target-rmse", type=float, default=50.0, help="adaptive: target RMSE of the estimate (W/m)")
     ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
     ap.add_argument("--no-serial", action="store_true", help="parareal: skip the batched serial comparison run")
+    ap.add_argument("--coarse-steps", type=int, default=0,
+                    help="parareal: coarse IE steps per slice (0: the workload's 1; 8 = the level L-2 grid)")
     ap.add_argument("--stable-requests", type=int, default=64,
                     help="serving: requests of the stable-load run at 0.7 x the measured capacity (0: skip)")
     args = ap.parse_args()
