@@ -200,6 +200,19 @@ int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv
                         const int32_t* n_samples, const double* const* xi,
                         double* const* q_fine, double* const* q_coarse, mq_run_stats* st);
 
+/* Spatial and temporal level hierarchy (Section I; Section II-B with levels
+ * that refine the mesh as well as the time step): level l runs on the mesh of
+ * problems[l] and its coupled coarse run on the mesh of problems[l - 1], with
+ * the same input (the KL field is evaluated at each mesh's element centroids).
+ * problems: host array of n_levels distinct handles that share material,
+ * input dimension and precision; lv, n_samples, xi, q_fine, q_coarse as in
+ * mlmc_multilevel_run.  One persistent launch per mesh (its fine runs and the
+ * next level's coarse runs), all meshes concurrently on their problems'
+ * streams; returns when all are done.  st: kernel_ms is the longest launch. */
+int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_level_desc* lv,
+                       const int32_t* n_samples, const double* const* xi, double* const* q_fine,
+                       double* const* q_coarse, mq_run_stats* st);
+
 /* Adaptive MLMC (Section II-B, Eq. (11)): the level variances V_l are
  * estimated at run time.  Every level first runs n_pilot samples; each round
  * then runs, in one persistent launch, the additional samples that

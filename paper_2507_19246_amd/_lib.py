@@ -120,6 +120,8 @@ SIGNATURES = {
     "mlmc_multilevel_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32),
                                       C.POINTER(VP), C.POINTER(VP), C.POINTER(VP), C.POINTER(RunStats)]),
     "parareal_run": (C.c_int, [VP, C.POINTER(PararealDesc), C.c_int32, VP, VP, VP, VP, C.POINTER(RunStats)]),
+    "mlmc_multimesh_run": (C.c_int, [C.c_int32, C.POINTER(VP), C.POINTER(LevelDesc), C.POINTER(C.c_int32),
+                                     C.POINTER(VP), C.POINTER(VP), C.POINTER(VP), C.POINTER(RunStats)]),
     "mlmc_adaptive_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32), C.POINTER(VP),
                                     C.POINTER(VP), C.POINTER(VP), C.POINTER(AdaptiveDesc), C.POINTER(C.c_int32),
                                     PD, C.POINTER(RunStats)]),

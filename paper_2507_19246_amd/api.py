@@ -133,6 +133,26 @@ def mlmc_multilevel_run(prob: Problem, levels: Sequence, xis: Sequence):
     return qfs, qcs, rc, st.as_dict()
 
 
+def mlmc_multimesh_run(probs: Sequence[Problem], levels: Sequence, xis: Sequence):
+    """Level l on the mesh of probs[l], its coupled coarse run on probs[l - 1]'s mesh.
+    Returns (list of q_fine, list of q_coarse or None, status, stats)."""
+    nl = len(levels)
+    lib = probs[0].lib
+    hs = (C.c_void_p * nl)(*[p.h.value for p in probs])
+    lvs = (L.LevelDesc * nl)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    xs = [_dev_f64(x).reshape(-1, probs[0].n_xi).contiguous() for x in xis]
+    ns = (C.c_int32 * nl)(*[x.shape[0] for x in xs])
+    qfs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") for x in xs]
+    qcs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") if l > 0 else None
+           for l, x in enumerate(xs)]
+    px = (C.c_void_p * nl)(*[x.data_ptr() for x in xs])
+    pf = (C.c_void_p * nl)(*[q.data_ptr() for q in qfs])
+    pc = (C.c_void_p * nl)(*[(q.data_ptr() if q is not None else None) for q in qcs])
+    st = L.RunStats()
+    rc = L.check(lib.mlmc_multimesh_run(nl, hs, lvs, ns, px, pf, pc, C.byref(st)))
+    return qfs, qcs, rc, st.as_dict()
+
+
 def mlmc_adaptive_run(prob: Problem, levels: Sequence, xi_pools: Sequence, target_rmse: float,
                       n_pilot: int = 32, var_fraction: float = 0.5, max_rounds: int = 10):
     """Adaptive MLMC (Eq. (11)) over per-level input pools xi_pools[l] ([n_max_l, n_xi]).

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "problem.h"
@@ -588,6 +589,95 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
   for (int l = 0; l < L; ++l) n_used[l] = have[l];
   std::memcpy(out, host.data(), host.size() * sizeof(double));
   if (st) st->total_ms = now_ms() - t0;
+  return status;
+}
+
+int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_level_desc* lv,
+                       const int32_t* n_samples, const double* const* xi, double* const* q_fine,
+                       double* const* q_coarse, mq_run_stats* st) {
+  if (!problems || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (n_levels < 1 || n_levels > 16) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 16]");
+  const int L = n_levels;
+  for (int l = 0; l < L; ++l) {
+    mq_problem* p = problems[l];
+    if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
+    for (int k = 0; k < l; ++k)
+      if (problems[k] == p) return fail(MQ_ERR_INVALID_ARG, "every level needs its own problem handle");
+    if (p->n_xi != problems[0]->n_xi || p->d.material != problems[0]->d.material ||
+        p->d.precision != problems[0]->d.precision)
+      return fail(MQ_ERR_INVALID_ARG, "the meshes must share material, input dimension and precision");
+    if (l > 0 && (lv[l].coarse_steps_per_period < 1 || !q_coarse[l]))
+      return fail(MQ_ERR_INVALID_ARG, "levels above 0 need a coupled coarse run");
+  }
+  const double t0 = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  // per mesh m: the fine runs of level m and the coupled coarse runs of level m + 1
+  std::vector<std::vector<LevelBufs>> bufs(L);
+  std::vector<std::vector<Inst>> runs(L);
+  for (int m = 0; m < L; ++m) {
+    mq_problem* p = problems[m];
+    bufs[m].resize(2);
+    std::vector<Inst> a, unused;
+    const mq_level_desc f{lv[m].steps_per_period, 0, lv[m].n_periods, 0};
+    int rc = prepare_level(p, &f, n_samples[m], xi[m], q_fine[m], nullptr, false, bufs[m][0], a, unused, 0);
+    if (rc) return rc;
+    if (m + 1 < L) {
+      const mq_level_desc c{lv[m + 1].coarse_steps_per_period, 0, lv[m + 1].n_periods, 0};
+      std::vector<Inst> b;
+      rc = prepare_level(p, &c, n_samples[m + 1], xi[m + 1], q_coarse[m + 1], nullptr, false, bufs[m][1], b,
+                         unused, n_samples[m]);
+      if (rc) return rc;
+      a.insert(a.end(), b.begin(), b.end());
+    }
+    std::stable_sort(a.begin(), a.end(), [](const Inst& x, const Inst& y) { return x.n_steps > y.n_steps; });
+    runs[m] = std::move(a);
+    // size the work buffer now: no allocation while other meshes run
+    rc = ensure_work(p, std::min<size_t>(runs[m].size(), max_slots(p)));
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  // one persistent launch per mesh, all meshes at once (a host thread each)
+  std::vector<int> rcs(L, MQ_OK);
+  std::vector<std::string> errs(L);
+  std::vector<mq_run_stats> sts(L);
+  std::vector<RunOut> ros(L);
+  std::vector<std::thread> th;
+  for (int m = 0; m < L; ++m) {
+    th.emplace_back([&, m] {
+      (void)hipSetDevice(problems[m]->device);
+      rcs[m] = run_instances(problems[m], runs[m], &sts[m], &ros[m], nullptr);
+      if (rcs[m] < 0) errs[m] = last_error();
+    });
+  }
+  for (auto& t : th) t.join();
+  int status = MQ_OK;
+  for (int m = 0; m < L; ++m) {
+    if (rcs[m] < 0) return fail(rcs[m], errs[m]);
+    status = std::max(status, ros[m].status);
+    if (st) {
+      const mq_run_stats& s = sts[m];
+      st->n_instances += s.n_instances;
+      st->sample_steps += s.sample_steps;
+      st->inner_iters += s.inner_iters;
+      st->sweeps += s.sweeps;
+      st->picard_iters += s.picard_iters;
+      st->max_inner_per_step = std::max(st->max_inner_per_step, s.max_inner_per_step);
+      st->n_not_converged += s.n_not_converged;
+      st->n_failed += s.n_failed;
+      st->kernel_ms = std::max(st->kernel_ms, s.kernel_ms);  // concurrent launches
+      st->busy_ms += s.busy_ms;
+      st->lat_p50_ms = std::max(st->lat_p50_ms, s.lat_p50_ms);
+      st->lat_p99_ms = std::max(st->lat_p99_ms, s.lat_p99_ms);
+      st->lat_max_ms = std::max(st->lat_max_ms, s.lat_max_ms);
+      for (int q = 0; q < 8; ++q) st->phase_ms[q] += s.phase_ms[q];
+    }
+  }
+  if (st) {
+    st->path = problems[L - 1]->path;
+    st->grid = ros[L - 1].grid;
+    st->block = ros[L - 1].block;
+    st->total_ms = now_ms() - t0;
+  }
   return status;
 }
 

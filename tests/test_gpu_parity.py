@@ -285,3 +285,36 @@ def test_adaptive_mlmc_matches_oracle():
     assert np.allclose(v, v_o, rtol=1e-8)
     assert sum(vi / ni for vi, ni in zip(v, n)) <= 0.5 * eps * eps
     p.close()
+
+
+def test_multimesh_mlmc_matches_oracle():
+    """Spatial + temporal levels: level l on mesh l (17, 33, 65 nodes per side),
+    its coupled coarse run on mesh l - 1 with the same input; every Q against
+    the oracle on the matching mesh, and the estimator against the oracle's."""
+    mq, L = mqmod()
+    meshes = [17, 33, 65]
+    levels = [(16, 0, 1), (32, 16, 1), (64, 32, 1)]
+    ns = [5, 3, 2]
+    probs = [W.Problem(n, W.Material(kind=W.MAT_KL)) for n in meshes]
+    hs = [mq.Problem(pb, L.MQ_PREC_MIXED) for pb in probs]
+    xis = [W.normals(0, 41, l, range(ns[l]), 8) for l in range(3)]
+    qf, qc, rc, st = mq.mlmc_multimesh_run(hs, levels, xis)
+    assert rc == 0
+    rf, rcq = [], [None]
+    for l in range(3):
+        f, _ = oracle_q(probs[l], xis[l], levels[l][0], levels[l][2])
+        rf.append(f)
+        e = np.max(np.abs(qf[l].cpu().numpy() - f) / np.abs(f))
+        say("level", l, "fine err", e)
+        assert e <= 1e-6
+        if l > 0:
+            c, _ = oracle_q(probs[l - 1], xis[l], levels[l][1], levels[l][2])
+            rcq.append(c)
+            ec = np.max(np.abs(qc[l].cpu().numpy() - c) / np.abs(c))
+            say("level", l, "coarse err", ec)
+            assert ec <= 1e-6
+    e_gpu, _, _ = mq.mlmc_estimate(qf, qc)
+    e_ref, _, _ = omlmc.estimate(rf, rcq)
+    assert abs(float(e_gpu) - e_ref) <= 1e-6 * abs(e_ref)
+    for h in hs:
+        h.close()
