@@ -61,7 +61,13 @@ enum { MQ_MAT_LOGNORMAL_SCALAR = 0, MQ_MAT_KL = 1, MQ_MAT_NONLINEAR = 2 };
 enum { MQ_PREC_FP64 = 0, MQ_PREC_MIXED = 1 };
 enum { MQ_APPLY_A = 0, MQ_APPLY_M = 1, MQ_APPLY_K = 2 };
 /* kernel path selection (mq_problem_desc.path) */
-enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2 };
+/* Execution path: RESIDENT (CG state in registers/LDS, meshes up to 129 x 129),
+ * STREAMING (vectors in global memory, any mesh), both one workgroup per
+ * instance and many instances per launch; WIDE: one instance at a time over
+ * the whole device (grid-wide passes, inner iterations replayed from a captured
+ * graph) — for few large instances, where latency matters more than throughput;
+ * needs multigrid (n_nodes = 2^k + 1) and a linear material; level runs only. */
+enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2, MQ_PATH_WIDE = 3 };
 /* inner preconditioner (mq_problem_desc.precond): Jacobi is a symmetric
  * diagonal scaling; MULTIGRID is a geometric V(1,1)-cycle with damped-Jacobi
  * smoothing and Galerkin coarse operators (resident path, n_nodes = 2^k + 1) */

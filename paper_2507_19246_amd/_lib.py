@@ -24,7 +24,7 @@ MQ_ERR_CANCELLED = -7
 MQ_MAT_LOGNORMAL_SCALAR, MQ_MAT_KL, MQ_MAT_NONLINEAR = 0, 1, 2
 MQ_PREC_FP64, MQ_PREC_MIXED = 0, 1
 MQ_APPLY_A, MQ_APPLY_M, MQ_APPLY_K = 0, 1, 2
-MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING = 0, 1, 2
+MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING, MQ_PATH_WIDE = 0, 1, 2, 3
 MQ_PRECOND_AUTO, MQ_PRECOND_JACOBI, MQ_PRECOND_MULTIGRID = 0, 1, 2
 
 

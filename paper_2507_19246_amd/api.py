@@ -93,6 +93,8 @@ class Problem:
 
     @property
     def path(self) -> int:
+        if self.desc.path == L.MQ_PATH_WIDE:
+            return L.MQ_PATH_WIDE
         return L.MQ_PATH_RESIDENT if (self.desc.path != L.MQ_PATH_STREAMING and self.info.resident_ok) else L.MQ_PATH_STREAMING
 
 

@@ -53,7 +53,7 @@ Solver solver_of(const mq_problem* p) {
 
 size_t slot_doubles(const mq_problem* p) {
   // FP64 slot planes + the streaming path's vector workspace (8-byte upper bound)
-  const bool smg = p->path == MQ_PATH_STREAMING && p->mg.nlev > 0;
+  const bool smg = (p->path == MQ_PATH_STREAMING || p->path == MQ_PATH_WIDE) && p->mg.nlev > 0;
   return ie_work_doubles(p->hm.g) + stream_vwork_elems(p->hm.g, smg ? &p->mg : nullptr);
 }
 
@@ -71,6 +71,7 @@ int ensure_work(mq_problem* p, size_t slots) {
 size_t work_bytes(const mq_problem* p, size_t slots) { return slots * slot_doubles(p) * sizeof(double); }
 
 size_t max_slots(const mq_problem* p) {
+  if (p->path == MQ_PATH_WIDE) return 1;
   const int per_cu = ie_slots_per_cu(p->hm.g, p->mg.nlev > 0 ? &p->mg : nullptr, p->path, p->d.precision, p->tile);
   return (size_t)p->num_cu * per_cu;
 }
@@ -112,7 +113,7 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->material < 0 || d->material > 2) return fail(MQ_ERR_INVALID_ARG, "unknown material kind");
   if (d->precision != MQ_PREC_FP64 && d->precision != MQ_PREC_MIXED)
     return fail(MQ_ERR_INVALID_ARG, "unknown precision");
-  if (d->path < 0 || d->path > 2) return fail(MQ_ERR_INVALID_ARG, "unknown path");
+  if (d->path < 0 || d->path > 3) return fail(MQ_ERR_INVALID_ARG, "unknown path");
   if (!(d->conductor[0] < d->conductor[1]) || !(d->conductor[2] < d->conductor[3]))
     return fail(MQ_ERR_INVALID_ARG, "empty conductor box");
   if (!(d->strip[0] <= d->strip[1])) return fail(MQ_ERR_INVALID_ARG, "bad strip");
@@ -155,6 +156,14 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
                   std::vector<int>* stat_host) {
   const int n = (int)insts.size();
   if (n == 0) return MQ_OK;
+  if (p->path == MQ_PATH_WIDE) {
+    (void)stat_host;
+    int status = MQ_OK;
+    const int rc = run_wide(p, insts, st, &status);
+    if (rc) return rc;
+    ro->status = std::max(ro->status, status);
+    return MQ_OK;
+  }
   DevPtr<int> dstat;
   HIP_TRY(dev_alloc(dstat, (size_t)n * STAT_N));
   HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)n * STAT_N, p->stream));
@@ -369,12 +378,19 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   if (d->material == MQ_MAT_NONLINEAR && (!p->resident_ok || d->path == MQ_PATH_STREAMING))
     return fail(MQ_ERR_INVALID_ARG, "the nonlinear (Picard) material runs on the resident path only");
   p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
+  if (d->path == MQ_PATH_WIDE) {
+    if (d->material == MQ_MAT_NONLINEAR || !want_mg)
+      return fail(MQ_ERR_INVALID_ARG, "the wide path needs a linear material and the multigrid preconditioner");
+    p->path = MQ_PATH_WIDE;
+  }
   p->mg = MGGeom{};
   if (p->path == MQ_PATH_RESIDENT) {
     if (res_mg) p->mg = rmg;
   } else if (want_mg && !build_mg(g0, 0, &p->mg)) {
     p->mg = MGGeom{};
   }
+  if (p->path == MQ_PATH_WIDE && p->mg.nlev < 1)
+    return fail(MQ_ERR_INVALID_ARG, "the wide path needs n_nodes = 2^k + 1 (multigrid hierarchy)");
   if (d->precond == MQ_PRECOND_MULTIGRID && p->mg.nlev == 0)
     return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS)");
   p->precond = p->mg.nlev > 0 ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
@@ -684,6 +700,7 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
 int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
                  double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
   if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "Parareal runs on the resident or streaming path");
   if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
   if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
   const int M = pd->n_slices, fs = pd->fine_steps_per_slice, cs = pd->coarse_steps_per_slice;

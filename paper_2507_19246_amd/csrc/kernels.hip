@@ -1338,6 +1338,7 @@ static bool pick_resident(const Geom& g, int tile, ResCfg* c) {
 int stream_threads(int tile);
 
 int ie_block_threads(const Geom& g, int path, int tile) {
+  if (path == MQ_PATH_WIDE) return 256;
   ResCfg c;
   if (path == MQ_PATH_RESIDENT && pick_resident(g, tile, &c)) return c.cw * c.ns;
   return stream_threads(tile);
@@ -2087,5 +2088,452 @@ hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, c
   if (nt == 512) return launch_stream_nt<512>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
   return launch_stream_nt<STREAM_NT>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
 }
+
+}  // namespace mq
+
+// ---------------------------------------------------------------------------
+// wide path: one instance spread over the whole device
+// ---------------------------------------------------------------------------
+// Every pass of the streaming solver becomes a grid-wide kernel (2-D grid:
+// blockIdx.y = row, blockIdx.x * 256 + tid = column); reductions leave one
+// partial per block and a one-block kernel sums them in a fixed order and
+// takes the solver's scalar decisions into WideScal.  Passes of the inner CG
+// return at once when WideScal::done is set, so the host can replay a fixed
+// batch of iterations (a captured graph) and read one flag per batch.
+namespace mq {
+
+constexpr int WIDE_BX = 256;
+
+#define WIDE_NODE                                                    \
+  const int i = blockIdx.x * WIDE_BX + threadIdx.x, j = blockIdx.y; \
+  const bool act = i < g.n;                                          \
+  const NodeRef nr = node_ref(g, act ? i : 0, j)
+
+// block partials of NV values (one per block, blocks numbered y * gridDim.x + x)
+template <int NV>
+__device__ inline void wide_partial(double (&v)[NV], double* part) {
+  __shared__ double red[2 * (WIDE_BX / 64) * 4];
+  int slot = 0;
+  block_sum<NV, WIDE_BX / 64>(v, red, slot);
+  if (threadIdx.x == 0) {
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) part[q * (size_t)gridDim.x * gridDim.y + b] = v[q];
+  }
+}
+
+template <typename VT>
+__device__ inline VT wide_dnode(const Geom& g, const VT* tD, double d_air, int i, int j, const NodeRef& nr) {
+  const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+  return box ? tD[nr.t] : (VT)d_air;
+}
+template <typename VT>
+__device__ inline VT wide_dinv(const Geom& g, const VT* tDi, double d_air, int i, int j, const NodeRef& nr) {
+  const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+  return box ? tDi[nr.t] : (VT)(1.0 / d_air);
+}
+
+// per-instance set-up (one workgroup): scaled tables, D^{+-1/2}, Galerkin
+// hierarchy, zero halos, initial state, scalars
+template <typename VT>
+__global__ __launch_bounds__(1024) void k_w_setup(Geom g, MGGeom mg, Solver sv, WidePtrs w, double inv_dt,
+                                                  const double* __restrict__ a_init) {
+  constexpr int NT = 1024;
+  __shared__ int s_dmin;
+  const int tid = threadIdx.x, RHW = g.RW * g.RH, n = g.n;
+  const double* tab = w.tab;
+  VT* tE = (VT*)w.tE;
+  VT* tN = (VT*)w.tN;
+  VT* tNE = (VT*)w.tNE;
+  VT* tD = (VT*)w.tD;
+  VT* tDi = (VT*)w.tDi;
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  auto dscale = [&](int i, int j) -> double {
+    if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
+      const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
+      return 1.0 / sqrt(tab[T_MC * RHW + t] * inv_dt + tab[T_KC * RHW + t]);
+    }
+    return d_air;
+  };
+  if (tid == 0) s_dmin = __float_as_int((float)d_air);
+  __syncthreads();
+  for (int t = tid; t < RHW; t += NT) {
+    const int i = g.bx0 - 1 + t % g.RW, j = g.by0 - 1 + t / g.RW;
+    const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+    const double di = dscale(i, j);
+    if (box) atomicMin(&s_dmin, __float_as_int((float)di));
+    double e = -0.25, nn = -0.25, ne = 0.0;
+    if (box) {
+      e = (tab[T_ME * RHW + t] * inv_dt + tab[T_KE * RHW + t]) * di * dscale(i + 1, j);
+      nn = (tab[T_MN * RHW + t] * inv_dt + tab[T_KN * RHW + t]) * di * dscale(i, j + 1);
+      ne = tab[T_MNE * RHW + t] * inv_dt * di * dscale(i + 1, j + 1);
+    }
+    tE[t] = (VT)e;
+    tN[t] = (VT)nn;
+    tNE[t] = (VT)ne;
+    tD[t] = (VT)di;
+    tDi[t] = (VT)(1.0 / di);
+  }
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int gi = (idx / n + 1) * g.P + idx % n + 1;
+    w.Av[gi] = a_init ? a_init[gi] : 0.0;
+    w.Xv[gi] = 0.0;
+    w.Xp[gi] = 0.0;
+  }
+  __syncthreads();
+  auto dn = [&](int i, int j) -> double {
+    if (i >= g.bx0 - 1 && i <= g.bx1 && j >= g.by0 - 1 && j <= g.by1)
+      return (double)tD[(j - g.by0 + 1) * g.RW + (i - g.bx0 + 1)];
+    return d_air;
+  };
+  build_galerkin<VT>(mg, (VT*)w.ctab, tE, tN, tNE, dn, true, d_air, g.RW, tid, NT);
+  for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, (VT*)w.mgreg, (VT*)w.ctab, NT), tid, NT);
+  if (tid == 0) {
+    const double dmin = (double)__int_as_float(s_dmin) * 0.999;
+    WideScal* sc = w.sc;
+    sc->floor_fac = sizeof(VT) == 4 ? 0.25 * sv.tol * sv.tol * dmin * dmin : 0.0;
+    sc->qsum = 0.0;
+    sc->flags = 0;
+    sc->it_total = 0;
+    sc->sweeps = 0;
+    sc->done = 1;
+  }
+}
+
+// b = J S - K a and partial ||b||^2
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_rhs(Geom g, WidePtrs w, double Jt) {
+  WIDE_NODE;
+  double v[1] = {0.0};
+  if (act) {
+    const double b = Jt * w.S[nr.gi] - K_apply(g, w.tab, w.Av, nr);
+    w.Bv[nr.gi] = b;
+    v[0] = b * b;
+  }
+  wide_partial<1>(v, w.part);
+}
+
+// FP64 residual r64 = b - A x, its scaled VT copy, fresh inner vectors
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_resid(Geom g, WidePtrs w, double inv_dt) {
+  WIDE_NODE;
+  double v[1] = {0.0};
+  if (act) {
+    const double res = w.Bv[nr.gi] - A_apply(g, w.tab, w.Xv, nr, inv_dt);
+    v[0] = res * res;
+    const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+    ((VT*)w.R)[nr.gi] = (VT)(res * (double)wide_dnode<VT>(g, (VT*)w.tD, d_air, i, j, nr));
+    ((VT*)w.Y)[nr.gi] = VT(0);
+    ((VT*)w.P)[nr.gi] = VT(0);
+    ((VT*)w.Q)[nr.gi] = VT(0);
+  }
+  wide_partial<1>(v, w.part);
+}
+
+enum { WRED_RHS = 0, WRED_RES = 1, WRED_RZ = 2, WRED_PQ = 3, WRED_QOI = 4 };
+
+// Sums the block partials in a fixed order and takes the scalar decisions.
+template <int KIND, int NV>
+__global__ __launch_bounds__(1024) void k_w_reduce(WidePtrs w, Solver sv, int nblk, double inv_dt) {
+  __shared__ double red[2 * 16 * 4];
+  WideScal* sc = w.sc;
+  if (KIND == WRED_RZ || KIND == WRED_PQ) {
+    if (sc->done) return;
+  }
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 1024) s += w.part[q * (size_t)nblk + b];
+    v[q] = s;
+  }
+  int slot = 0;
+  block_sum<NV, 16>(v, red, slot);
+  if (threadIdx.x != 0) return;
+  if (KIND == WRED_RHS) {
+    sc->bb = v[0];
+  } else if (KIND == WRED_RES) {
+    sc->rr = v[0];
+    sc->it = 0;
+    sc->rho = 1.0;
+    if (!(v[0] == v[0]) || isinf(v[0])) {
+      sc->flags |= FLAG_FAILED;
+      sc->conv = 1;
+    } else {
+      sc->conv = v[0] <= sv.tol * sv.tol * sc->bb ? 1 : 0;
+    }
+    sc->done = sc->conv;
+  } else if (KIND == WRED_RZ) {
+    const double rz = v[0], rr = v[1];
+    double beta = 0.0;
+    int done = 0;
+    if (sc->it == 0) {
+      sc->stop = fmax(sv.inner_rtol * sv.inner_rtol * rr, sc->floor_fac * sc->bb);
+      if (!(rr > 0.0) || !(rz > 0.0)) done = 1;
+    } else {
+      if (rr <= sc->stop || !(rr == rr)) done = 1;
+      else beta = rz / sc->rho;
+    }
+    if (!done) {
+      sc->rho = rz;
+      if (sc->it == sv.max_iter) {
+        done = 1;
+      } else {
+        sc->beta = beta;
+        sc->it += 1;
+        sc->it_total += 1;
+      }
+    }
+    sc->done = done;
+  } else if (KIND == WRED_PQ) {
+    sc->alpha = sc->rho / v[0];
+  } else {
+    sc->qsum += v[0] * inv_dt;
+  }
+}
+
+// pre-smoothing from zero: Z = om R, T = D^{1/2} (R - om A R)
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_pre(Geom g, WidePtrs w, VT om) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  if (!act) return;
+  const VT* R = (const VT*)w.R;
+  const VT r = R[nr.gi];
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  ((VT*)w.Z)[nr.gi] = om * r;
+  ((VT*)w.T)[nr.gi] = (r - om * stencil_scaled<VT>(g, R, (VT*)w.tE, (VT*)w.tN, (VT*)w.tNE, nr)) *
+                      wide_dinv<VT>(g, (VT*)w.tDi, d_air, i, j, nr);
+}
+
+// restriction of T to level 1: R_1 and Z_1 = om ID R_1 (ID R_1 if level 1 is the coarsest)
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_restrict1(Geom g, MGGeom mg, WidePtrs w, VT om, VT air) {
+  if (w.sc->done) return;
+  const int nthr = gridDim.x * blockDim.x, me = blockIdx.x * blockDim.x + threadIdx.x;
+  const CLev<VT> L1 = clev<VT>(mg, 1, (VT*)w.mgreg, (const VT*)w.ctab, nthr, air);
+  const int tx = me & ((1 << L1.txs) - 1), ty = nthr >> L1.txs;
+  if (tx >= L1.n) return;
+  const bool exact1 = mg.nlev == 1;
+  for (int jj = me >> L1.txs; jj < L1.n; jj += ty) {
+    const VT rc = restrict_at((const VT*)w.T, g.P, tx, jj);
+    const int q = (jj + 1) * L1.np + tx + 1;
+    L1.R[q] = rc;
+    L1.Z[q] = (exact1 ? VT(1) : om) * clev_id(L1, tx, jj) * rc;
+  }
+}
+
+enum { WC_RESID = 0, WC_RESTRICT = 1, WC_PROLONG = 2, WC_POST = 3 };
+
+// one coarse-level pass over the whole grid (levels too large for one workgroup)
+template <typename VT, int KIND>
+__global__ __launch_bounds__(WIDE_BX) void k_w_cpass(MGGeom mg, WidePtrs w, int l, VT om, VT air) {
+  if (w.sc->done) return;
+  const int nthr = gridDim.x * blockDim.x, me = blockIdx.x * blockDim.x + threadIdx.x;
+  VT* reg = (VT*)w.mgreg;
+  const VT* ctab = (const VT*)w.ctab;
+  const CLev<VT> F = clev<VT>(mg, l, reg, ctab, nthr, air);
+  if (KIND == WC_RESID) {
+    c_resid(F, me, nthr);
+  } else if (KIND == WC_RESTRICT) {
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, reg, ctab, nthr, air);
+    c_restrict(F, Cc, om, l + 1 == mg.nlev, me, nthr);
+  } else if (KIND == WC_PROLONG) {
+    const CLev<VT> Cc = clev<VT>(mg, l + 1, reg, ctab, nthr, air);
+    c_prolong(F, l + 1 == mg.nlev ? Cc.Z : Cc.T, Cc.np, me, nthr);
+  } else {
+    c_post(F, om, me, nthr);
+  }
+}
+
+// the coarse levels from lt down (one workgroup): the shifted hierarchy sub
+// has sub.lv[1] = level lt
+template <typename VT>
+__global__ __launch_bounds__(1024) void k_w_ctail(MGGeom sub, WidePtrs w, VT om, VT air) {
+  if (w.sc->done) return;
+  (void)coarse_cycle<VT, 1024>(sub, (VT*)w.mgreg, (const VT*)w.ctab, om, threadIdx.x, air);
+}
+
+// Z += D^{1/2} P z_1
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_prolong(Geom g, MGGeom mg, WidePtrs w, VT air) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  if (!act) return;
+  const CLev<VT> L1 = clev<VT>(mg, 1, (VT*)w.mgreg, (const VT*)w.ctab, 64, air);
+  const VT* z1 = mg.nlev == 1 ? L1.Z : L1.T;
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  ((VT*)w.Z)[nr.gi] += prolong_at(z1, L1.np, i, j) * wide_dinv<VT>(g, (VT*)w.tDi, d_air, i, j, nr);
+}
+
+// post-smoothing T = Z + om (R - A Z); partials r.T and r.r
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_post(Geom g, WidePtrs w, VT om) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  double v[2] = {0.0, 0.0};
+  if (act) {
+    const VT* Z = (const VT*)w.Z;
+    const VT r = ((const VT*)w.R)[nr.gi], z = Z[nr.gi];
+    const VT zn = z + om * (r - stencil_scaled<VT>(g, Z, (VT*)w.tE, (VT*)w.tN, (VT*)w.tNE, nr));
+    ((VT*)w.T)[nr.gi] = zn;
+    v[0] = (double)(r * zn);
+    v[1] = (double)(r * r);
+  }
+  wide_partial<2>(v, w.part);
+}
+
+// p = z + beta p, q = A z + beta q (z in T); partial p.q
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_pq(Geom g, WidePtrs w) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  double v[1] = {0.0};
+  if (act) {
+    const VT b_ = (VT)w.sc->beta;
+    const bool first = w.sc->it == 1;
+    const VT* Zt = (const VT*)w.T;
+    VT* Pv = (VT*)w.P;
+    VT* Qv = (VT*)w.Q;
+    const VT az = stencil_scaled<VT>(g, Zt, (VT*)w.tE, (VT*)w.tN, (VT*)w.tNE, nr);
+    const VT p = first ? Zt[nr.gi] : Zt[nr.gi] + b_ * Pv[nr.gi];
+    const VT q = first ? az : az + b_ * Qv[nr.gi];
+    Pv[nr.gi] = p;
+    Qv[nr.gi] = q;
+    v[0] = (double)(p * q);
+  }
+  wide_partial<1>(v, w.part);
+}
+
+// y += alpha p, r -= alpha q
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_yr(Geom g, WidePtrs w) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  if (!act) return;
+  const VT a_ = (VT)w.sc->alpha;
+  ((VT*)w.Y)[nr.gi] += a_ * ((const VT*)w.P)[nr.gi];
+  ((VT*)w.R)[nr.gi] -= a_ * ((const VT*)w.Q)[nr.gi];
+}
+
+// x += D^{-1/2} y
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_xupd(Geom g, WidePtrs w) {
+  WIDE_NODE;
+  if (!act) return;
+  const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
+  w.Xv[nr.gi] += (double)wide_dnode<VT>(g, (VT*)w.tD, d_air, i, j, nr) * (double)((const VT*)w.Y)[nr.gi];
+}
+
+// partial x^T M x over the lookup region
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_qoi(Geom g, WidePtrs w) {
+  WIDE_NODE;
+  double v[1] = {0.0};
+  if (act && nr.inL) v[0] = w.Xv[nr.gi] * M_apply(g, w.tab, w.Xv, nr);
+  wide_partial<1>(v, w.part);
+}
+
+// a += x; next start 2 x - x_prev; x_prev = x
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_state(Geom g, WidePtrs w) {
+  WIDE_NODE;
+  if (!act) return;
+  const double d = w.Xv[nr.gi];
+  w.Av[nr.gi] += d;
+  w.Xv[nr.gi] = 2.0 * d - w.Xp[nr.gi];
+  w.Xp[nr.gi] = d;
+}
+
+__global__ void k_w_finish(Geom g, WidePtrs w, double q_scale, double* q_out, double* a_out) {
+  const int n = g.n;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
+    const int gi = (idx / n + 1) * g.P + idx % n + 1;
+    if (a_out) a_out[gi] = w.Av[gi];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && q_out) *q_out = w.sc->qsum * q_scale;
+}
+
+// ---- host launchers ----
+static dim3 wide_grid(const WideCtx& c) { return dim3((c.g.n + WIDE_BX - 1) / WIDE_BX, c.g.n); }
+
+// 1-D grid with one thread per node of coarse level l (2^s columns >= n_l)
+static int wide_cblocks(const MGGeom& mg, int l) {
+  int s = 0;
+  while ((1 << s) < mg.lv[l].n) ++s;
+  const long t = (long)(2 << s) * mg.lv[l].n;
+  return (int)((t + WIDE_BX - 1) / WIDE_BX);
+}
+
+template <typename VT>
+static hipError_t wide_setup_t(const WideCtx& c, double inv_dt, const double* a_init, hipStream_t st) {
+  hipLaunchKernelGGL((k_w_setup<VT>), dim3(1), dim3(1024), 0, st, c.g, c.mg, c.sv, c.w, inv_dt, a_init);
+  return hipGetLastError();
+}
+template <typename VT>
+static hipError_t wide_rhs_t(const WideCtx& c, double Jt, hipStream_t st) {
+  hipLaunchKernelGGL((k_w_rhs<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w, Jt);
+  hipLaunchKernelGGL((k_w_reduce<WRED_RHS, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+  return hipGetLastError();
+}
+template <typename VT>
+static hipError_t wide_resid_t(const WideCtx& c, double inv_dt, hipStream_t st) {
+  hipLaunchKernelGGL((k_w_resid<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w, inv_dt);
+  hipLaunchKernelGGL((k_w_reduce<WRED_RES, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+  return hipGetLastError();
+}
+template <typename VT>
+static hipError_t wide_iteration_t(const WideCtx& c, hipStream_t st) {
+  const VT om = (VT)c.sv.mg_omega, air = (VT)c.air;
+  const dim3 gr = wide_grid(c), bl(WIDE_BX);
+  hipLaunchKernelGGL((k_w_pre<VT>), gr, bl, 0, st, c.g, c.w, om);
+  hipLaunchKernelGGL((k_w_restrict1<VT>), dim3(wide_cblocks(c.mg, 1)), bl, 0, st, c.g, c.mg, c.w, om, air);
+  for (int l = 1; l < c.lt; ++l) {
+    hipLaunchKernelGGL((k_w_cpass<VT, WC_RESID>), dim3(wide_cblocks(c.mg, l)), bl, 0, st, c.mg, c.w, l, om, air);
+    hipLaunchKernelGGL((k_w_cpass<VT, WC_RESTRICT>), dim3(wide_cblocks(c.mg, l + 1)), bl, 0, st, c.mg, c.w, l, om,
+                       air);
+  }
+  hipLaunchKernelGGL((k_w_ctail<VT>), dim3(1), dim3(1024), 0, st, c.sub, c.w, om, air);
+  for (int l = c.lt - 1; l >= 1; --l) {
+    hipLaunchKernelGGL((k_w_cpass<VT, WC_PROLONG>), dim3(wide_cblocks(c.mg, l)), bl, 0, st, c.mg, c.w, l, om, air);
+    hipLaunchKernelGGL((k_w_cpass<VT, WC_POST>), dim3(wide_cblocks(c.mg, l)), bl, 0, st, c.mg, c.w, l, om, air);
+  }
+  hipLaunchKernelGGL((k_w_prolong<VT>), gr, bl, 0, st, c.g, c.mg, c.w, air);
+  hipLaunchKernelGGL((k_w_post<VT>), gr, bl, 0, st, c.g, c.w, om);
+  hipLaunchKernelGGL((k_w_reduce<WRED_RZ, 2>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+  hipLaunchKernelGGL((k_w_pq<VT>), gr, bl, 0, st, c.g, c.w);
+  hipLaunchKernelGGL((k_w_reduce<WRED_PQ, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+  hipLaunchKernelGGL((k_w_yr<VT>), gr, bl, 0, st, c.g, c.w);
+  return hipGetLastError();
+}
+template <typename VT>
+static hipError_t wide_xupd_t(const WideCtx& c, hipStream_t st) {
+  hipLaunchKernelGGL((k_w_xupd<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
+  return hipGetLastError();
+}
+template <typename VT>
+static hipError_t wide_end_step_t(const WideCtx& c, double inv_dt, hipStream_t st) {
+  hipLaunchKernelGGL((k_w_qoi<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
+  hipLaunchKernelGGL((k_w_reduce<WRED_QOI, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, inv_dt);
+  hipLaunchKernelGGL((k_w_state<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
+  return hipGetLastError();
+}
+
+#define WIDE_DISPATCH(fn, ...) \
+  return c.sv.precision == MQ_PREC_FP64 ? fn<double>(c, __VA_ARGS__) : fn<float>(c, __VA_ARGS__)
+hipError_t wide_setup(const WideCtx& c, double inv_dt, const double* a_init, hipStream_t st) {
+  WIDE_DISPATCH(wide_setup_t, inv_dt, a_init, st);
+}
+hipError_t wide_rhs(const WideCtx& c, double Jt, hipStream_t st) { WIDE_DISPATCH(wide_rhs_t, Jt, st); }
+hipError_t wide_resid(const WideCtx& c, double inv_dt, hipStream_t st) { WIDE_DISPATCH(wide_resid_t, inv_dt, st); }
+hipError_t wide_iteration(const WideCtx& c, hipStream_t st) { WIDE_DISPATCH(wide_iteration_t, st); }
+hipError_t wide_xupd(const WideCtx& c, hipStream_t st) { WIDE_DISPATCH(wide_xupd_t, st); }
+hipError_t wide_end_step(const WideCtx& c, double inv_dt, hipStream_t st) { WIDE_DISPATCH(wide_end_step_t, inv_dt, st); }
+#undef WIDE_DISPATCH
+hipError_t wide_finish(const WideCtx& c, double q_scale, double* q_out, double* a_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_w_finish, dim3(256), dim3(256), 0, st, c.g, c.w, q_scale, q_out, a_out);
+  return hipGetLastError();
+}
+int wide_blocks(const Geom& g) { return ((g.n + WIDE_BX - 1) / WIDE_BX) * g.n; }
 
 }  // namespace mq

@@ -120,6 +120,40 @@ struct Solver {
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
 enum { STAT_N = 17 };
 
+// Wide path (one instance over the whole device): solver scalars in device
+// memory, the instance's buffers, and the launch context.
+struct WideScal {
+  double bb, rr, rho, beta, alpha, stop, floor_fac, qsum;
+  int it, done, conv, flags, it_total, sweeps;
+};
+struct WidePtrs {
+  double *Av, *Xv, *Bv, *Xp;                 // FP64 full grid
+  void *R, *Y, *P, *Z, *T, *Q;               // VT full grid
+  void *tE, *tN, *tNE, *tD, *tDi, *mgreg, *ctab;
+  double* part;                              // block partials [2][blocks]
+  WideScal* sc;
+  const double* tab;                         // the sample's FP64 tables
+  const double* S;
+};
+struct WideCtx {
+  Geom g;
+  MGGeom mg;   // full hierarchy
+  MGGeom sub;  // levels lt..nlev renumbered from 1 (run by one workgroup)
+  Solver sv;
+  WidePtrs w;
+  int lt;      // first coarse level handled by one workgroup
+  int nblk;    // blocks of a fine-level pass
+  double air;  // air diagonal of the coarse levels (4 nu_air)
+};
+hipError_t wide_setup(const WideCtx& c, double inv_dt, const double* a_init, hipStream_t st);
+hipError_t wide_rhs(const WideCtx& c, double Jt, hipStream_t st);
+hipError_t wide_resid(const WideCtx& c, double inv_dt, hipStream_t st);
+hipError_t wide_iteration(const WideCtx& c, hipStream_t st);
+hipError_t wide_xupd(const WideCtx& c, hipStream_t st);
+hipError_t wide_end_step(const WideCtx& c, double inv_dt, hipStream_t st);
+hipError_t wide_finish(const WideCtx& c, double q_scale, double* q_out, double* a_out, hipStream_t st);
+int wide_blocks(const Geom& g);
+
 // Launch helpers implemented in the .hip translation units.
 // tile: resident workgroup shape (1: 16 rows per thread, 2: 32 rows per thread)
 int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_limit, int* lds_bytes, int tile);

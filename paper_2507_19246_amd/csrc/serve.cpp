@@ -479,6 +479,8 @@ int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out) {
   *out = nullptr;
   if (sd->base.material == MQ_MAT_NONLINEAR)
     return fail(MQ_ERR_INVALID_ARG, "the server runs linear materials");
+  if (sd->base.path == MQ_PATH_WIDE)
+    return fail(MQ_ERR_INVALID_ARG, "the server batches requests: resident or streaming path");
   if (sd->hbm_budget_bytes <= 0 || sd->max_inflight < 1 || sd->n_streams < 0 || sd->n_streams > 8 ||
       sd->max_batch < 0 || sd->chunk_steps < 0)
     return fail(MQ_ERR_INVALID_ARG, "bad server limits");
