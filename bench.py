@@ -357,10 +357,11 @@ def bench_adaptive(args, mq, L, W, np, torch):
     return res
 
 
-def _serve(mq, L, W, np, torch, reqs, limit_s, label):
+def _serve(mq, L, W, np, torch, reqs, limit_s, label, wide_min_nodes=0, wide_load_limit=0):
     """Submit `reqs` at their arrival times into a fresh server; wait for all results."""
     base = W.Problem(65, W.Material(kind=W.MAT_KL))
-    srv = mq.Server(base, L.MQ_PREC_MIXED, hbm_budget_bytes=96 << 30, max_inflight=4096, n_streams=2)
+    srv = mq.Server(base, L.MQ_PREC_MIXED, hbm_budget_bytes=96 << 30, max_inflight=4096, n_streams=2,
+                    wide_min_nodes=wide_min_nodes, wide_load_limit=wide_load_limit)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_report = t0
@@ -402,19 +403,23 @@ def bench_serving(args, mq, L, W, np, torch):
     """Poisson request stream into the continuous-batching server: the offered
     rate (saturating), then a stable load at 0.7 x the measured capacity."""
     reqs = W.serving_stream(args.requests, rate_hz=args.rate)
-    sat = _serve(mq, L, W, np, torch, reqs, args.serving_limit_s, "offered rate")
+    sat = _serve(mq, L, W, np, torch, reqs, args.serving_limit_s, "offered rate", args.wide_min_nodes,
+                 args.wide_load_limit)
     args.steps, args.warmup = 1, 0
     res = _contract("sample-steps/s", sat["sample_steps_per_s"], sat["wall_s"], args, {
         "workload": f"serving-kl8-mixed-{len(reqs)}req-{args.rate:g}rps",
         "meshes": list(W.SERVING_MESHES), "mesh_weights": list(W.SERVING_MESH_WEIGHTS),
         "steps_per_period": list(W.SERVING_STEPS), "n_periods": 2, "requests": len(reqs),
-        "rate_req_per_s": args.rate, "lanes_per_mesh": 2, "chunk_steps": 32})
+        "rate_req_per_s": args.rate, "lanes_per_mesh": 2, "chunk_steps": 32,
+        "wide_min_nodes": 513 if args.wide_min_nodes == 0 else args.wide_min_nodes,
+        "wide_load_limit": args.wide_load_limit or "half the compute units",
+        "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None})
     res.update({k: sat[k] for k in ("p50_latency_ms", "p99_latency_ms", "requests_per_s", "failed",
                                     "latency_ms_by_mesh")})
     if args.stable_requests > 0:
         rate = 0.7 * sat["requests_per_s"]
         st = _serve(mq, L, W, np, torch, W.serving_stream(args.stable_requests, rate_hz=rate),
-                    args.serving_limit_s, "stable load")
+                    args.serving_limit_s, "stable load", args.wide_min_nodes, args.wide_load_limit)
         st["rate_req_per_s"] = rate
         st["requests"] = args.stable_requests
         res["stable_load"] = st
@@ -435,6 +440,12 @@ def main():
     ap.add_argument("--target-rmse", type=float, default=50.0, help="adaptive: target RMSE of the estimate (W/m)")
     ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
+    ap.add_argument("--wide-min-nodes", type=int, default=0,
+                    help="serving: smallest mesh of the wide lane (0: the library default 513; -1: no wide lane)")
+    ap.add_argument("--wide-load-limit", type=int, default=0,
+                    help="serving: batched requests above which the wide lane is not used (0: library default)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="serving: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0: leave as set)")
     ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
     ap.add_argument("--no-serial", action="store_true", help="parareal: skip the batched serial comparison run")
     ap.add_argument("--coarse-steps", type=int, default=0,
@@ -448,6 +459,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serving" and args.hw_queues > 0:
+        # two lanes (streams) per mesh size plus the wide lane: streams beyond the
+        # process's hardware queues share one and run one after another
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np
     import torch
 

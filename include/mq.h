@@ -279,7 +279,8 @@ int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const dou
  * the device with those already running.  Launches split a request at fixed
  * request-relative steps and resume it exactly, so its result is the same bit
  * for bit whatever else the server runs, and equal to mlmc_level_run of the
- * same input at level 0.  Device memory (per-mesh work buffers, request slots)
+ * same input at level 0 (for a request of the wide lane, below: on a problem
+ * set up with path MQ_PATH_WIDE).  Device memory (per-mesh work buffers, request slots)
  * is kept for reuse until mq_server_destroy and counts against the budget. */
 typedef struct mq_server_desc {
   mq_problem_desc base;      /* material/precision/tolerances; n_nodes ignored; linear */
@@ -288,6 +289,16 @@ typedef struct mq_server_desc {
   int32_t n_streams;         /* lanes per mesh size, 0..8 (0: 2) */
   int32_t max_batch;         /* requests in one launch at most (0: 4096) */
   int32_t chunk_steps;       /* steps per request per launch (0: 32) */
+  int32_t wide_min_nodes;    /* requests with n_nodes >= this (and n_nodes = 2^k + 1, multigrid
+                                allowed by base) run one at a time on the wide path, over the
+                                whole device, while fewer than wide_load_limit batched requests
+                                are admitted and at most wide_queue of them wait; otherwise they
+                                are batched.  0: 513; -1: never.  The wide lane's set-up (one
+                                work slot per mesh size) is outside hbm_budget_bytes and its
+                                requests outside max_inflight. */
+  int32_t wide_queue;        /* wide-lane requests allowed to wait (0: 8) */
+  int32_t wide_load_limit;   /* see wide_min_nodes (0: half the device's compute units) */
+  int32_t reserved;
 } mq_server_desc;
 
 typedef struct mq_request {

@@ -91,7 +91,9 @@ class AdaptiveDesc(C.Structure):
 
 class ServerDesc(C.Structure):
     _fields_ = [("base", ProblemDesc), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
-                ("n_streams", C.c_int32), ("max_batch", C.c_int32), ("chunk_steps", C.c_int32)]
+                ("n_streams", C.c_int32), ("max_batch", C.c_int32), ("chunk_steps", C.c_int32),
+                ("wide_min_nodes", C.c_int32), ("wide_queue", C.c_int32), ("wide_load_limit", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Request(C.Structure):

@@ -221,7 +221,8 @@ class Server:
     """Continuous-batching request server (mq_server_*)."""
 
     def __init__(self, base_problem, precision: int, hbm_budget_bytes: int, max_inflight: int = 1024,
-                 n_streams: int = 2, max_batch: int = 0, chunk_steps: int = 0, **solver):
+                 n_streams: int = 2, max_batch: int = 0, chunk_steps: int = 0, wide_min_nodes: int = 0,
+                 wide_queue: int = 0, wide_load_limit: int = 0, **solver):
         self.lib = L.load()
         sd = L.ServerDesc()
         sd.base = default_desc(base_problem, precision, **solver)
@@ -230,6 +231,9 @@ class Server:
         sd.n_streams = n_streams
         sd.max_batch = max_batch
         sd.chunk_steps = chunk_steps
+        sd.wide_min_nodes = wide_min_nodes
+        sd.wide_queue = wide_queue
+        sd.wide_load_limit = wide_load_limit
         self.desc = sd
         h = C.c_void_p()
         L.check(self.lib.mq_server_create(C.byref(sd), _stream(), C.byref(h)))

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -71,6 +72,9 @@ struct mq_problem {
   // per-slot work buffers (grown on demand, zeroed when allocated)
   mq::DevPtr<double> work;
   size_t work_slots = 0;
+  // wide path: called on the host between time steps (may block to let other
+  // work have the device); empty: none
+  std::function<void()> wide_yield;
 };
 
 namespace mq {

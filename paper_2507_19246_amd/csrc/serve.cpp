@@ -12,6 +12,19 @@
 // other lanes and classes.  Launch boundaries sit at fixed request-relative
 // steps and the kernels resume bit for bit (Inst::carry), so a request's
 // result does not depend on what else the server is running.
+//
+// Requests on large multigrid meshes (n_nodes >= wide_min_nodes) go instead to
+// the wide lane while the device has room and its queue is short: a worker
+// thread that runs them one at a time, each over the whole device (the wide
+// path), which cuts their latency from one workgroup's pace to the device's.
+// Batched, such a request costs one workgroup; wide, it takes every compute
+// unit at a lower efficiency (and its stream of short kernels keeps the
+// batched launches' large workgroups from finding free compute units), so a
+// large request is routed to the lane only while fewer than wide_load_limit
+// batched requests are admitted and at most wide_queue wait for it, and the
+// lane pauses between time steps while the batched load is at or above that
+// limit.  A request runs on one path from start to end, so its result stays
+// the same bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +53,23 @@ int64_t now_ns() {
 constexpr int SLAB = 16;          // request slots allocated at a time
 constexpr int XI_SLOT = 16;       // doubles reserved for a request's input
 
+// Pinned host memory (asynchronous copies that never wait for the device).
+template <typename T>
+struct PinnedPtr {
+  T* p = nullptr;
+  PinnedPtr() = default;
+  PinnedPtr(const PinnedPtr&) = delete;
+  PinnedPtr& operator=(const PinnedPtr&) = delete;
+  ~PinnedPtr() {
+    if (p) (void)hipHostFree(p);
+  }
+  T* get() const { return p; }
+};
+template <typename T>
+hipError_t pinned_alloc(PinnedPtr<T>& h, size_t count) {
+  return hipHostMalloc((void**)&h.p, (count > 0 ? count : 1) * sizeof(T), hipHostMallocDefault);
+}
+
 struct Req {
   mq_request rq;
   uint64_t ticket = 0;
@@ -52,6 +82,12 @@ struct Req {
   bool initialised = false;
 };
 
+// The scheduler thread never waits for a stream: a lane's instance table and
+// the inputs of new requests go up from pinned buffers, and the launch's
+// statistics and the QoI of the requests it completes come back into pinned
+// buffers before its `done` event, all sized for max_batch requests when the
+// lane is activated.  (Streams share the process's hardware queues, so a
+// blocking copy could wait for another lane's whole launch.)
 struct Lane {
   mq_problem* p = nullptr;
   hipStream_t stream = nullptr;
@@ -59,10 +95,25 @@ struct Lane {
   bool busy = false;
   std::vector<Req*> running;
   std::vector<Inst> insts;
-  std::vector<int> stat_host;
   DevPtr<Inst> dinst;
   DevPtr<int> dstat;
+  PinnedPtr<Inst> hinst;
+  PinnedPtr<int> hstat;
+  PinnedPtr<double> hq;   // QoI of the requests that complete in the launch, by launch position
+  PinnedPtr<double> hxi;  // inputs of the requests initialised by the launch
   size_t cap = 0;
+};
+
+// J(t_k) of one time grid: FP64 on the host, uploaded once per class from a
+// pinned copy on the stream of the lane that first needs it; other lanes wait
+// for `ready` before using it.
+struct SrcTable {
+  DevPtr<double> dev;
+  PinnedPtr<double> host;
+  hipEvent_t ready = nullptr;
+  ~SrcTable() {
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 struct Class {
@@ -72,7 +123,7 @@ struct Class {
   std::vector<double*> slot_ptr;
   std::vector<int> free_slots;
   std::vector<std::unique_ptr<Lane>> lanes;
-  std::map<std::pair<int, int64_t>, DevPtr<double>> src;  // (steps/period, steps) -> J(t_k)
+  std::map<std::pair<int, int64_t>, std::unique_ptr<SrcTable>> src;  // (steps/period, steps) -> J(t_k)
   std::vector<Req*> active;                                // admitted, in admission order
   size_t lane_slots = 0;
   int64_t fixed_bytes = 0;  // lane work buffers
@@ -99,7 +150,16 @@ struct mq_server {
   // scheduler-thread state
   std::map<int, std::unique_ptr<Class>> classes;
   int64_t used_bytes = 0;
-  int inflight = 0;
+  std::atomic<int> inflight{0};  // admitted batched requests (written by the scheduler only)
+  // wide lane (queue and count guarded by mu)
+  int wide_min = 0;  // 0: no wide lane
+  int wide_queue = 8;
+  int wide_load = 128;
+  bool wide_mg = false;  // the base description allows multigrid
+  std::deque<Req*> wq;
+  int wide_count = 0;  // queued + running on the wide lane
+  std::condition_variable wcv;
+  std::thread wth;
 };
 
 namespace {
@@ -123,8 +183,9 @@ void finish(mq_server* s, Req* r, int status, double q) {
 }
 
 void destroy_class(Class& c) {
-  for (auto& L : c.lanes) {
+  for (auto& L : c.lanes)
     if (L->stream) (void)hipStreamSynchronize(L->stream);
+  for (auto& L : c.lanes) {
     L->dinst.reset();
     L->dstat.reset();
     if (L->p) mq_problem_destroy(L->p);
@@ -177,30 +238,45 @@ int make_class(mq_server* s, int n_nodes, std::unique_ptr<Class>* out) {
 
 int64_t slab_bytes(const Class& c) { return (int64_t)(SLAB * c.slot_d * sizeof(double)); }
 
-int activate(Class& c) {
+// Work buffers and per-lane tables (the work buffer is cleared on each lane's
+// own stream, ahead of its first launch).
+int activate(mq_server* s, Class& c) {
+  const size_t cap = (size_t)s->max_batch;
   for (auto& L : c.lanes) {
     int rc = ensure_work(L->p, c.lane_slots);
     if (rc) return rc;
-    HIP_TRY(hipStreamSynchronize(L->stream));
+    if (L->cap < cap) {
+      HIP_TRY(dev_alloc(L->dinst, cap));
+      HIP_TRY(dev_alloc(L->dstat, cap * STAT_N));
+      HIP_TRY(pinned_alloc(L->hinst, cap));
+      HIP_TRY(pinned_alloc(L->hstat, cap * STAT_N));
+      HIP_TRY(pinned_alloc(L->hq, cap));
+      HIP_TRY(pinned_alloc(L->hxi, cap * XI_SLOT));
+      L->cap = cap;
+    }
   }
   c.ready = true;
   return MQ_OK;
 }
 
-// Source table for one time grid (host sin in FP64, uploaded once per class).
-int source_for(Class& c, const mq_problem_desc& d, int spp, int64_t n_total, const double** out) {
+// Source table for one time grid, enqueued on lane L's stream.
+int source_for(Class& c, Lane& L, const mq_problem_desc& d, int spp, int64_t n_total, const double** out) {
   auto key = std::make_pair(spp, n_total);
   auto it = c.src.find(key);
   if (it == c.src.end()) {
     auto h = source_table(d, 1.0 / (d.freq * spp), (int)n_total);
-    DevPtr<double> t;
-    HIP_TRY(dev_alloc(t, h.size()));
-    Lane& L0 = *c.lanes[0];
-    HIP_TRY(hipMemcpyAsync(t.get(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, L0.stream));
-    HIP_TRY(hipStreamSynchronize(L0.stream));
+    auto t = std::make_unique<SrcTable>();
+    HIP_TRY(dev_alloc(t->dev, h.size()));
+    HIP_TRY(pinned_alloc(t->host, h.size()));
+    std::memcpy(t->host.get(), h.data(), h.size() * sizeof(double));
+    HIP_TRY(hipEventCreateWithFlags(&t->ready, hipEventDisableTiming));
+    HIP_TRY(hipMemcpyAsync(t->dev.get(), t->host.get(), h.size() * sizeof(double), hipMemcpyHostToDevice, L.stream));
+    HIP_TRY(hipEventRecord(t->ready, L.stream));
     it = c.src.emplace(key, std::move(t)).first;
+  } else {
+    HIP_TRY(hipStreamWaitEvent(L.stream, it->second->ready, 0));
   }
-  *out = it->second.get();
+  *out = it->second->dev.get();
   return MQ_OK;
 }
 
@@ -208,15 +284,8 @@ int source_for(Class& c, const mq_problem_desc& d, int spp, int64_t n_total, con
 // requests that reached their last step.
 void retire(mq_server* s, Class& c, Lane& L, hipError_t q) {
   L.busy = false;
-  int rc = q == hipSuccess ? MQ_OK : MQ_ERR_DEVICE;
+  const int rc = q == hipSuccess ? MQ_OK : MQ_ERR_DEVICE;
   const size_t n = L.running.size();
-  if (rc == MQ_OK) {
-    L.stat_host.resize(n * STAT_N);
-    if (hipMemcpyAsync(L.stat_host.data(), L.dstat.get(), n * STAT_N * sizeof(int), hipMemcpyDeviceToHost,
-                       L.stream) != hipSuccess ||
-        hipStreamSynchronize(L.stream) != hipSuccess)
-      rc = MQ_ERR_DEVICE;
-  }
   std::vector<Req*> fin;
   std::vector<double> qh;
   for (size_t i = 0; i < n; ++i) {
@@ -226,23 +295,17 @@ void retire(mq_server* s, Class& c, Lane& L, hipError_t q) {
       r->flags |= FLAG_FAILED;
       r->done_steps = r->n_total;
     } else {
-      const int* st = &L.stat_host[i * STAT_N];
+      const int* st = L.hstat.get() + i * STAT_N;
       r->done_steps += L.insts[i].n_steps;
       r->iters += st[0];
       r->flags |= st[3];
     }
-    if (r->done_steps >= r->n_total) fin.push_back(r);
+    if (r->done_steps >= r->n_total) {
+      fin.push_back(r);
+      qh.push_back(rc == MQ_OK ? L.hq.get()[i] : NAN);
+    }
   }
   L.running.clear();
-  if (fin.empty()) return;
-  qh.assign(fin.size(), NAN);
-  if (rc == MQ_OK) {
-    for (size_t i = 0; i < fin.size(); ++i) {
-      const double* qd = c.slot_ptr[fin[i]->slot] + c.tab + 3 * c.FS + 1;
-      if (hipMemcpyAsync(&qh[i], qd, sizeof(double), hipMemcpyDeviceToHost, L.stream) != hipSuccess) rc = MQ_ERR_DEVICE;
-    }
-    if (hipStreamSynchronize(L.stream) != hipSuccess) rc = MQ_ERR_DEVICE;
-  }
   for (size_t i = 0; i < fin.size(); ++i) {
     Req* r = fin[i];
     c.active.erase(std::find(c.active.begin(), c.active.end(), r));
@@ -280,15 +343,18 @@ int launch_lane(mq_server* s, Class& c, Lane& L, const std::vector<Req*>& pick) 
     double* q = carry + 2 * c.FS + 1;
     double* xi = q + 1;
     if (!r->initialised) {
-      // request input -> device, per-sample tables, zero initial state
-      HIP_TRY(hipMemcpyAsync(xi, r->rq.xi, sizeof(double) * s->n_xi, hipMemcpyHostToDevice, L.stream));
+      // request input -> device (through the lane's pinned buffer), per-sample
+      // tables, zero initial state
+      double* hx = L.hxi.get() + L.insts.size() * XI_SLOT;
+      std::memcpy(hx, r->rq.xi, sizeof(double) * s->n_xi);
+      HIP_TRY(hipMemcpyAsync(xi, hx, sizeof(double) * s->n_xi, hipMemcpyHostToDevice, L.stream));
       HIP_TRY(launch_assemble(g, L.p->hm.cr, L.p->dcond.get(), L.p->dkl.get(), L.p->hm.n_modes, d.material, xi,
                               s->n_xi, 1, L.p->mat, tab, L.stream));
       HIP_TRY(launch_fill_zero(a, c.FS, L.stream));
       r->initialised = true;
     }
     const double* src = nullptr;
-    int rc = source_for(c, d, r->rq.steps_per_period, r->n_total, &src);
+    int rc = source_for(c, L, d, r->rq.steps_per_period, r->n_total, &src);
     if (rc) return rc;
     Inst in{};
     in.tab = tab;
@@ -316,23 +382,26 @@ int launch_lane(mq_server* s, Class& c, Lane& L, const std::vector<Req*>& pick) 
   }
   L.insts.swap(ins);
   const size_t n = L.insts.size();
-  if (L.cap < n) {
-    L.dinst.reset();
-    L.dstat.reset();
-    L.cap = 0;
-    HIP_TRY(dev_alloc(L.dinst, n));
-    HIP_TRY(dev_alloc(L.dstat, n * STAT_N));
-    L.cap = n;
-  }
+  if (n > L.cap) return fail(MQ_ERR_INVALID_ARG, "launch larger than the lane's tables");
   for (size_t i = 0; i < n; ++i) L.insts[i].stat = L.dstat.get() + STAT_N * i;
+  std::memcpy(L.hinst.get(), L.insts.data(), n * sizeof(Inst));
   HIP_TRY(launch_fill_zero_i(L.dstat.get(), n * STAT_N, L.stream));
-  HIP_TRY(hipMemcpyAsync(L.dinst.get(), L.insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, L.stream));
+  HIP_TRY(hipMemcpyAsync(L.dinst.get(), L.hinst.get(), n * sizeof(Inst), hipMemcpyHostToDevice, L.stream));
   int grid = 0, block = 0;
   int rc = launch_persistent(L.p, L.dinst.get(), (int)n, &grid, &block);
   if (rc) return rc;
+  // statistics, and the QoI of every request this launch completes, come back
+  // ahead of the event
+  HIP_TRY(hipMemcpyAsync(L.hstat.get(), L.dstat.get(), n * STAT_N * sizeof(int), hipMemcpyDeviceToHost, L.stream));
+  for (size_t i = 0; i < n; ++i) {
+    Req* r = L.running[i];
+    if (r->done_steps + L.insts[i].n_steps < r->n_total) continue;
+    const double* qd = c.slot_ptr[r->slot] + c.tab + 3 * c.FS + 1;
+    HIP_TRY(hipMemcpyAsync(L.hq.get() + i, qd, sizeof(double), hipMemcpyDeviceToHost, L.stream));
+  }
   HIP_TRY(hipEventRecord(L.done, L.stream));
-  // the instance table and the inputs are read by the stream: keep the host
-  // copy (L.insts) until the launch has been retired
+  // the pinned tables and inputs are read by the stream: they are not
+  // rewritten before the launch has been retired
   const int64_t t = now_ns();
   for (Req* r : L.running) {
     r->running = true;
@@ -340,6 +409,74 @@ int launch_lane(mq_server* s, Class& c, Lane& L, const std::vector<Req*>& pick) 
   }
   L.busy = true;
   return MQ_OK;
+}
+
+// Large meshes with a multigrid hierarchy (n_nodes = 2^k + 1) may use the wide lane.
+bool wide_eligible(const mq_server* s, int n_nodes) {
+  if (s->wide_min <= 0 || !s->wide_mg || n_nodes < s->wide_min) return false;
+  const int m = n_nodes - 1;
+  return m >= 2 && (m & (m - 1)) == 0;
+}
+
+// The wide lane: runs its requests one at a time with mlmc_level_run on a
+// wide-path problem per mesh size (set up on first use, kept until the
+// server ends).
+void wide_worker(mq_server* s) {
+  (void)hipSetDevice(s->device);
+  hipStream_t st = nullptr;
+  std::map<int, mq_problem*> probs;
+  DevPtr<double> buf;  // xi | q
+  bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            dev_alloc(buf, XI_SLOT + 1) == hipSuccess;
+  for (;;) {
+    Req* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->wcv.wait(lk, [&] { return s->stop.load() || !s->wq.empty(); });
+      if (s->stop.load()) break;
+      r = s->wq.front();
+      s->wq.pop_front();
+    }
+    r->t_start = now_ns();
+    int status = MQ_ERR_DEVICE;
+    double q = NAN;
+    if (ok) {
+      mq_problem*& p = probs[r->rq.n_nodes];
+      int rc = MQ_OK;
+      if (!p) {
+        mq_problem_desc d = s->sd.base;
+        d.n_nodes = r->rq.n_nodes;
+        d.path = MQ_PATH_WIDE;
+        rc = fem_setup(&d, (void*)st, &p);
+        if (rc != MQ_OK) p = nullptr;
+        else
+          p->wide_yield = [s] {
+            while (s->inflight.load() >= s->wide_load && !s->stop.load())
+              std::this_thread::sleep_for(std::chrono::microseconds(500));
+          };
+      }
+      if (rc == MQ_OK &&
+          hipMemcpyAsync(buf.get(), r->rq.xi, sizeof(double) * s->n_xi, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = MQ_ERR_DEVICE;
+      if (rc == MQ_OK) {
+        const mq_level_desc lv{r->rq.steps_per_period, 0, r->rq.n_periods, 0};
+        mq_run_stats rs{};
+        rc = mlmc_level_run(p, &lv, 1, buf.get(), buf.get() + XI_SLOT, nullptr, nullptr, &rs);
+        r->iters = rs.inner_iters;
+        if (rc >= 0 && (hipMemcpyAsync(&q, buf.get() + XI_SLOT, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
+          rc = MQ_ERR_DEVICE;
+      }
+      status = rc;
+      if (status >= 0 && !std::isfinite(q)) status = MQ_ERR_NONFINITE;
+    }
+    finish(s, r, status, status < 0 ? NAN : q);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->wide_count--;
+  }
+  for (auto& kv : probs)
+    if (kv.second) mq_problem_destroy(kv.second);
+  if (st) (void)hipStreamDestroy(st);
 }
 
 // Admit queued requests in arrival order while they fit.
@@ -350,6 +487,16 @@ void admit(mq_server* s) {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->queue.empty()) return;
       r = s->queue.front();
+    }
+    if (wide_eligible(s, r->rq.n_nodes)) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->wide_count < s->wide_queue + 1 && s->inflight < s->wide_load) {
+        s->queue.pop_front();
+        s->wq.push_back(r);
+        s->wide_count++;
+        s->wcv.notify_one();
+        continue;
+      }
     }
     if (s->inflight >= s->sd.max_inflight) return;
     auto it = s->classes.find(r->rq.n_nodes);
@@ -365,7 +512,7 @@ void admit(mq_server* s) {
         if (s->inflight > 0) return;  // wait for memory to free up
         rc = MQ_ERR_BUSY;
       } else {
-        rc = activate(c);
+        rc = activate(s, c);
         if (rc == MQ_OK) s->used_bytes += c.fixed_bytes;
       }
     }
@@ -482,7 +629,8 @@ int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out) {
   if (sd->base.path == MQ_PATH_WIDE)
     return fail(MQ_ERR_INVALID_ARG, "the server batches requests: resident or streaming path");
   if (sd->hbm_budget_bytes <= 0 || sd->max_inflight < 1 || sd->n_streams < 0 || sd->n_streams > 8 ||
-      sd->max_batch < 0 || sd->chunk_steps < 0)
+      sd->max_batch < 0 || sd->chunk_steps < 0 || sd->wide_min_nodes < -1 || sd->wide_queue < 0 ||
+      sd->wide_load_limit < 0)
     return fail(MQ_ERR_INVALID_ARG, "bad server limits");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MQ_ERR_NO_DEVICE, "no HIP device");
@@ -500,7 +648,15 @@ int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out) {
   s->chunk = sd->chunk_steps > 0 ? sd->chunk_steps : 32;
   s->lanes = sd->n_streams > 0 ? sd->n_streams : 2;
   s->max_batch = sd->max_batch > 0 ? sd->max_batch : 4096;
+  s->wide_min = sd->wide_min_nodes == 0 ? 513 : (sd->wide_min_nodes < 0 ? 0 : sd->wide_min_nodes);
+  s->wide_queue = sd->wide_queue > 0 ? sd->wide_queue : 8;
+  s->wide_mg = sd->base.precond != MQ_PRECOND_JACOBI;
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || n_cu < 2)
+    n_cu = 256;
+  s->wide_load = sd->wide_load_limit > 0 ? sd->wide_load_limit : n_cu / 2;
   s->th = std::thread(scheduler, s);
+  if (s->wide_min > 0) s->wth = std::thread(wide_worker, s);
   *out = s;
   return MQ_OK;
 }
@@ -552,8 +708,15 @@ int mq_server_pending(const mq_server* s, int32_t* n) {
 int mq_server_destroy(mq_server* s) {
   if (!s) return MQ_OK;
   s->stop.store(true);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);  // no wake-up is lost between the workers' test and wait
+  }
   s->cv.notify_all();
+  s->wcv.notify_all();
   if (s->th.joinable()) s->th.join();
+  if (s->wth.joinable()) s->wth.join();
+  for (Req* r : s->wq) delete r;
+  s->wq.clear();
   for (auto& kv : s->classes) {
     destroy_class(*kv.second);
     for (Req* r : kv.second->active) delete r;

@@ -38,16 +38,17 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
   int rc = ensure_work(p, 1);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(p->stream));
-  // a private stream: the problem's may be the legacy default stream, which
-  // cannot be captured
+  // the legacy default stream cannot be captured: a private stream then
+  // (every stream takes a share of the process's hardware queues, so an
+  // explicit stream is used as it is)
   struct OwnStream {
     hipStream_t s = nullptr;
     ~OwnStream() {
       if (s) (void)hipStreamDestroy(s);
     }
   } own;
-  HIP_TRY(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
-  const hipStream_t ws = own.s;
+  if (!p->stream) HIP_TRY(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+  const hipStream_t ws = p->stream ? p->stream : own.s;
   const size_t FS = (size_t)g.N * g.P, RHW = (size_t)g.RW * g.RH;
   const size_t vsz = p->d.precision == MQ_PREC_FP64 ? sizeof(double) : sizeof(float);
   WideCtx c{};
@@ -126,6 +127,7 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
                            ws));
     HIP_TRY(hipStreamSynchronize(ws));
     for (int step = 0; step < in.n_steps; ++step) {
+      if (p->wide_yield) p->wide_yield();
       HIP_TRY(wide_rhs(c, src[step], ws));
       bool conv = false;
       for (int sweep = 0; sweep <= c.sv.max_sweeps; ++sweep) {

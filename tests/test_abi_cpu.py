@@ -57,6 +57,7 @@ def test_struct_layout_matches_c(tmp_path):
     lines.append('printf("off_t_done %zu\\n", offsetof(mq_result, t_done_ns));')
     lines.append('printf("off_mg_sweeps %zu\\n", offsetof(mq_problem_desc, mg_coarse_sweeps));')
     lines.append('printf("off_busy %zu\\n", offsetof(mq_run_stats, busy_ms));')
+    lines.append('printf("off_wide_queue %zu\\n", offsetof(mq_server_desc, wide_queue));')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -69,6 +70,7 @@ def test_struct_layout_matches_c(tmp_path):
     assert int(out["off_t_done"]) == _lib.Result.t_done_ns.offset
     assert int(out["off_mg_sweeps"]) == _lib.ProblemDesc.mg_coarse_sweeps.offset
     assert int(out["off_busy"]) == _lib.RunStats.busy_ms.offset
+    assert int(out["off_wide_queue"]) == _lib.ServerDesc.wide_queue.offset
 
 
 def test_no_device_and_invalid_arguments(lib):

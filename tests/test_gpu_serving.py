@@ -150,3 +150,37 @@ def test_server_max_inflight_one_serialises():
     for r, t in zip(reqs, tickets):
         q = level_q(mq, L, r.n_nodes, r.steps_per_period, r.n_periods, [r.xi])
         assert res[t].status == 0 and res[t].q == q[0]
+
+
+def test_server_wide_lane():
+    """Large requests on the wide lane: with wide_min_nodes = 65 and a queue
+    of one, a burst of 65 x 65 requests runs partly on the wide lane and the
+    rest batched; every result equals mlmc_level_run of its input on the path
+    that ran it, bit for bit, and the oracle within 1e-6.  33 x 33 requests in
+    the same burst are batched as usual."""
+    mq, L = mqmod()
+    reqs = W.serving_stream(10, rate_hz=1e6, meshes=(33, 65), weights=(0.3, 0.7), steps=(16, 24))
+    srv = mq.Server(kl_problem(33), L.MQ_PREC_MIXED, BUDGET, chunk_steps=16, wide_min_nodes=65, wide_queue=1)
+    tickets = [srv.submit(r.n_nodes, r.steps_per_period, r.n_periods, r.xi, user_id=r.rid) for r in reqs]
+    res = drain(srv, len(reqs))
+    srv.close()
+    n_wide = 0
+    for i, r in enumerate(reqs):
+        got = res[tickets[i]]
+        assert got.status == 0 and got.user_id == r.rid
+        qb = level_q(mq, L, r.n_nodes, r.steps_per_period, r.n_periods, [r.xi])[0]
+        if r.n_nodes == 65:
+            pw = mq.Problem(kl_problem(65), L.MQ_PREC_MIXED, path=L.MQ_PATH_WIDE)
+            qw = float(mq.mlmc_level_run(pw, r.steps_per_period, 0, r.n_periods, np.asarray([r.xi]))[0][0])
+            pw.close()
+            assert got.q in (qw, qb), (i, got.q, qw, qb)
+            n_wide += got.q == qw and qw != qb
+        else:
+            assert got.q == qb
+        prob = kl_problem(r.n_nodes)
+        m = omesh.build(r.n_nodes)
+        ref = ots.solve_sample(prob, np.array(r.xi), r.steps_per_period, r.n_periods, m=m,
+                               kl_table=ots.kl_table_for(prob, m))[0]
+        assert abs(got.q - ref) / abs(ref) <= 1e-6
+    say("65 x 65 requests on the wide lane:", n_wide, "of", sum(r.n_nodes == 65 for r in reqs))
+    assert n_wide >= 1
