@@ -357,6 +357,76 @@ def bench_adaptive(args, mq, L, W, np, torch):
     return res
 
 
+def bench_combined(args, mq, L, W, np, torch):
+    """MLMC with Parareal on the finest level (Section II-D) on the three-level
+    129x129 model: the plain MLMC estimate as reference, then the combined run
+    (levels 0-1 batched, level 2 by Parareal with the level-0 time grid as coarse
+    propagator, at once); measured times and effort against Eqs. (15)-(25) with
+    C_l = one sample of level l alone."""
+    from paper_2507_19246_amd import autotune
+    w = W.mlmc3_mixed_129()
+    levels = [(lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods) for lv in w.levels]
+    xis = [torch.tensor(W.level_xi(w, l), dtype=torch.float64, device="cuda") for l in range(3)]
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
+    Lf = len(levels) - 1
+    useful = sum(x.shape[0] * lv[2] * (lv[0] + lv[1]) for x, lv in zip(xis, levels))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    # warm-up of both paths (the combined run sets up its second handle here)
+    mq.mlmc_multilevel_run(prob, levels, xis)
+    mq.mlmc_combined_run(prob, levels, xis, tol=args.para_tol)
+    (ref, t_ref) = timed(lambda: mq.mlmc_multilevel_run(prob, levels, xis))
+    (comb, t_comb) = timed(lambda: mq.mlmc_combined_run(prob, levels, xis, tol=args.para_tol))
+    qf, qc, it, rc, st, cs = comb
+    e_ref = float(mq.mlmc_estimate(ref[0], ref[1])[0])
+    e_comb = float(mq.mlmc_estimate(qf, qc)[0])
+    # C_l: one sample of level l alone (fine run), and the level-L serial fine runs batched
+    C_ms = []
+    for l, (spp, _, nper) in enumerate(levels):
+        _, t = timed(lambda: mq.mlmc_level_run(prob, spp, 0, nper, xis[l][:1]))
+        C_ms.append(1e3 * t)
+    _, t_serial_L = timed(lambda: mq.mlmc_level_run(prob, levels[Lf][0], 0, levels[Lf][2], xis[Lf]))
+    M, kmax = cs["n_slices"], cs["max_k"]
+    N = [x.shape[0] for x in xis]
+    model = mq.cost_model(C_ms, N, kmax, M, cs["n_cores"])
+    steps = [lv[0] * lv[2] for lv in levels]
+    model_steps = mq.cost_model(steps, N, kmax, M, cs["n_cores"])
+    Kv = it.cpu().numpy()
+    pred_effort = sum(mq.cost_model(steps, N, int(k), M, cs["n_cores"])["effort_para"] for k in Kv)
+    args.steps, args.warmup = 1, 1
+    res = _contract("sample-steps/s", useful / t_comb, t_comb, args, {
+        "workload": "combined-mlmc3-mixed-129x129-kl8-512/128/32-parareal-level2",
+        "mesh": "129x129", "levels_steps_per_period": [lv[0] for lv in levels], "n_periods": levels[0][2],
+        "n_slices": M, "coarse_propagator_steps_per_period": cs["coarse_steps_per_period"],
+        "parareal_tol": args.para_tol, "knobs": dict(knobs, precond=prob.info.precond)})
+    res.update({
+        "status": rc, "reference_mlmc_sample_steps_per_s": useful / t_ref,
+        "measured": {"t_ref_ms": 1e3 * t_ref, "t_comb_ms": 1e3 * t_comb, "speedup": t_ref / t_comb,
+                     "ms_levels": cs["ms_levels"], "ms_parareal": cs["ms_parareal"],
+                     "level_L_serial_fine_ms": 1e3 * t_serial_L,
+                     "level_L_parareal_speedup": 1e3 * t_serial_L / cs["ms_parareal"],
+                     "K_mean": cs["mean_k"], "K_max": kmax, "n_c_para_eq25": cs["n_c_para"],
+                     "n_cores_slots": cs["n_cores"], "level_slots": cs["level_slots"],
+                     "parareal_effort_steps_per_sample": (cs["para_fine_steps"] + cs["para_coarse_steps"]) / N[Lf],
+                     "estimate": e_comb, "estimate_reference": e_ref,
+                     "estimate_rel_diff": abs(e_comb - e_ref) / abs(e_ref)},
+        "predicted": {"C_ms_one_sample": C_ms, "tau_para_ms_eq15": model["tau_para"],
+                      "level_L_parareal_speedup": C_ms[Lf] / model["tau_para"],
+                      "speedup_unlimited_eq17_18": model["speedup"], "s_inf_eq21": model["s_inf"],
+                      "kappa_eq22": model_steps["kappa"], "eps_inf_eq23": model["eps_inf"],
+                      "batches_eq24": model["batches"], "speedup_n_cores": model["s_nc"],
+                      "parareal_effort_steps_per_sample_eq16": pred_effort / N[Lf]},
+        "sample_steps_executed": st["sample_steps"], "roofline": None, "cpu_baseline": None})
+    prob.close()
+    return res
+
+
 def _serve(mq, L, W, np, torch, reqs, limit_s, label, wide_min_nodes=0, wide_load_limit=0):
     """Submit `reqs` at their arrival times into a fresh server; wait for all results."""
     base = W.Problem(65, W.Material(kind=W.MAT_KL))
@@ -436,7 +506,9 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
-    ap.add_argument("--workload", default="mlmc3", choices=["mlmc3", "parareal", "nonlinear", "serving", "adaptive"])
+    ap.add_argument("--workload", default="mlmc3",
+                    choices=["mlmc3", "parareal", "nonlinear", "serving", "adaptive", "combined"])
+    ap.add_argument("--para-tol", type=float, default=1e-8, help="combined: Parareal jump tolerance")
     ap.add_argument("--target-rmse", type=float, default=50.0, help="adaptive: target RMSE of the estimate (W/m)")
     ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
@@ -485,7 +557,7 @@ def main():
         return
     if args.workload != "mlmc3":
         fn = {"parareal": bench_parareal, "nonlinear": bench_nonlinear, "serving": bench_serving,
-              "adaptive": bench_adaptive}[args.workload]
+              "adaptive": bench_adaptive, "combined": bench_combined}[args.workload]
         print(json.dumps(fn(args, mq, L, W, np, torch)), flush=True)
         return
     w = W.mlmc3_mixed_129()

@@ -253,6 +253,70 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
 int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
                  double* q, int32_t* iters, double* final_state, mq_run_stats* st);
 
+/* MLMC with Parareal on the finest level (Section II-D): levels 0..L-1 and
+ * the coupled coarse runs of level L are batched as in mlmc_multilevel_run,
+ * while the fine values of level L come from Parareal (as parareal_run) with
+ * the level L-2 discretisation as coarse propagator, both at once on the
+ * device (the Parareal part runs on a second set-up of the same problem with
+ * a stream of its own, created on the first call and kept with p; the batched
+ * part's launch leaves N_L * M persistent slots to it, at most half).
+ * n_slices = 0 picks M from Eq. (25) with the device's persistent slots as
+ * cores: the largest power of two <= max(2, n_c,para) that divides the fine
+ * and coarse step counts of level L (a given M must divide both).  q_coarse[L] is bitwise what
+ * mlmc_level_run gives for level L; q_fine[L] is the Parareal value and
+ * para_iters[N_L] (device) its iteration count K per sample.
+ * Errors: fewer than 2 levels, nonlinear material, wide path, invalid slices. */
+typedef struct mq_combined_desc {
+  int32_t n_slices;                 /* M (0: from Eq. (25), see above) */
+  int32_t coarse_steps_per_period;  /* coarse propagator (0: level L-2's steps per period) */
+  int32_t k_max;                    /* 0: M */
+  int32_t reserved;
+  double tol;                       /* largest relative interface jump to stop at */
+} mq_combined_desc;
+
+typedef struct mq_combined_stats {
+  int32_t n_slices, coarse_steps_per_period, n_cores, n_c_para;
+  double ms_levels;    /* wall time of the batched part */
+  double ms_parareal;  /* wall time of level L's Parareal */
+  double ms_total;
+  int64_t para_fine_steps, para_coarse_steps;  /* sample-steps Parareal executed (all samples) */
+  double mean_k;
+  int32_t max_k;
+  int32_t level_slots;  /* persistent slots of the batched part: the device's n_cores less
+                           N_L * M (at most half) kept for the Parareal part */
+} mq_combined_stats;
+
+int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_samples,
+                      const double* const* xi, const mq_combined_desc* cd, double* const* q_fine,
+                      double* const* q_coarse, int32_t* para_iters, mq_run_stats* st, mq_combined_stats* cs);
+
+/* Cost model of the combined method (Section II-C Eqs. (13)-(16), Section
+ * II-D Eqs. (17)-(25)), host arithmetic only.  C_l: sequential cost of one
+ * sample of level l (any unit), N_l: samples; K, M: Parareal iterations and
+ * slices on level L with tau_F = C_L and tau_C = C_{L-2}; n_cores: n_c of
+ * Eqs. (24)-(25).  Errors: n_levels outside [3, 16], K outside [1, M],
+ * C_l <= 0, N_l < 1. */
+typedef struct mq_cost_in {
+  int32_t n_levels, K, M, n_cores;
+  double C[16], N[16];
+} mq_cost_in;
+
+typedef struct mq_cost_out {
+  double tau_para, effort_para;  /* Eqs. (15), (16) */
+  double tau_ref, effort_ref;    /* Eq. (17) */
+  double tau_comb, effort_comb;  /* Eqs. (18), (19) */
+  double speedup;                /* tau_ref / tau_comb */
+  double s_inf;                  /* Eq. (21): sum_l C_l / (sum_{l<L} C_l + C_{L-1}) */
+  double eps_inf;                /* Eq. (23): effort_comb / effort_ref */
+  double r;                      /* C_L / C_{L-1} */
+  int32_t kappa;                 /* Eq. (22) with n = M */
+  int32_t n_c_para;              /* Eq. (25) */
+  int32_t batches[16];           /* Eq. (24) */
+  double s_nc;                   /* speedup on n_cores cores (0 when n_c_para < 1) */
+} mq_cost_out;
+
+int mq_cost_model(const mq_cost_in* in, mq_cost_out* out);
+
 /* Eq. (9) in FP64 on the device with a fixed summation order.
  * n_per_level: host [n_levels]; q_fine, q_coarse: host arrays of device
  * pointers (q_coarse[0] ignored, Q_{-1} = 0).  out: device [1 + 2 n_levels] =

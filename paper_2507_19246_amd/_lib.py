@@ -107,6 +107,33 @@ class Result(C.Structure):
                 ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64)]
 
 
+class CombinedDesc(C.Structure):
+    _fields_ = [("n_slices", C.c_int32), ("coarse_steps_per_period", C.c_int32), ("k_max", C.c_int32),
+                ("reserved", C.c_int32), ("tol", C.c_double)]
+
+
+class CombinedStats(C.Structure):
+    _fields_ = [("n_slices", C.c_int32), ("coarse_steps_per_period", C.c_int32), ("n_cores", C.c_int32),
+                ("n_c_para", C.c_int32), ("ms_levels", C.c_double), ("ms_parareal", C.c_double),
+                ("ms_total", C.c_double), ("para_fine_steps", C.c_int64), ("para_coarse_steps", C.c_int64),
+                ("mean_k", C.c_double), ("max_k", C.c_int32), ("level_slots", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class CostIn(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("K", C.c_int32), ("M", C.c_int32), ("n_cores", C.c_int32),
+                ("C", C.c_double * 16), ("N", C.c_double * 16)]
+
+
+class CostOut(C.Structure):
+    _fields_ = [("tau_para", C.c_double), ("effort_para", C.c_double), ("tau_ref", C.c_double),
+                ("effort_ref", C.c_double), ("tau_comb", C.c_double), ("effort_comb", C.c_double),
+                ("speedup", C.c_double), ("s_inf", C.c_double), ("eps_inf", C.c_double), ("r", C.c_double),
+                ("kappa", C.c_int32), ("n_c_para", C.c_int32), ("batches", C.c_int32 * 16), ("s_nc", C.c_double)]
+
+
 VP = C.c_void_p
 PD = C.POINTER(C.c_double)
 
@@ -127,6 +154,10 @@ SIGNATURES = {
     "mlmc_adaptive_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32), C.POINTER(VP),
                                     C.POINTER(VP), C.POINTER(VP), C.POINTER(AdaptiveDesc), C.POINTER(C.c_int32),
                                     PD, C.POINTER(RunStats)]),
+    "mlmc_combined_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32), C.POINTER(VP),
+                                    C.POINTER(CombinedDesc), C.POINTER(VP), C.POINTER(VP), VP, C.POINTER(RunStats),
+                                    C.POINTER(CombinedStats)]),
+    "mq_cost_model": (C.c_int, [C.POINTER(CostIn), C.POINTER(CostOut)]),
     "mlmc_estimate": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(VP), C.POINTER(VP), VP, VP]),
     "mq_debug_apply": (C.c_int, [VP, C.c_int32, C.c_double, C.c_int32, VP, VP, VP]),
     "mq_server_create": (C.c_int, [C.POINTER(ServerDesc), VP, C.POINTER(VP)]),

@@ -179,6 +179,43 @@ def mlmc_adaptive_run(prob: Problem, levels: Sequence, xi_pools: Sequence, targe
             [q[:k] if l > 0 else None for l, (q, k) in enumerate(zip(qcs, n))], rc, st.as_dict())
 
 
+def mlmc_combined_run(prob: Problem, levels: Sequence, xis: Sequence, n_slices: int = 0,
+                      coarse_steps_per_period: int = 0, k_max: int = 0, tol: float = 1e-8):
+    """MLMC with Parareal on the finest level (mlmc_combined_run).  Returns (list of
+    q_fine, list of q_coarse (None at level 0), Parareal K per finest-level sample,
+    status, run stats, combined-run stats)."""
+    nl = len(levels)
+    lvs = (L.LevelDesc * nl)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    xs = [_dev_f64(x).reshape(-1, prob.n_xi).contiguous() for x in xis]
+    ns = (C.c_int32 * nl)(*[x.shape[0] for x in xs])
+    qfs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") for x in xs]
+    qcs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") if l > 0 else None
+           for l, x in enumerate(xs)]
+    it = torch.zeros(xs[-1].shape[0], dtype=torch.int32, device="cuda")
+    px = (C.c_void_p * nl)(*[x.data_ptr() for x in xs])
+    pf = (C.c_void_p * nl)(*[q.data_ptr() for q in qfs])
+    pc = (C.c_void_p * nl)(*[(q.data_ptr() if q is not None else None) for q in qcs])
+    cd = L.CombinedDesc(n_slices, coarse_steps_per_period, k_max, 0, tol)
+    st, cs = L.RunStats(), L.CombinedStats()
+    rc = L.check(prob.lib.mlmc_combined_run(prob.h, nl, lvs, ns, px, C.byref(cd), pf, pc, _ptr(it),
+                                            C.byref(st), C.byref(cs)))
+    return qfs, qcs, it, rc, st.as_dict(), cs.as_dict()
+
+
+def cost_model(C_l: Sequence[float], N_l: Sequence[float], K: int, M: int, n_cores: int) -> dict:
+    """The combined method's cost model (mq_cost_model): Eqs. (15)-(19), (21)-(25)."""
+    lib = L.load()
+    ci = L.CostIn()
+    ci.n_levels, ci.K, ci.M, ci.n_cores = len(C_l), K, M, n_cores
+    for i, (c, n) in enumerate(zip(C_l, N_l)):
+        ci.C[i], ci.N[i] = float(c), float(n)
+    co = L.CostOut()
+    L.check(lib.mq_cost_model(C.byref(ci), C.byref(co)))
+    out = {f: getattr(co, f) for f, _ in co._fields_ if f != "batches"}
+    out["batches"] = list(co.batches[:len(C_l)])
+    return out
+
+
 def parareal_run(prob: Problem, n_periods: int, n_slices: int, fine_steps_per_slice: int,
                  coarse_steps_per_slice: int, k_max: int, tol: float, xi, fixed_k: int = 0,
                  want_state: bool = False):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmq.so")
 ARCH = os.environ.get("MQ_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip"]
-HOST_SOURCES = ["abi.cpp", "setup.cpp", "serve.cpp", "wide.cpp"]
+HOST_SOURCES = ["abi.cpp", "setup.cpp", "serve.cpp", "wide.cpp", "costmodel.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-mcode-object-version=5",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -77,7 +77,8 @@ size_t max_slots(const mq_problem* p) {
 }
 
 int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block) {
-  const size_t slots = std::min<size_t>((size_t)n, max_slots(p));
+  size_t slots = std::min<size_t>((size_t)n, max_slots(p));
+  if (p->grid_cap > 0) slots = std::min<size_t>(slots, (size_t)p->grid_cap);
   if (p->work_slots < slots) return fail(MQ_ERR_INVALID_ARG, "work buffer smaller than the launch");
   HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
   const Solver sv = solver_of(p);
@@ -164,12 +165,12 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     ro->status = std::max(ro->status, status);
     return MQ_OK;
   }
-  DevPtr<int> dstat;
-  HIP_TRY(dev_alloc(dstat, (size_t)n * STAT_N));
+  TmpPtr<int> dstat;
+  HIP_TRY(tmp_alloc(dstat, (size_t)n * STAT_N, p->stream));
   HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)n * STAT_N, p->stream));
   for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + STAT_N * i;
-  DevPtr<Inst> dinst;
-  HIP_TRY(dev_alloc(dinst, n));
+  TmpPtr<Inst> dinst;
+  HIP_TRY(tmp_alloc(dinst, n, p->stream));
   HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
   const size_t slots = std::min<size_t>((size_t)n, max_slots(p));
   int rc = ensure_work(p, slots);
@@ -249,16 +250,16 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   return MQ_OK;
 }
 
-int assemble(mq_problem* p, const double* xi, int n, DevPtr<double>& tables) {
+int assemble(mq_problem* p, const double* xi, int n, TmpPtr<double>& tables) {
   const Geom& g = p->hm.g;
-  HIP_TRY(dev_alloc(tables, (size_t)n * tab_stride(g)));
+  HIP_TRY(tmp_alloc(tables, (size_t)n * tab_stride(g), p->stream));
   HIP_TRY(launch_assemble(g, p->hm.cr, p->dcond.get(), p->dkl.get(), p->hm.n_modes, p->d.material, xi,
                           p->n_xi, n, p->mat, tables.get(), p->stream));
   return MQ_OK;
 }
 
 struct LevelBufs {
-  DevPtr<double> tables, src_f, src_c, afull;
+  TmpPtr<double> tables, src_f, src_c, afull;
   std::vector<double*> afull_ptr;
 };
 
@@ -283,13 +284,13 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
   const double T = lv->n_periods / p->d.freq;
   const double dtf = 1.0 / (p->d.freq * lv->steps_per_period);
   auto sf = source_table(p->d, dtf, (int)nf);
-  HIP_TRY(dev_alloc(lb.src_f, sf.size()));
+  HIP_TRY(tmp_alloc(lb.src_f, sf.size(), p->stream));
   HIP_TRY(hipMemcpyAsync(lb.src_f.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   double dtc = 0;
   if (nc > 0) {
     dtc = 1.0 / (p->d.freq * lv->coarse_steps_per_period);
     auto sc = source_table(p->d, dtc, (int)nc);
-    HIP_TRY(dev_alloc(lb.src_c, sc.size()));
+    HIP_TRY(tmp_alloc(lb.src_c, sc.size(), p->stream));
     HIP_TRY(hipMemcpyAsync(lb.src_c.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
     // the copy's host vector must outlive the async copy
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -297,7 +298,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
   HIP_TRY(hipStreamSynchronize(p->stream));
   const size_t FS = (size_t)g.N * g.P;
   if (want_state) {
-    HIP_TRY(dev_alloc(lb.afull, FS * n));
+    HIP_TRY(tmp_alloc(lb.afull, FS * n, p->stream));
     lb.afull_ptr.resize(n);
     for (int s = 0; s < n; ++s) lb.afull_ptr[s] = lb.afull.get() + FS * s;
   }
@@ -414,6 +415,8 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
 
 int mq_problem_destroy(mq_problem* p) {
   if (!p) return MQ_OK;
+  if (p->twin) mq_problem_destroy(p->twin);
+  if (p->twin_stream) (void)hipStreamDestroy(p->twin_stream);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   delete p;
@@ -465,8 +468,8 @@ int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, co
   rc = run_instances(p, all, st, &ro, nullptr);
   if (rc) return rc;
   if (final_state) {
-    DevPtr<double*> dptr;
-    HIP_TRY(dev_alloc(dptr, lb.afull_ptr.size()));
+    TmpPtr<double*> dptr;
+    HIP_TRY(tmp_alloc(dptr, lb.afull_ptr.size(), p->stream));
     HIP_TRY(hipMemcpyAsync(dptr.get(), lb.afull_ptr.data(), lb.afull_ptr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(launch_to_interior(p->hm.g, n_samples, dptr.get(), final_state, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -533,8 +536,8 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     cost[l] = (double)lv[l].n_periods * (lv[l].steps_per_period + lv[l].coarse_steps_per_period);
   }
   if (st) std::memset(st, 0, sizeof(*st));
-  DevPtr<double> dout;
-  HIP_TRY(dev_alloc(dout, 1 + 2 * (size_t)L));
+  TmpPtr<double> dout;
+  HIP_TRY(tmp_alloc(dout, 1 + 2 * (size_t)L, p->stream));
   std::vector<double> host(1 + 2 * (size_t)L);
   int status = MQ_OK;
   for (int round = 1;; ++round) {
@@ -578,7 +581,7 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     // level means and variances of all samples so far (device, fixed order)
     const int rc = mlmc_estimate(L, have.data(), q_fine, q_coarse, dout.get(), p->stream);
     if (rc) return rc;
-    HIP_TRY(hipMemcpy(host.data(), dout.get(), host.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(host.data(), dout.get(), host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     // Eq. (11) at the current variance estimates
     double s = 0.0;
     for (int l = 0; l < L; ++l) s += std::sqrt(host[1 + L + l] * cost[l]);
@@ -713,25 +716,25 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
   if (rc) return rc;
   const Geom& g = p->hm.g;
   const size_t FS = (size_t)g.N * g.P;
-  DevPtr<double> tables;
+  TmpPtr<double> tables;
   rc = assemble(p, xi, n_samples, tables);
   if (rc) return rc;
   const double T = pd->n_periods / p->d.freq;
   const double dtf = T / ((double)M * fs), dtc = T / ((double)M * cs);
   auto sf = source_table(p->d, dtf, M * fs);
   auto sc = source_table(p->d, dtc, M * cs);
-  DevPtr<double> dsf, dsc;
-  HIP_TRY(dev_alloc(dsf, sf.size()));
-  HIP_TRY(dev_alloc(dsc, sc.size()));
-  HIP_TRY(hipMemcpy(dsf.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(dsc.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice));
+  TmpPtr<double> dsf, dsc;
+  HIP_TRY(tmp_alloc(dsf, sf.size(), p->stream));
+  HIP_TRY(tmp_alloc(dsc, sc.size(), p->stream));
+  HIP_TRY(copy_sync(dsf.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(copy_sync(dsc.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   // states: U_0..U_{M-1} (U_0 = 0), F_1..F_M, C_old_1..C_old_{M-1}, per sample
   const int S = n_samples;
   const size_t per = (size_t)(M + M + M) * FS;
-  DevPtr<double> states, qn;
-  HIP_TRY(dev_alloc(states, per * S));
+  TmpPtr<double> states, qn;
+  HIP_TRY(tmp_alloc(states, per * S, p->stream));
   HIP_TRY(launch_fill_zero(states.get(), per * S, p->stream));
-  HIP_TRY(dev_alloc(qn, (size_t)S * M));
+  HIP_TRY(tmp_alloc(qn, (size_t)S * M, p->stream));
   HIP_TRY(launch_fill_zero(qn.get(), (size_t)S * M, p->stream));
   auto U = [&](int s, int nn) { return states.get() + per * s + (size_t)nn * FS; };             // nn = 0..M-1
   auto F = [&](int s, int nn) { return states.get() + per * s + (size_t)(M + nn - 1) * FS; };   // nn = 1..M
@@ -755,9 +758,9 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
         arr[L + a * nseg + k] = initial ? nullptr : F(smp[a], nn);
         arr[2 * L + a * nseg + k] = C(smp[a], nn);
       }
-    DevPtr<double*> darr;
-    HIP_TRY(dev_alloc(darr, arr.size()));
-    HIP_TRY(hipMemcpy(darr.get(), arr.data(), arr.size() * sizeof(double*), hipMemcpyHostToDevice));
+    TmpPtr<double*> darr;
+    HIP_TRY(tmp_alloc(darr, arr.size(), p->stream));
+    HIP_TRY(copy_sync(darr.get(), arr.data(), arr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
     std::vector<Inst> insts;
     for (size_t a = 0; a < smp.size(); ++a) {
       Inst in{};
@@ -814,13 +817,13 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
           fp[k] = F(s, nn);
           up[k] = U(s, nn);
         }
-      DevPtr<const double*> dfp, dup;
-      DevPtr<double> dj;
-      HIP_TRY(dev_alloc(dfp, npair));
-      HIP_TRY(dev_alloc(dup, npair));
-      HIP_TRY(dev_alloc(dj, 2 * (size_t)npair));
-      HIP_TRY(hipMemcpy(dfp.get(), fp.data(), npair * sizeof(double*), hipMemcpyHostToDevice));
-      HIP_TRY(hipMemcpy(dup.get(), up.data(), npair * sizeof(double*), hipMemcpyHostToDevice));
+      TmpPtr<const double*> dfp, dup;
+      TmpPtr<double> dj;
+      HIP_TRY(tmp_alloc(dfp, npair, p->stream));
+      HIP_TRY(tmp_alloc(dup, npair, p->stream));
+      HIP_TRY(tmp_alloc(dj, 2 * (size_t)npair, p->stream));
+      HIP_TRY(copy_sync(dfp.get(), fp.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
+      HIP_TRY(copy_sync(dup.get(), up.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
       HIP_TRY(launch_jumps(g, npair, dfp.get(), dup.get(), dj.get(), p->stream));
       jump_host.assign(2 * (size_t)npair, 0.0);
       HIP_TRY(hipMemcpyAsync(jump_host.data(), dj.get(), jump_host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -853,21 +856,21 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
   }
   // Q = sum_n q_n / T in slice order (FP64, host)
   std::vector<double> qh((size_t)S * M);
-  HIP_TRY(hipMemcpy(qh.data(), qn.get(), qh.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(copy_sync(qh.data(), qn.get(), qh.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   std::vector<double> Q(S);
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
     for (int nn = 0; nn < M; ++nn) acc += qh[(size_t)s * M + nn];
     Q[s] = acc / T;
   }
-  HIP_TRY(hipMemcpy(q, Q.data(), S * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(iters, Kout.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(copy_sync(q, Q.data(), S * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(copy_sync(iters, Kout.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   if (final_state) {
     std::vector<const double*> fp(S);
     for (int s = 0; s < S; ++s) fp[s] = F(s, M);
-    DevPtr<const double*> dfp;
-    HIP_TRY(dev_alloc(dfp, S));
-    HIP_TRY(hipMemcpy(dfp.get(), fp.data(), S * sizeof(double*), hipMemcpyHostToDevice));
+    TmpPtr<const double*> dfp;
+    HIP_TRY(tmp_alloc(dfp, S, p->stream));
+    HIP_TRY(copy_sync(dfp.get(), fp.data(), S * sizeof(double*), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(launch_to_interior(g, S, dfp.get(), final_state, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
@@ -877,6 +880,162 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
     return MQ_WARN_NOT_CONVERGED;
   }
   return ro.status;
+}
+
+int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_samples,
+                      const double* const* xi, const mq_combined_desc* cd, double* const* q_fine,
+                      double* const* q_coarse, int32_t* para_iters, mq_run_stats* st, mq_combined_stats* cs) {
+  if (!p || !lv || !n_samples || !xi || !cd || !q_fine || !q_coarse || !para_iters)
+    return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (n_levels < 2 || n_levels > 16) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [2, 16]");
+  if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "the combined run uses the resident or streaming path");
+  if (p->d.material == MQ_MAT_NONLINEAR) return fail(MQ_ERR_INVALID_ARG, "the combined run takes linear materials");
+  const int L = n_levels - 1;
+  for (int l = 0; l <= L; ++l) {
+    if (n_samples[l] < 1 || !xi[l] || !q_fine[l] || (l > 0 && !q_coarse[l]))
+      return fail(MQ_ERR_INVALID_ARG, "every level needs samples, xi and outputs");
+    if (lv[l].steps_per_period < 1 || lv[l].n_periods < 1 || (l > 0 && lv[l].coarse_steps_per_period < 1))
+      return fail(MQ_ERR_INVALID_ARG, "invalid level description");
+  }
+  const int nper = lv[L].n_periods;
+  int cspp = cd->coarse_steps_per_period;
+  if (cspp == 0) {
+    if (L < 2) return fail(MQ_ERR_INVALID_ARG, "coarse_steps_per_period is required with fewer than 3 levels");
+    cspp = lv[L - 2].steps_per_period;
+  }
+  if (cspp < 1 || cd->n_slices < 0 || cd->k_max < 0 || !(cd->tol >= 0))
+    return fail(MQ_ERR_INVALID_ARG, "invalid combined-run description");
+  // Eq. (25) with the device's persistent slots as cores
+  const int n_c = (int)max_slots(p);
+  const double CL = (double)lv[L].steps_per_period * nper;
+  const double CL1 = (double)lv[L - 1].steps_per_period * lv[L - 1].n_periods;
+  const int n_c_para = (int)std::floor(n_c / (n_samples[L] * (1.0 + CL1 / CL)));
+  const int64_t fine_total = (int64_t)lv[L].steps_per_period * nper, coarse_total = (int64_t)cspp * nper;
+  int M = cd->n_slices;
+  if (M == 0)
+    for (int m = 2; m <= std::max(2, n_c_para); m *= 2)
+      if (fine_total % m == 0 && coarse_total % m == 0) M = m;
+  if (M < 2 || fine_total % M || coarse_total % M)
+    return fail(MQ_ERR_INVALID_ARG, "the slices (>= 2) must divide the fine and coarse step counts of level L");
+  const int kmax = cd->k_max > 0 ? cd->k_max : M;
+  if (!p->twin) {
+    hipStream_t ts = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking));
+    mq_problem* tw = nullptr;
+    const int rc = fem_setup(&p->d, (void*)ts, &tw);
+    if (rc) {
+      (void)hipStreamDestroy(ts);
+      return rc;
+    }
+    p->twin = tw;
+    p->twin_stream = ts;
+  }
+  const double t0 = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  // batched part: levels 0..L-1 and the coupled coarse runs of level L
+  std::vector<LevelBufs> lbs(n_levels);
+  std::vector<std::pair<int64_t, Inst>> keyed;
+  int group0 = 0;
+  for (int l = 0; l <= L; ++l) {
+    std::vector<Inst> f, c;
+    int rc;
+    if (l < L) {
+      rc = prepare_level(p, &lv[l], n_samples[l], xi[l], q_fine[l], q_coarse[l], false, lbs[l], f, c, group0);
+    } else {
+      const mq_level_desc lc{lv[L].coarse_steps_per_period, 0, nper, 0};
+      rc = prepare_level(p, &lc, n_samples[L], xi[L], q_coarse[L], nullptr, false, lbs[L], f, c, group0);
+    }
+    if (rc) return rc;
+    group0 += n_samples[l];
+    for (auto& i : f) keyed.push_back({i.n_steps, i});
+    for (auto& i : c) keyed.push_back({i.n_steps, i});
+  }
+  std::stable_sort(keyed.begin(), keyed.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<Inst> all;
+  for (auto& k : keyed) all.push_back(k.second);
+  // size both work buffers before the two parts overlap (growing one frees memory)
+  int rc = ensure_work(p, std::min(all.size(), max_slots(p)));
+  if (rc) return rc;
+  rc = ensure_work(p->twin, std::min<size_t>((size_t)n_samples[L] * M, max_slots(p->twin)));
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(p->twin_stream));
+  // Eq. (25) on the device: the batched part leaves N_L * M slots (at most half
+  // of them) to the Parareal part, so both run at once
+  const int level_slots = n_c - std::min(n_samples[L] * M, n_c / 2);
+  struct CapGuard {
+    mq_problem* p;
+    ~CapGuard() { p->grid_cap = 0; }
+  } cap_guard{p};
+  p->grid_cap = level_slots;
+  mq_run_stats sa{}, sb{};
+  RunOut ro;
+  int rca = MQ_OK;
+  std::string erra;
+  double ms_a = 0;
+  std::thread ta([&] {
+    (void)hipSetDevice(p->device);
+    const double ta0 = now_ms();
+    rca = run_instances(p, all, &sa, &ro, nullptr);
+    if (rca < 0) erra = last_error();
+    ms_a = now_ms() - ta0;
+  });
+  const double tb0 = now_ms();
+  const mq_parareal_desc pd{nper, M, (int32_t)(fine_total / M), (int32_t)(coarse_total / M), kmax, 0, cd->tol};
+  const int rcb = parareal_run(p->twin, &pd, n_samples[L], xi[L], q_fine[L], para_iters, nullptr, &sb);
+  const std::string errb = rcb < 0 ? last_error() : std::string();
+  const double ms_b = now_ms() - tb0;
+  ta.join();
+  if (rca < 0) return fail(rca, erra);
+  if (rcb < 0) return fail(rcb, errb);
+  std::vector<int32_t> K(n_samples[L]);
+  HIP_TRY(copy_sync(K.data(), para_iters, K.size() * sizeof(int32_t), hipMemcpyDeviceToHost, p->twin_stream));
+  // executed work: fine slices j..M in iteration j; coarse chains over M - j slices
+  // before iteration j + 1 while the sample is still iterating (the first one is the
+  // initial prediction)
+  int64_t fsteps = 0, csteps = 0;
+  int kmx = 0;
+  double ksum = 0;
+  for (int32_t k : K) {
+    for (int j = 1; j <= k; ++j) {
+      fsteps += (int64_t)(M - j + 1) * (fine_total / M);
+      csteps += (int64_t)(M - j) * (coarse_total / M);
+    }
+    kmx = std::max(kmx, (int)k);
+    ksum += k;
+  }
+  if (st) {
+    for (const mq_run_stats* s : {&sa, &sb}) {
+      st->n_instances += s->n_instances;
+      st->sample_steps += s->sample_steps;
+      st->inner_iters += s->inner_iters;
+      st->sweeps += s->sweeps;
+      st->max_inner_per_step = std::max(st->max_inner_per_step, s->max_inner_per_step);
+      st->n_not_converged += s->n_not_converged;
+      st->n_failed += s->n_failed;
+      st->kernel_ms += s->kernel_ms;
+    }
+    st->path = sa.path;
+    st->grid = sa.grid;
+    st->block = sa.block;
+    st->total_ms = now_ms() - t0;
+  }
+  if (cs) {
+    std::memset(cs, 0, sizeof(*cs));
+    cs->n_slices = M;
+    cs->coarse_steps_per_period = cspp;
+    cs->n_cores = n_c;
+    cs->n_c_para = n_c_para;
+    cs->ms_levels = ms_a;
+    cs->ms_parareal = ms_b;
+    cs->ms_total = now_ms() - t0;
+    cs->para_fine_steps = fsteps;
+    cs->para_coarse_steps = csteps;
+    cs->mean_k = ksum / K.size();
+    cs->max_k = kmx;
+    cs->level_slots = level_slots;
+  }
+  if (rcb == MQ_WARN_NOT_CONVERGED) last_error() = errb.empty() ? "Parareal reached k_max above the tolerance" : errb;
+  return std::max(ro.status, rcb);
 }
 
 int mlmc_estimate(int32_t n_levels, const int32_t* n_per_level, const double* const* q_fine,
@@ -891,11 +1050,11 @@ int mlmc_estimate(int32_t n_levels, const int32_t* n_per_level, const double* co
   hipStream_t st = (hipStream_t)stream;
   std::vector<const double*> qc(n_levels, nullptr);
   for (int l = 1; l < n_levels; ++l) qc[l] = q_coarse[l];
-  DevPtr<int> dn;
-  DevPtr<const double*> dqf, dqc;
-  HIP_TRY(dev_alloc(dn, n_levels));
-  HIP_TRY(dev_alloc(dqf, n_levels));
-  HIP_TRY(dev_alloc(dqc, n_levels));
+  TmpPtr<int> dn;
+  TmpPtr<const double*> dqf, dqc;
+  HIP_TRY(tmp_alloc(dn, n_levels, st));
+  HIP_TRY(tmp_alloc(dqf, n_levels, st));
+  HIP_TRY(tmp_alloc(dqc, n_levels, st));
   HIP_TRY(hipMemcpyAsync(dn.get(), n_per_level, n_levels * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dqf.get(), q_fine, n_levels * sizeof(double*), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dqc.get(), qc.data(), n_levels * sizeof(double*), hipMemcpyHostToDevice, st));
@@ -910,7 +1069,7 @@ int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const dou
   if (which < 0 || which > 2 || n < 1 || !(dt > 0)) return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
   int rc = check_finite(p, xi, (size_t)n * p->n_xi);
   if (rc) return rc;
-  DevPtr<double> tables;
+  TmpPtr<double> tables;
   rc = assemble(p, xi, n, tables);
   if (rc) return rc;
   HIP_TRY(launch_apply(p->hm.g, which, dt, tables.get(), n, x, y, p->stream));

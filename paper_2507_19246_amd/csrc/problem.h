@@ -46,6 +46,33 @@ hipError_t dev_alloc(DevPtr<T>& out, size_t count) {
   return e;
 }
 
+// Per-call device buffer, allocated and freed in the order of one stream
+// (hipMallocAsync / hipFreeAsync): unlike hipFree, releasing it does not wait
+// for the work of other streams, so calls on different streams overlap.
+struct StreamFree {
+  hipStream_t s = nullptr;
+  void operator()(void* p) const {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+template <class T>
+using TmpPtr = std::unique_ptr<T, StreamFree>;
+
+template <class T>
+hipError_t tmp_alloc(TmpPtr<T>& out, size_t count, hipStream_t s) {
+  T* p = nullptr;
+  hipError_t e = hipMallocAsync((void**)&p, (count > 0 ? count : 1) * sizeof(T), s);
+  if (e == hipSuccess) out = TmpPtr<T>(p, StreamFree{s});
+  return e;
+}
+
+// Copy ordered on stream s, complete when it returns.
+inline hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
 }  // namespace mq
 
 struct mq_problem {
@@ -75,6 +102,12 @@ struct mq_problem {
   // wide path: called on the host between time steps (may block to let other
   // work have the device); empty: none
   std::function<void()> wide_yield;
+  // upper bound on the persistent grid (0: the device's slots); set while a
+  // combined run keeps slots free for its Parareal part
+  int grid_cap = 0;
+  // second set-up of the same problem on a stream of its own (combined runs)
+  mq_problem* twin = nullptr;
+  hipStream_t twin_stream = nullptr;
 };
 
 namespace mq {

@@ -88,10 +88,10 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
   c.w.mgreg = vec(6 * FS + 5 * RHW);
   c.w.ctab = vec(6 * FS + 5 * RHW + c.mg.region_elems);
   c.w.S = p->dS.get();
-  DevPtr<double> part;
-  DevPtr<WideScal> sc;
-  HIP_TRY(dev_alloc(part, 2 * (size_t)c.nblk));
-  HIP_TRY(dev_alloc(sc, 1));
+  TmpPtr<double> part;
+  TmpPtr<WideScal> sc;
+  HIP_TRY(tmp_alloc(part, 2 * (size_t)c.nblk, ws));
+  HIP_TRY(tmp_alloc(sc, 1, ws));
   c.w.part = part.get();
   c.w.sc = sc.get();
 

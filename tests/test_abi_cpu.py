@@ -30,6 +30,7 @@ def lib():
 def test_header_declares_the_boundary():
     fns = header_functions()
     for name in ["fem_setup", "mlmc_level_run", "parareal_run", "mlmc_estimate", "mlmc_adaptive_run", "mq_debug_apply",
+                 "mlmc_combined_run", "mq_cost_model",
                  "mq_server_create", "mq_submit", "mq_poll", "mq_server_destroy", "mq_last_error"]:
         assert name in fns
 
@@ -47,7 +48,9 @@ def test_struct_layout_matches_c(tmp_path):
     structs = {"mq_problem_desc": _lib.ProblemDesc, "mq_problem_info": _lib.ProblemInfo,
                "mq_run_stats": _lib.RunStats, "mq_level_desc": _lib.LevelDesc,
                "mq_parareal_desc": _lib.PararealDesc, "mq_server_desc": _lib.ServerDesc,
-               "mq_request": _lib.Request, "mq_result": _lib.Result, "mq_adaptive_desc": _lib.AdaptiveDesc}
+               "mq_request": _lib.Request, "mq_result": _lib.Result, "mq_adaptive_desc": _lib.AdaptiveDesc,
+               "mq_combined_desc": _lib.CombinedDesc, "mq_combined_stats": _lib.CombinedStats,
+               "mq_cost_in": _lib.CostIn, "mq_cost_out": _lib.CostOut}
     src = tmp_path / "sz.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void){']
     for cname in structs:
@@ -58,6 +61,8 @@ def test_struct_layout_matches_c(tmp_path):
     lines.append('printf("off_mg_sweeps %zu\\n", offsetof(mq_problem_desc, mg_coarse_sweeps));')
     lines.append('printf("off_busy %zu\\n", offsetof(mq_run_stats, busy_ms));')
     lines.append('printf("off_wide_queue %zu\\n", offsetof(mq_server_desc, wide_queue));')
+    lines.append('printf("off_s_nc %zu\\n", offsetof(mq_cost_out, s_nc));')
+    lines.append('printf("off_level_slots %zu\\n", offsetof(mq_combined_stats, level_slots));')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -71,6 +76,8 @@ def test_struct_layout_matches_c(tmp_path):
     assert int(out["off_mg_sweeps"]) == _lib.ProblemDesc.mg_coarse_sweeps.offset
     assert int(out["off_busy"]) == _lib.RunStats.busy_ms.offset
     assert int(out["off_wide_queue"]) == _lib.ServerDesc.wide_queue.offset
+    assert int(out["off_s_nc"]) == _lib.CostOut.s_nc.offset
+    assert int(out["off_level_slots"]) == _lib.CombinedStats.level_slots.offset
 
 
 def test_no_device_and_invalid_arguments(lib):

@@ -318,3 +318,53 @@ def test_multimesh_mlmc_matches_oracle():
     assert abs(float(e_gpu) - e_ref) <= 1e-6 * abs(e_ref)
     for h in hs:
         h.close()
+
+
+def test_combined_run_matches_oracle():
+    """MLMC with Parareal on the finest level (17 x 17, FP64, 3 levels, M = 4,
+    coarse propagator = level 0's time grid): levels 0-1 and level 2's coupled
+    coarse values as the oracle's level runs, level 2's fine values and K as the
+    oracle's Parareal, the executed Parareal work as the oracle's propagator
+    counts; level 2's coupled coarse values equal mlmc_level_run's bit for bit."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    levels = [(8, 0, 1), (16, 8, 1), (32, 16, 1)]
+    ns = (5, 4, 3)
+    xis = [W.normals(0, 25, l, range(n), 8) for l, n in enumerate(ns)]
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    say("combined 17 fp64")
+    qf, qc, it, rc, st, cs = mq.mlmc_combined_run(p, levels, xis, n_slices=4, tol=1e-6)
+    say("combined stats", cs)
+    assert rc == 0 and cs["n_slices"] == 4 and cs["coarse_steps_per_period"] == 8
+    for l in range(3):
+        spp, cspp, nper = levels[l]
+        rf, rcq = omlmc.level_run(prob, spp, cspp, nper, xis[l])
+        if l < 2:
+            assert np.max(np.abs(qf[l].cpu().numpy() - rf) / np.abs(rf)) <= 1e-10
+        if l > 0:
+            assert np.max(np.abs(qc[l].cpu().numpy() - rcq) / np.abs(rcq)) <= 1e-10
+    _, qc_lvl, _, _, _ = mq.mlmc_level_run(p, 32, 16, 1, xis[2])
+    assert np.array_equal(qc[2].cpu().numpy(), qc_lvl.cpu().numpy())
+    fine_ev = coarse_ev = 0
+    all_k_match = True
+    for s in range(ns[2]):
+        ref = opara.run(prob, xis[2][s], 1, 4, 8, 2, k_max=4, tol=1e-6)
+        k = int(it[s])
+        say("sample", s, "K", k, "oracle K", ref["K"])
+        assert abs(k - ref["K"]) <= 1
+        if k == ref["K"]:
+            assert float(qf[2][s]) == pytest.approx(ref["Q"], rel=1e-9)
+            fine_ev += ref["fine_evals"]
+            coarse_ev += ref["coarse_evals"]
+        else:
+            all_k_match = False
+    if all_k_match:
+        assert cs["para_fine_steps"] == 8 * fine_ev and cs["para_coarse_steps"] == 2 * coarse_ev
+    # M from Eq. (25): the largest power of two <= max(2, n_c,para) dividing both step counts
+    qf2, _, _, rc2, _, cs2 = mq.mlmc_combined_run(p, levels, xis, tol=1e-6)
+    m = cs2["n_slices"]
+    assert rc2 == 0 and m >= 2 and (m & (m - 1)) == 0 and 32 % m == 0 and 8 % m == 0
+    assert m <= max(2, cs2["n_c_para"]) and (2 * m > max(2, cs2["n_c_para"]) or 8 % (2 * m) != 0)
+    for l in range(2):
+        assert np.array_equal(qf2[l].cpu().numpy(), qf[l].cpu().numpy())
+    p.close()
