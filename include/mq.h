@@ -380,6 +380,7 @@ typedef struct mq_result {
   int32_t inner_iters;
   int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock ns: mq_submit, first launch,
                                                  QoI copied to the host */
+  char message[64];          /* status < 0: what failed (NUL-terminated, truncated) */
 } mq_result;
 
 typedef struct mq_server mq_server;

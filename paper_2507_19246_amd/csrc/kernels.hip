@@ -114,6 +114,7 @@ hipError_t launch_assemble(const Geom& g, const CellRegion& cr, const uint8_t* c
                            const double* kltab, int n_modes, int material, const double* xi,
                            int n_xi, int n_samples, const double* mat_params, double* tables,
                            hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   MatParams mp;
   mp.sigma0 = mat_params[0];
   mp.nu_cond = mat_params[1];
@@ -1372,6 +1373,7 @@ static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, 
                              int n_inst, int* counter, double* work, int max_grid, const double* S,
                              const uint8_t* cond, const CellRegion& cr,
                              int* grid_out, int* block_out, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   constexpr int NT = CW * NS;
   const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP}, MG ? &mg : nullptr);
   auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG, NL>;
@@ -1491,6 +1493,7 @@ __global__ void k_zero_i(int* p, size_t n) {
 }
 
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n == 0) return hipSuccess;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 4096) blocks = 4096;
@@ -1498,6 +1501,7 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n == 0) return hipSuccess;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 4096) blocks = 4096;
@@ -1507,6 +1511,7 @@ hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st) {
 
 hipError_t launch_apply(const Geom& g, int which, double dt, const double* tables, int n,
                         const double* x, double* y, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   // x: [n][nd] interior order; builds full-grid copies in y's scratch? Use a temporary.
   const size_t FS = (size_t)g.N * g.P;
   double* scratch = nullptr;
@@ -1534,6 +1539,7 @@ __global__ void k_gather_interior(Geom g, const double* const* full, double* out
 
 hipError_t launch_to_interior(const Geom& g, int n, const double* const* full, double* out,
                               hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   const int nd = g.n * g.n;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_interior, dim3((nd + 255) / 256, n), dim3(256), 0, st, g, full, out);
@@ -1550,6 +1556,7 @@ __global__ void k_scatter_interior(Geom g, const double* in, double* const* full
 }
 
 hipError_t launch_to_full(const Geom& g, int n, const double* in, double* const* full, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   const int nd = g.n * g.n;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_interior, dim3((nd + 255) / 256, n), dim3(256), 0, st, g, in, full);
@@ -1607,6 +1614,7 @@ __global__ void k_level_total(double* out, int n_levels) {
 
 hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double* const* qf,
                               const double* const* qc, double* out, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL(k_level_stats, dim3(n_levels), dim3(256), 0, st, n_per_level, qf, qc, out, n_levels);
   hipLaunchKernelGGL(k_level_total, dim3(1), dim3(64), 0, st, out, n_levels);
   return hipGetLastError();
@@ -1645,6 +1653,7 @@ __global__ void k_jumps(Geom g, const double* const* f, const double* const* u, 
 
 hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f, const double* const* u,
                         double* out2, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_jumps, dim3(n_pairs), dim3(256), 0, st, g, f, u, out2);
   return hipGetLastError();
@@ -1656,6 +1665,7 @@ __global__ void k_check_finite(const double* x, size_t n, int* bad) {
 }
 
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n == 0) return hipSuccess;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 1024) blocks = 1024;
@@ -2052,6 +2062,7 @@ size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
 template <int NT>
 static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                                   int* counter, double* work, int n_slots, int grid, const double* S, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
   const bool usemg = sv.precond == 1 && mg.nlev > 0;
   if (sv.precision == MQ_PREC_FP64) {
@@ -2467,23 +2478,27 @@ static int wide_cblocks(const MGGeom& mg, int l) {
 
 template <typename VT>
 static hipError_t wide_setup_t(const WideCtx& c, double inv_dt, const double* a_init, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL((k_w_setup<VT>), dim3(1), dim3(1024), 0, st, c.g, c.mg, c.sv, c.w, inv_dt, a_init);
   return hipGetLastError();
 }
 template <typename VT>
 static hipError_t wide_rhs_t(const WideCtx& c, double Jt, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL((k_w_rhs<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w, Jt);
   hipLaunchKernelGGL((k_w_reduce<WRED_RHS, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
   return hipGetLastError();
 }
 template <typename VT>
 static hipError_t wide_resid_t(const WideCtx& c, double inv_dt, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL((k_w_resid<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w, inv_dt);
   hipLaunchKernelGGL((k_w_reduce<WRED_RES, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
   return hipGetLastError();
 }
 template <typename VT>
 static hipError_t wide_iteration_t(const WideCtx& c, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   const VT om = (VT)c.sv.mg_omega, air = (VT)c.air;
   const dim3 gr = wide_grid(c), bl(WIDE_BX);
   hipLaunchKernelGGL((k_w_pre<VT>), gr, bl, 0, st, c.g, c.w, om);
@@ -2508,11 +2523,13 @@ static hipError_t wide_iteration_t(const WideCtx& c, hipStream_t st) {
 }
 template <typename VT>
 static hipError_t wide_xupd_t(const WideCtx& c, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL((k_w_xupd<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
   return hipGetLastError();
 }
 template <typename VT>
 static hipError_t wide_end_step_t(const WideCtx& c, double inv_dt, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL((k_w_qoi<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
   hipLaunchKernelGGL((k_w_reduce<WRED_QOI, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, inv_dt);
   hipLaunchKernelGGL((k_w_state<VT>), wide_grid(c), dim3(WIDE_BX), 0, st, c.g, c.w);
@@ -2531,6 +2548,7 @@ hipError_t wide_xupd(const WideCtx& c, hipStream_t st) { WIDE_DISPATCH(wide_xupd
 hipError_t wide_end_step(const WideCtx& c, double inv_dt, hipStream_t st) { WIDE_DISPATCH(wide_end_step_t, inv_dt, st); }
 #undef WIDE_DISPATCH
 hipError_t wide_finish(const WideCtx& c, double q_scale, double* q_out, double* a_out, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   hipLaunchKernelGGL(k_w_finish, dim3(256), dim3(256), 0, st, c.g, c.w, q_scale, q_out, a_out);
   return hipGetLastError();
 }

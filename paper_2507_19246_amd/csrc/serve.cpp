@@ -32,6 +32,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -164,8 +165,12 @@ struct mq_server {
 
 namespace {
 
-void finish(mq_server* s, Req* r, int status, double q) {
+void finish(mq_server* s, Req* r, int status, double q, const std::string& msg = std::string()) {
   mq_result res{};
+  if (status < 0) {
+    const std::string m = msg.empty() ? last_error() : msg;
+    std::snprintf(res.message, sizeof(res.message), "%s", m.c_str());
+  }
   res.ticket = r->ticket;
   res.user_id = r->rq.user_id;
   res.q = q;
@@ -285,6 +290,7 @@ int source_for(Class& c, Lane& L, const mq_problem_desc& d, int spp, int64_t n_t
 void retire(mq_server* s, Class& c, Lane& L, hipError_t q) {
   L.busy = false;
   const int rc = q == hipSuccess ? MQ_OK : MQ_ERR_DEVICE;
+  const std::string qmsg = q == hipSuccess ? std::string() : std::string("launch: ") + hipGetErrorString(q);
   const size_t n = L.running.size();
   std::vector<Req*> fin;
   std::vector<double> qh;
@@ -315,7 +321,8 @@ void retire(mq_server* s, Class& c, Lane& L, hipError_t q) {
     if (rc != MQ_OK) status = rc;
     else if (r->flags & FLAG_FAILED) status = MQ_ERR_NONFINITE;
     else if (r->flags & FLAG_NOT_CONVERGED) status = MQ_WARN_NOT_CONVERGED;
-    finish(s, r, status, status < 0 ? NAN : qh[i]);
+    finish(s, r, status, status < 0 ? NAN : qh[i],
+           rc != MQ_OK ? qmsg : (status == MQ_ERR_NONFINITE ? "the solve produced NaN or Inf" : ""));
   }
 }
 
@@ -440,6 +447,7 @@ void wide_worker(mq_server* s) {
     r->t_start = now_ns();
     int status = MQ_ERR_DEVICE;
     double q = NAN;
+    std::string msg = ok ? std::string() : std::string("wide lane set-up failed");
     if (ok) {
       mq_problem*& p = probs[r->rq.n_nodes];
       int rc = MQ_OK;
@@ -468,9 +476,13 @@ void wide_worker(mq_server* s) {
           rc = MQ_ERR_DEVICE;
       }
       status = rc;
-      if (status >= 0 && !std::isfinite(q)) status = MQ_ERR_NONFINITE;
+      if (status < 0) msg = std::string("wide lane: ") + last_error();
+      if (status >= 0 && !std::isfinite(q)) {
+        status = MQ_ERR_NONFINITE;
+        msg = "wide lane: the solve produced NaN or Inf";
+      }
     }
-    finish(s, r, status, status < 0 ? NAN : q);
+    finish(s, r, status, status < 0 ? NAN : q, msg);
     std::lock_guard<std::mutex> lk(s->mu);
     s->wide_count--;
   }
@@ -533,7 +545,7 @@ void admit(mq_server* s) {
           std::lock_guard<std::mutex> lk(s->mu);
           s->queue.pop_front();
         }
-        finish(s, r, MQ_ERR_BUSY, NAN);
+        finish(s, r, MQ_ERR_BUSY, NAN, "the request alone does not fit the memory budget");
         continue;
       }
       DevPtr<double> slab;
@@ -543,7 +555,7 @@ void admit(mq_server* s) {
           std::lock_guard<std::mutex> lk(s->mu);
           s->queue.pop_front();
         }
-        finish(s, r, MQ_ERR_OUT_OF_MEMORY, NAN);
+        finish(s, r, MQ_ERR_OUT_OF_MEMORY, NAN, "request slots: out of device memory");
         continue;
       }
       for (int k = SLAB - 1; k >= 0; --k) {

@@ -164,6 +164,9 @@ def test_server_wide_lane():
     tickets = [srv.submit(r.n_nodes, r.steps_per_period, r.n_periods, r.xi, user_id=r.rid) for r in reqs]
     res = drain(srv, len(reqs))
     srv.close()
+    for i, r in enumerate(reqs):
+        got = res[tickets[i]]
+        say("request", i, r.n_nodes, r.steps_per_period, "status", got.status, got.message.decode(errors="replace"))
     n_wide = 0
     for i, r in enumerate(reqs):
         got = res[tickets[i]]
