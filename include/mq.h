@@ -116,6 +116,12 @@ typedef struct mq_problem_desc {
   int32_t mg_levels; /* coarse levels in use (0: all, down to one node) */
   int32_t mg_coarse_sweeps; /* damped-Jacobi sweeps after Z = diag^{-1} R at the coarsest level
                                in use (0..64) */
+  int32_t split_steps;  /* resident path, linear material: when a launch holds more instances than
+                           the device has slots, short instances may run as dependent pieces of
+                           this many steps, queued after the long ones, where a simulation of the
+                           work queue says the launch ends sooner (results are bitwise those of
+                           the unsplit run).  0: 64; -1: never. */
+  int32_t reserved;
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;
@@ -142,7 +148,8 @@ typedef struct mq_run_stats {
   int64_t picard_iters;        /* Picard iterations summed (nonlinear) */
   int32_t max_inner_per_step;  /* largest inner-iteration count of any step */
   int32_t n_not_converged;     /* instances that hit a cap */
-  int32_t n_failed;            /* instances with a non-finite residual */
+  int32_t n_failed;            /* instances with a non-finite residual (or a piece that waited
+                                  for its predecessor past the time limit) */
   int32_t path;                /* MQ_PATH_RESIDENT or MQ_PATH_STREAMING */
   int32_t grid, block;         /* launch shape of the time-stepping kernel */
   double kernel_ms;            /* device time of the time-stepping launches */
@@ -154,6 +161,8 @@ typedef struct mq_run_stats {
                           reductions; right-hand side, refinement residuals, increment
                           updates, QoI + state update */
   double busy_ms;      /* sum over instances of their device time (start to end) */
+  int64_t n_pieces;    /* launch entries when instances ran as dependent pieces (split_steps),
+                          else 0 */
 } mq_run_stats;
 
 /* One MLMC level (Section II-B): every sample runs steps_per_period *

@@ -43,6 +43,7 @@ class ProblemDesc(C.Structure):
         ("max_iter", C.c_int32), ("max_sweeps", C.c_int32),
         ("precond", C.c_int32), ("tile", C.c_int32), ("mg_omega", C.c_double),
         ("mg_levels", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
+        ("split_steps", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -64,7 +65,7 @@ class RunStats(C.Structure):
         ("path", C.c_int32), ("grid", C.c_int32), ("block", C.c_int32),
         ("kernel_ms", C.c_double), ("total_ms", C.c_double),
         ("lat_p50_ms", C.c_double), ("lat_p99_ms", C.c_double), ("lat_max_ms", C.c_double),
-        ("phase_ms", C.c_double * 8), ("busy_ms", C.c_double),
+        ("phase_ms", C.c_double * 8), ("busy_ms", C.c_double), ("n_pieces", C.c_int64),
     ]
 
     def as_dict(self):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <queue>
 #include <string>
 #include <thread>
 #include <vector>
@@ -133,6 +134,7 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->tile < 0 || d->tile > 2) return fail(MQ_ERR_INVALID_ARG, "tile must be 0, 1 or 2");
   if (d->mg_levels < 0 || d->mg_coarse_sweeps < 0 || d->mg_coarse_sweeps > 64)
     return fail(MQ_ERR_INVALID_ARG, "mg_levels >= 0 and 0 <= mg_coarse_sweeps <= 64 required");
+  if (d->split_steps < -1) return fail(MQ_ERR_INVALID_ARG, "split_steps must be >= -1");
   return MQ_OK;
 }
 
@@ -153,6 +155,136 @@ struct RunOut {
 };
 
 // Launch one persistent time-stepping kernel over `insts` (host copy).
+// Makespan, in steps, of the greedy work queue over `slots` workgroups: each
+// item starts when a workgroup is free and its predecessor (dep >= 0) is done.
+double queue_makespan(const std::vector<std::pair<int, int>>& items, size_t slots) {
+  std::priority_queue<double, std::vector<double>, std::greater<double>> freeq;
+  for (size_t s = 0; s < slots; ++s) freeq.push(0.0);
+  std::vector<double> end(items.size());
+  double mk = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    double t = freeq.top();
+    freeq.pop();
+    if (items[i].second >= 0) t = std::max(t, end[items[i].second]);
+    end[i] = t + items[i].first;
+    mk = std::max(mk, end[i]);
+    freeq.push(end[i]);
+  }
+  return mk;
+}
+
+// Tail splitting (resident path, linear, plain instances, more instances than
+// slots): instances of at most a quarter (or half) of the longest one's steps
+// become chains of S-step pieces, queued after the other instances one round of
+// pieces at a time; the threshold whose simulated makespan is shortest (by more
+// than 2%, counting two steps per piece for its set-up) is used.  The pieces
+// carry the state through `buf` (per split instance: a, then the carry record)
+// and order themselves through `flags` (one per piece but the last).
+struct Split {
+  std::vector<Inst> pieces;
+  std::vector<int> orig;  // original instance of each entry
+  TmpPtr<double> buf;
+  TmpPtr<int> flags;
+};
+
+int plan_split(mq_problem* p, const std::vector<Inst>& insts, Split& out, bool* used) {
+  *used = false;
+  const size_t n = insts.size();
+  size_t slots = std::min(n, max_slots(p));
+  if (p->grid_cap > 0) slots = std::min(slots, (size_t)p->grid_cap);
+  const int S = p->d.split_steps == 0 ? 64 : p->d.split_steps;
+  if (p->d.split_steps < 0 || p->path != MQ_PATH_RESIDENT || p->d.material == MQ_MAT_NONLINEAR || n <= slots)
+    return MQ_OK;
+  int max_steps = 0;
+  for (const Inst& in : insts) {
+    if (in.n_chain > 0 || in.carry || in.dep_wait || in.dep_done) return MQ_OK;
+    max_steps = std::max(max_steps, in.n_steps);
+  }
+  constexpr int SETUP = 2;
+  std::vector<std::pair<int, int>> base;
+  for (const Inst& in : insts) base.push_back({in.n_steps, -1});
+  const double mk0 = queue_makespan(base, slots);
+  double best = mk0 * 0.98;
+  int best_th = 0;
+  for (int th : {max_steps / 4, max_steps / 2}) {
+    std::vector<std::pair<int, int>> q;
+    std::vector<size_t> sp;
+    for (size_t i = 0; i < n; ++i) {
+      if (insts[i].n_steps <= th && insts[i].n_steps >= 2 * S) sp.push_back(i);
+      else q.push_back({insts[i].n_steps, -1});
+    }
+    if (sp.empty()) continue;
+    std::vector<int> last(sp.size(), -1);
+    for (int k = 0;; ++k) {
+      bool any = false;
+      for (size_t a = 0; a < sp.size(); ++a) {
+        const int len = insts[sp[a]].n_steps - k * S;
+        if (len <= 0) continue;
+        any = true;
+        q.push_back({std::min(S, len) + SETUP, last[a]});
+        last[a] = (int)q.size() - 1;
+      }
+      if (!any) break;
+    }
+    const double mk = queue_makespan(q, slots);
+    if (mk < best) {
+      best = mk;
+      best_th = th;
+    }
+  }
+  if (best_th == 0) return MQ_OK;
+  // build the pieces
+  const Geom& g = p->hm.g;
+  const size_t FS = (size_t)g.N * g.P, per = 3 * FS + 1;
+  std::vector<size_t> sp;
+  for (size_t i = 0; i < n; ++i) {
+    if (insts[i].n_steps <= best_th && insts[i].n_steps >= 2 * S) sp.push_back(i);
+    else {
+      out.pieces.push_back(insts[i]);
+      out.orig.push_back((int)i);
+    }
+  }
+  if (per * sp.size() * sizeof(double) > ((size_t)8 << 30)) {  // keep the state buffers modest
+    out.pieces.clear();
+    out.orig.clear();
+    return MQ_OK;
+  }
+  size_t n_flags = 0;
+  for (size_t i : sp) n_flags += (insts[i].n_steps + S - 1) / S - 1;
+  HIP_TRY(tmp_alloc(out.buf, per * sp.size(), p->stream));
+  HIP_TRY(tmp_alloc(out.flags, n_flags, p->stream));
+  HIP_TRY(launch_fill_zero_i(out.flags.get(), n_flags, p->stream));
+  std::vector<int*> prev(sp.size(), nullptr);
+  size_t fl = 0;
+  for (int k = 0;; ++k) {
+    bool any = false;
+    for (size_t a = 0; a < sp.size(); ++a) {
+      const Inst& o = insts[sp[a]];
+      const int done = k * S;
+      if (done >= o.n_steps) continue;
+      any = true;
+      const bool first = k == 0, lastp = done + S >= o.n_steps;
+      double* abuf = out.buf.get() + per * a;
+      Inst pc = o;
+      pc.k0 = o.k0 + done;
+      pc.n_steps = std::min(S, o.n_steps - done);
+      pc.a_init = first ? o.a_init : abuf;
+      pc.a_out = lastp ? o.a_out : abuf;
+      pc.q_out = lastp ? o.q_out : nullptr;
+      pc.carry = abuf + FS;
+      pc.carry_in = first ? 0 : 1;
+      pc.dep_wait = prev[a];
+      pc.dep_done = lastp ? nullptr : out.flags.get() + fl;
+      if (!lastp) prev[a] = out.flags.get() + fl++;
+      out.pieces.push_back(pc);
+      out.orig.push_back((int)sp[a]);
+    }
+    if (!any) break;
+  }
+  *used = true;
+  return MQ_OK;
+}
+
 int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, RunOut* ro,
                   std::vector<int>* stat_host) {
   const int n = (int)insts.size();
@@ -165,28 +297,34 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     ro->status = std::max(ro->status, status);
     return MQ_OK;
   }
+  Split spl;
+  bool split = false;
+  int rc = stat_host ? MQ_OK : plan_split(p, insts, spl, &split);
+  if (rc) return rc;
+  std::vector<Inst>& run = split ? spl.pieces : insts;
+  const int nr = (int)run.size();
   TmpPtr<int> dstat;
-  HIP_TRY(tmp_alloc(dstat, (size_t)n * STAT_N, p->stream));
-  HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)n * STAT_N, p->stream));
-  for (int i = 0; i < n; ++i) insts[i].stat = dstat.get() + STAT_N * i;
+  HIP_TRY(tmp_alloc(dstat, (size_t)nr * STAT_N, p->stream));
+  HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)nr * STAT_N, p->stream));
+  for (int i = 0; i < nr; ++i) run[i].stat = dstat.get() + STAT_N * i;
   TmpPtr<Inst> dinst;
-  HIP_TRY(tmp_alloc(dinst, n, p->stream));
-  HIP_TRY(hipMemcpyAsync(dinst.get(), insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
-  const size_t slots = std::min<size_t>((size_t)n, max_slots(p));
-  int rc = ensure_work(p, slots);
+  HIP_TRY(tmp_alloc(dinst, nr, p->stream));
+  HIP_TRY(hipMemcpyAsync(dinst.get(), run.data(), nr * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
+  const size_t slots = std::min<size_t>((size_t)nr, max_slots(p));
+  rc = ensure_work(p, slots);
   if (rc) return rc;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, p->stream));
-  rc = launch_persistent(p, dinst.get(), n, &ro->grid, &ro->block);
+  rc = launch_persistent(p, dinst.get(), nr, &ro->grid, &ro->block);
   if (rc) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
   }
   HIP_TRY(hipEventRecord(e1, p->stream));
-  std::vector<int> sh((size_t)n * STAT_N);
+  std::vector<int> sh((size_t)nr * STAT_N);
   HIP_TRY(hipMemcpyAsync(sh.data(), dstat.get(), sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   float ms = 0;
@@ -194,16 +332,16 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ro->kernel_ms += ms;
-  // per-instance device wall-clock stamps -> per-group completion latency
+  // per-entry device wall-clock stamps -> per-group completion latency
   auto stamp = [&](int i, int w) {
     const int* q = &sh[(size_t)STAT_N * i + 4 + 2 * w];
     return (uint64_t)(uint32_t)q[0] | ((uint64_t)(uint32_t)q[1] << 32);
   };
   uint64_t t_first = ~0ull;
-  for (int i = 0; i < n; ++i) t_first = std::min(t_first, stamp(i, 0));
+  for (int i = 0; i < nr; ++i) t_first = std::min(t_first, stamp(i, 0));
   {
     std::vector<std::pair<int, uint64_t>> done;
-    for (int i = 0; i < n; ++i) done.push_back({insts[i].group, stamp(i, 1)});
+    for (int i = 0; i < nr; ++i) done.push_back({run[i].group, stamp(i, 1)});
     std::sort(done.begin(), done.end());
     std::vector<double> lat;
     for (size_t a = 0; a < done.size();) {
@@ -224,27 +362,35 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
       st->lat_max_ms = lat.back();
     }
   }
-  for (int i = 0; i < n; ++i) {
+  // counters per entry; flags per original instance (its pieces OR-ed)
+  std::vector<int> oflags(n, 0);
+  for (int i = 0; i < nr; ++i) {
     const int* s4 = &sh[(size_t)STAT_N * i];
+    oflags[split ? spl.orig[i] : i] |= s4[3];
     if (st) {
-      st->n_instances += 1;
-      st->sample_steps += (int64_t)insts[i].n_steps * std::max(1, insts[i].n_chain);
+      st->sample_steps += (int64_t)run[i].n_steps * std::max(1, run[i].n_chain);
       st->inner_iters += s4[0];
       st->sweeps += s4[1];
       st->max_inner_per_step = std::max(st->max_inner_per_step, s4[2]);
       for (int q = 0; q < 8; ++q) st->phase_ms[q] += (double)(uint32_t)s4[8 + q] * 16.0 / p->wall_khz;
       st->busy_ms += (double)(stamp(i, 1) - stamp(i, 0)) / p->wall_khz;
       st->picard_iters += s4[16];
-      if (s4[3] & FLAG_NOT_CONVERGED) st->n_not_converged++;
-      if (s4[3] & FLAG_FAILED) st->n_failed++;
     }
-    if (s4[3] & (FLAG_NOT_CONVERGED | FLAG_FAILED)) ro->status = MQ_WARN_NOT_CONVERGED;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (st) {
+      st->n_instances += 1;
+      if (oflags[i] & FLAG_NOT_CONVERGED) st->n_not_converged++;
+      if (oflags[i] & FLAG_FAILED) st->n_failed++;
+    }
+    if (oflags[i] & (FLAG_NOT_CONVERGED | FLAG_FAILED)) ro->status = MQ_WARN_NOT_CONVERGED;
   }
   if (st) {
     st->path = p->path;
     st->grid = ro->grid;
     st->block = ro->block;
     st->kernel_ms += ms;
+    st->n_pieces += split ? nr : 0;
   }
   if (stat_host) *stat_host = std::move(sh);
   return MQ_OK;
@@ -569,6 +715,7 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
         st->max_inner_per_step = std::max(st->max_inner_per_step, s.max_inner_per_step);
         st->n_not_converged += s.n_not_converged;
         st->n_failed += s.n_failed;
+      st->n_pieces += s.n_pieces;
         st->path = s.path;
         st->grid = s.grid;
         st->block = s.block;
@@ -683,6 +830,7 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
       st->max_inner_per_step = std::max(st->max_inner_per_step, s.max_inner_per_step);
       st->n_not_converged += s.n_not_converged;
       st->n_failed += s.n_failed;
+      st->n_pieces += s.n_pieces;
       st->kernel_ms = std::max(st->kernel_ms, s.kernel_ms);  // concurrent launches
       st->busy_ms += s.busy_ms;
       st->lat_p50_ms = std::max(st->lat_p50_ms, s.lat_p50_ms);
@@ -1012,6 +1160,7 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
       st->max_inner_per_step = std::max(st->max_inner_per_step, s->max_inner_per_step);
       st->n_not_converged += s->n_not_converged;
       st->n_failed += s->n_failed;
+      st->n_pieces += s->n_pieces;
       st->kernel_ms += s->kernel_ms;
     }
     st->path = sa.path;

@@ -594,6 +594,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   VT* tNE = tN + TRH;
   VT* ctab = tNE + TRH;                                  // coarse Galerkin tables (multigrid)
   __shared__ int s_inst;
+  __shared__ int s_depok;
   __shared__ int s_dmin;  // bits of min_i D_ii^{-1/2} (positive float: int order = float order)
 
   const int tid = threadIdx.x;
@@ -706,6 +707,27 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       build_galerkin<VT>(mg, ctab, tE, tN, tNE, dnf, false, d_air, TP, tid, NT);
     }
     };
+    // a later piece of an instance: wait (bounded) until the previous piece has
+    // published its state; the work queue hands out a piece only after its
+    // predecessor, so the wait ends
+    int dep_flags = 0;
+    if (in.dep_wait) {
+      if (tid == 0) {
+        const unsigned long long tw = wall_clock64();
+        int ok = 1;
+        while (__hip_atomic_load(in.dep_wait, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          if (wall_clock64() - tw > DEP_WAIT_TICKS) {
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+        s_depok = ok;
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (!s_depok) dep_flags = FLAG_FAILED;
+    }
     for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
 #pragma unroll 1
     for (int k = 0; k < SH; ++k) {
@@ -774,7 +796,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     auto DN = [&](int k) -> double { return (double)Dv[k * NT + tid]; };
 
     double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
-    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0, pic_total = 0;
+    int it_total = 0, sw_total = 0, it_max_step = 0, flags = dep_flags, pic_total = 0;
     // per-phase device wall-clock ticks (thread 0): fine V-cycle descent,
     // coarse levels, fine ascent, CG apply + reductions; right-hand side,
     // refinement residuals, increment updates, QoI + state update
@@ -1223,6 +1245,12 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         }
       }
       if (tid == 0) in.carry[2 * FS] = qsum;
+    }
+    if (in.dep_done) {
+      // publish a_out and carry to the next piece (it may run on another XCD)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(in.dep_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;

@@ -83,7 +83,17 @@ struct Inst {
   // so a run split into launches at any step gives the unsplit result bit for bit.
   double* carry;
   int carry_in;
+  // Pieces of one instance in one launch (resident path): a piece with
+  // dep_wait waits until that flag is set before it reads a_init and carry;
+  // one with dep_done sets that flag once its a_out and carry are written.
+  const int* dep_wait;
+  int* dep_done;
 };
+
+// Longest wait of a piece for its predecessor, 5 s of the device wall clock
+// (100 MHz), far above one piece's run time; past it the piece runs flagged
+// FLAG_FAILED instead of waiting on.
+constexpr unsigned long long DEP_WAIT_TICKS = 500000000ull;
 
 // Geometric multigrid hierarchy of the resident path (fine interior n = 2^k - 1;
 // level l+1 has (n_l - 1)/2 nodes per side, coarse node c sits at fine 2c + 1).

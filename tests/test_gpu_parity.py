@@ -368,3 +368,36 @@ def test_combined_run_matches_oracle():
     for l in range(2):
         assert np.array_equal(qf2[l].cpu().numpy(), qf[l].cpu().numpy())
     p.close()
+
+
+def test_tail_split_is_bitwise():
+    """Short instances run as chains of dependent pieces (split_steps) when that
+    shortens the launch: on a level mix shaped like the three-level workload and
+    sized to the device's slots, every Q equals the unsplit run's bit for bit,
+    and a few against the oracle."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    p0 = mq.Problem(prob, L.MQ_PREC_MIXED, path=L.MQ_PATH_RESIDENT, split_steps=-1)
+    p1 = mq.Problem(prob, L.MQ_PREC_MIXED, path=L.MQ_PATH_RESIDENT, split_steps=16)
+    probe = W.normals(0, 26, 0, range(4096), 8)
+    _, _, _, rc, st = mq.mlmc_level_run(p0, 2, 0, 1, probe)
+    G = st["grid"]
+    ns = (2 * G, max(2, G // 2), max(2, G // 8))
+    levels = [(16, 0, 4), (32, 16, 4), (64, 32, 4)]
+    xis = [W.normals(0, 27, l, range(n), 8) for l, n in enumerate(ns)]
+    say("tail split: slots", G, "samples", ns)
+    qf0, qc0, rc0, st0 = mq.mlmc_multilevel_run(p0, levels, xis)
+    qf1, qc1, rc1, st1 = mq.mlmc_multilevel_run(p1, levels, xis)
+    say("unsplit", st0["kernel_ms"], "ms; split", st1["kernel_ms"], "ms, entries", st1["n_pieces"])
+    assert rc0 == 0 and rc1 == 0
+    assert st0["n_pieces"] == 0 and st1["n_pieces"] > st1["n_instances"]
+    assert st1["n_instances"] == st0["n_instances"] and st1["sample_steps"] == st0["sample_steps"]
+    assert st1["inner_iters"] == st0["inner_iters"] and st1["n_failed"] == 0
+    for l in range(3):
+        assert np.array_equal(qf0[l].cpu().numpy(), qf1[l].cpu().numpy()), l
+        if l > 0:
+            assert np.array_equal(qc0[l].cpu().numpy(), qc1[l].cpu().numpy()), l
+    rf, _ = oracle_q(prob, xis[0][:3], 16, 4)
+    assert np.max(np.abs(qf1[0][:3].cpu().numpy() - rf) / np.abs(rf)) <= 1e-6
+    p0.close()
+    p1.close()
