@@ -120,7 +120,7 @@ typedef struct mq_problem_desc {
                            the device has slots, short instances may run as dependent pieces of
                            this many steps, queued after the long ones, where a simulation of the
                            work queue says the launch ends sooner (results are bitwise those of
-                           the unsplit run).  0: 64; -1: never. */
+                           the unsplit run).  0: 32; -1: never. */
   int32_t reserved;
 } mq_problem_desc;
 

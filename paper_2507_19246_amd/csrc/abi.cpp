@@ -173,8 +173,8 @@ double queue_makespan(const std::vector<std::pair<int, int>>& items, size_t slot
   return mk;
 }
 
-// Tail splitting (resident path, linear, plain instances, more instances than
-// slots): instances of at most a quarter (or half) of the longest one's steps
+// Tail splitting (resident path, linear material, plain instances, more
+// instances than slots): instances of at most a quarter (or half) of the longest one's steps
 // become chains of S-step pieces, queued after the other instances one round of
 // pieces at a time; the threshold whose simulated makespan is shortest (by more
 // than 2%, counting two steps per piece for its set-up) is used.  The pieces
@@ -192,7 +192,7 @@ int plan_split(mq_problem* p, const std::vector<Inst>& insts, Split& out, bool* 
   const size_t n = insts.size();
   size_t slots = std::min(n, max_slots(p));
   if (p->grid_cap > 0) slots = std::min(slots, (size_t)p->grid_cap);
-  const int S = p->d.split_steps == 0 ? 64 : p->d.split_steps;
+  const int S = p->d.split_steps == 0 ? 32 : p->d.split_steps;
   if (p->d.split_steps < 0 || p->path != MQ_PATH_RESIDENT || p->d.material == MQ_MAT_NONLINEAR || n <= slots)
     return MQ_OK;
   int max_steps = 0;

@@ -401,3 +401,4 @@ def test_tail_split_is_bitwise():
     assert np.max(np.abs(qf1[0][:3].cpu().numpy() - rf) / np.abs(rf)) <= 1e-6
     p0.close()
     p1.close()
+
