@@ -121,7 +121,8 @@ typedef struct mq_problem_desc {
                            this many steps, queued after the long ones, where a simulation of the
                            work queue says the launch ends sooner (results are bitwise those of
                            the unsplit run).  0: 32; -1: never. */
-  int32_t reserved;
+  int32_t mg_block_min; /* multigrid coarse levels with at least this many interior nodes per side
+                           run on the whole workgroup, smaller ones on one wavefront (0: 15) */
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;

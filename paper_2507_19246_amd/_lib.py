@@ -43,7 +43,7 @@ class ProblemDesc(C.Structure):
         ("max_iter", C.c_int32), ("max_sweeps", C.c_int32),
         ("precond", C.c_int32), ("tile", C.c_int32), ("mg_omega", C.c_double),
         ("mg_levels", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
-        ("split_steps", C.c_int32), ("reserved", C.c_int32),
+        ("split_steps", C.c_int32), ("mg_block_min", C.c_int32),
     ]
 
 

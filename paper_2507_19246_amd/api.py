@@ -42,6 +42,7 @@ def default_desc(problem, precision: int, path: int = L.MQ_PATH_AUTO, **solver) 
     d.mg_levels = sv.get("mg_levels", 0)
     d.mg_coarse_sweeps = sv.get("mg_coarse_sweeps", 0)
     d.split_steps = sv.get("split_steps", 0)
+    d.mg_block_min = sv.get("mg_block_min", 0)
     d.mg_omega = sv.get("mg_omega", 0.0)
     return d
 

@@ -49,6 +49,7 @@ Solver solver_of(const mq_problem* p) {
   sv.tile = p->tile;
   sv.mg_levels = p->d.mg_levels;
   sv.mg_coarse_sweeps = p->d.mg_coarse_sweeps;
+  sv.mg_block_min = p->d.mg_block_min > 0 ? p->d.mg_block_min : 15;
   return sv;
 }
 
@@ -135,6 +136,7 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->mg_levels < 0 || d->mg_coarse_sweeps < 0 || d->mg_coarse_sweeps > 64)
     return fail(MQ_ERR_INVALID_ARG, "mg_levels >= 0 and 0 <= mg_coarse_sweeps <= 64 required");
   if (d->split_steps < -1) return fail(MQ_ERR_INVALID_ARG, "split_steps must be >= -1");
+  if (d->mg_block_min < 0) return fail(MQ_ERR_INVALID_ARG, "mg_block_min must be >= 0");
   return MQ_OK;
 }
 
@@ -545,12 +547,12 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   std::memcpy(p->mat, m, sizeof(m));
   const Geom& g = p->hm.g;
   HIP_TRY(dev_alloc(p->dS, p->hm.S.size()));
-  HIP_TRY(hipMemcpy(p->dS.get(), p->hm.S.data(), p->hm.S.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(copy_sync(p->dS.get(), p->hm.S.data(), p->hm.S.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(dev_alloc(p->dcond, p->hm.cond.size()));
-  HIP_TRY(hipMemcpy(p->dcond.get(), p->hm.cond.data(), p->hm.cond.size(), hipMemcpyHostToDevice));
+  HIP_TRY(copy_sync(p->dcond.get(), p->hm.cond.data(), p->hm.cond.size(), hipMemcpyHostToDevice, p->stream));
   if (!p->hm.kl.empty()) {
     HIP_TRY(dev_alloc(p->dkl, p->hm.kl.size()));
-    HIP_TRY(hipMemcpy(p->dkl.get(), p->hm.kl.data(), p->hm.kl.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(copy_sync(p->dkl.get(), p->hm.kl.data(), p->hm.kl.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   }
   HIP_TRY(dev_alloc(p->dcounter, 1));
   HIP_TRY(dev_alloc(p->dflag, 1));

@@ -411,14 +411,14 @@ __device__ __attribute__((always_inline)) inline const VT* c_coarsest(CLev<VT> C
 // Coarse part of the V(1,1) cycle over levels 1..L (L = min(nlev, lmax) when
 // lmax > 0), R_1 and Z_1 = om ID R_1 (ID R_1 if L = 1) already in place.  At
 // level L, Z_L = ID R_L followed by `csweeps` damped-Jacobi sweeps (exact when
-// level L is the single-node level).  Levels with n >= 31 use the whole
+// level L is the single-node level).  Levels with n >= block_min use the whole
 // workgroup, smaller ones run on wave 0 alone.  Returns level 1's corrected
 // vector.
 template <typename VT, int NT>
 __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
-                                         VT air = VT(1), int lmax = 0, int csweeps = 0) {
+                                         VT air = VT(1), int lmax = 0, int csweeps = 0, int block_min = 15) {
   const int L = (lmax > 0 && lmax < mg.nlev) ? lmax : mg.nlev;
-  auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= 31; };
+  auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= block_min; };
   auto bsync = [] { __syncthreads(); };
   int lb = 0;  // last block level
   while (lb + 1 <= L && is_block(lb + 1)) ++lb;
@@ -977,7 +977,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
                 }
                 __syncthreads();
                 tick(0);
-                const VT* z1 = coarse_cycle<VT, NT>(mg, rl, ctab, om, tid, VT(1), sv.mg_levels, sv.mg_coarse_sweeps);
+                const VT* z1 = coarse_cycle<VT, NT>(mg, rl, ctab, om, tid, VT(1), sv.mg_levels, sv.mg_coarse_sweeps,
+                                                    sv.mg_block_min);
                 tick(1);
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
@@ -1914,7 +1915,8 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                   }
                 }
                 __syncthreads();
-                const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps);
+                const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
+                                                    sv.mg_block_min);
                 __syncthreads();
                 nodes([&](int i, int j, const NodeRef& nr) {
                   Zm[nr.gi] += prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr);

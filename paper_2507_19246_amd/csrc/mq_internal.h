@@ -125,6 +125,7 @@ struct Solver {
   int tile;        // resident workgroup shape (host-side dispatch)
   int mg_levels;   // coarse levels in use (0: all)
   int mg_coarse_sweeps;  // damped-Jacobi sweeps at the coarsest level in use
+  int mg_block_min;      // coarse levels with at least this many nodes per side use the whole workgroup
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };

@@ -96,15 +96,24 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
   c.w.sc = sc.get();
 
   // capture one batch of inner iterations (its kernels read everything that
-  // changes from device memory, so one graph serves every instance)
+  // changes from device memory, so one graph serves every instance).  Another
+  // thread's operation on the legacy default stream can invalidate a capture;
+  // the batch is then launched directly (the same kernels in the same order).
   GraphExec graph;
-  HIP_TRY(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
-  hipError_t ce = hipSuccess;
-  for (int b = 0; b < WIDE_BATCH && ce == hipSuccess; ++b) ce = wide_iteration(c, ws);
-  hipError_t ee = hipStreamEndCapture(ws, &graph.g);
-  if (ce != hipSuccess) return fail(MQ_ERR_DEVICE, std::string("wide capture: ") + hipGetErrorString(ce));
-  if (ee != hipSuccess) return fail(MQ_ERR_DEVICE, std::string("wide capture: ") + hipGetErrorString(ee));
-  HIP_TRY(hipGraphInstantiate(&graph.e, graph.g, nullptr, nullptr, 0));
+  bool use_graph = false;
+  if (hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    hipError_t ce = hipSuccess;
+    for (int b = 0; b < WIDE_BATCH && ce == hipSuccess; ++b) ce = wide_iteration(c, ws);
+    const hipError_t ee = hipStreamEndCapture(ws, &graph.g);
+    use_graph = ce == hipSuccess && ee == hipSuccess && graph.g &&
+                hipGraphInstantiate(&graph.e, graph.g, nullptr, nullptr, 0) == hipSuccess;
+  }
+  if (!use_graph) {
+    (void)hipGetLastError();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(ws, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(MQ_ERR_DEVICE, "wide path: stream left in capture");
+  }
 
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -141,7 +150,11 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
         if (sweep == c.sv.max_sweeps) break;
         ++sweeps;
         for (int b = 0; b < max_batches; ++b) {
-          HIP_TRY(hipGraphLaunch(graph.e, ws));
+          if (use_graph) {
+            HIP_TRY(hipGraphLaunch(graph.e, ws));
+          } else {
+            for (int i = 0; i < WIDE_BATCH; ++i) HIP_TRY(wide_iteration(c, ws));
+          }
           HIP_TRY(read_sc());
           if (h.done) break;
         }
