@@ -38,6 +38,15 @@ def cache_path() -> str:
     return os.environ.get("MQ_AUTOTUNE_CACHE", DEFAULT_CACHE)
 
 
+def device_id() -> str:
+    """Cache identity of device 0: architecture and compute-unit count (the
+    marketing name depends on the host's device table and is not stable)."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    arch = (getattr(p, "gcnArchName", "") or "").split(":")[0] or torch.cuda.get_device_name(0)
+    return f"{arch}-{p.multi_processor_count}cu"
+
+
 def cache_key(device: str, problem, precision: int) -> str:
     m = problem.material
     return f"{device}|n{problem.n_nodes}|mat{m.kind}|prec{precision}"
@@ -89,7 +98,7 @@ def _load(path: str) -> Dict:
 def lookup(problem, precision: int, device: Optional[str] = None, path: Optional[str] = None) -> Optional[Dict]:
     """Cached knobs for this problem, or None."""
     import torch
-    device = device or torch.cuda.get_device_name(0)
+    device = device or device_id()
     return _load(path or cache_path()).get(cache_key(device, problem, precision), {}).get("knobs")
 
 
@@ -103,7 +112,7 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
     from . import api as mq
 
     path = path or cache_path()
-    device = torch.cuda.get_device_name(0)
+    device = device_id()
     key = cache_key(device, problem, precision)
     db = _load(path)
     if not force and key in db:

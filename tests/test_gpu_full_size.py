@@ -130,3 +130,13 @@ def test_full_size_serving_513(golden):
     say("513x513 request", r.steps_per_period, "steps/period: err", e,
         "latency ms", (res.t_done_ns - res.t_submit_ns) / 1e6)
     assert e <= TOL
+
+
+def test_tuned_knobs_are_found():
+    """The committed autotuner cache has this device's entries for the bench
+    workloads, so every bench line runs its tuned configuration."""
+    import paper_2507_19246_amd  # noqa: F401
+    from paper_2507_19246_amd import _lib as L, autotune
+    say("device id", autotune.device_id())
+    for w in (W.mlmc3_mixed_129(), W.parareal_257(), W.nonlinear_mlmc4_129()):
+        assert autotune.lookup(w.problem, L.MQ_PREC_MIXED) is not None, w.name
