@@ -96,7 +96,7 @@ def _oracle_task(args):
     return q, spp * nper, time.perf_counter() - t
 
 
-def cpu_baseline(w, xis, n_per_level=(4, 1, 1)):
+def cpu_baseline(w, xis, n_per_level=(12, 4, 2)):
     """Time the FP64 oracle on a bounded sample of the same workload."""
     import multiprocessing as mp
     tasks, keys = [], []
