@@ -1734,7 +1734,7 @@ __host__ __device__ inline size_t stream_slot_elems(const Geom& g, const MGGeom&
 }
 
 template <typename VT, int NT, bool MG>
-__global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, const Inst* __restrict__ insts,
+__global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver sv, const Inst* __restrict__ insts,
                                                   int n_inst, int* counter, double* work,
                                                   const double* __restrict__ S, VT* vwork) {
   constexpr int NWAVES = NT / 64;
@@ -1887,6 +1887,27 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 for (int j = fj0; j < n; j += fty)
                   for (int i = ftx; i < n; i += (1 << fs)) f(i, j, node_ref(g, i, j));
               };
+              // The same nodes two rows at a time, split into a pure load/compute
+              // part `ld` and a store/accumulate part `st`: both nodes' loads are
+              // issued before either node's stores, which doubles the loads in
+              // flight (no node of a pass reads what another node of the same pass
+              // writes).  Stores and sums keep the order of `nodes` whenever a row
+              // holds one node per thread (meshes up to 513 x 513).
+              struct V2 {
+                VT x, y;
+              };
+              auto nodes2 = [&](auto&& ld, auto&& st) __attribute__((always_inline)) {
+                for (int j = fj0; j < n; j += 2 * fty) {
+                  const int j2 = j + fty;
+                  const int jb = j2 < n ? j2 : j;  // past the last row: reload row j, store nothing
+                  for (int i = ftx; i < n; i += (1 << fs)) {
+                    const NodeRef a = node_ref(g, i, j), b = node_ref(g, i, jb);
+                    const V2 va = ld(i, j, a), vb = ld(i, jb, b);
+                    st(a, va);
+                    if (j2 < n) st(b, vb);
+                  }
+                }
+              };
               VT* Zm = Sv;  // preconditioned residual
               VT* Tm = Wv;  // fine residual t / smoothing output (swapped with Zm)
               // coarse levels hold the unscaled operators: level 1 <-> scaled fine
@@ -1897,11 +1918,15 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
               double rho = 1.0, stop = 0.0;
               for (;;) {
                 // z = B r: pre-smoothing from zero (z = om r) and t = r - A z
-                nodes([&](int i, int j, const NodeRef& nr) {
-                  const VT r = Rv[nr.gi];
-                  Zm[nr.gi] = om * r;
-                  Tm[nr.gi] = (r - om * stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr)) * dnode_inv(i, j, nr);
-                });
+                nodes2(
+                    [&](int i, int j, const NodeRef& nr) {
+                      const VT r = Rv[nr.gi];
+                      return V2{om * r, (r - om * stencil_scaled<VT>(g, Rv, tE, tN, tNE, nr)) * dnode_inv(i, j, nr)};
+                    },
+                    [&](const NodeRef& nr, const V2& v) {
+                      Zm[nr.gi] = v.x;
+                      Tm[nr.gi] = v.y;
+                    });
                 __syncthreads();
                 {  // restriction to level 1
                   const int tx = tid & ((1 << L1.txs) - 1), ty = NT >> L1.txs;
@@ -1918,19 +1943,24 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
                                                     sv.mg_block_min);
                 __syncthreads();
-                nodes([&](int i, int j, const NodeRef& nr) {
-                  Zm[nr.gi] += prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr);
-                });
+                nodes2(
+                    [&](int i, int j, const NodeRef& nr) {
+                      return V2{Zm[nr.gi] + prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr), VT(0)};
+                    },
+                    [&](const NodeRef& nr, const V2& v) { Zm[nr.gi] = v.x; });
                 __syncthreads();
                 // post-smoothing z <- z + om (r - A z); r.z and r.r of the new z
                 double rz[2] = {0.0, 0.0};
-                nodes([&](int, int, const NodeRef& nr) {
-                  const VT r = Rv[nr.gi], z = Zm[nr.gi];
-                  const VT zn = z + om * (r - stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr));
-                  Tm[nr.gi] = zn;
-                  rz[0] += (double)(r * zn);
-                  rz[1] += (double)(r * r);
-                });
+                nodes2(
+                    [&](int, int, const NodeRef& nr) {
+                      const VT r = Rv[nr.gi], z = Zm[nr.gi];
+                      return V2{z + om * (r - stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr)), r};
+                    },
+                    [&](const NodeRef& nr, const V2& v) {
+                      Tm[nr.gi] = v.x;
+                      rz[0] += (double)(v.y * v.x);
+                      rz[1] += (double)(v.y * v.y);
+                    });
                 block_sum<2, NWAVES>(rz, red, slot);
                 { VT* t_ = Zm; Zm = Tm; Tm = t_; }
                 double beta = 0.0;
@@ -1947,19 +1977,25 @@ __global__ __launch_bounds__(NT) void k_ie_stream(Geom g, MGGeom mg, Solver sv, 
                 // p = z + beta p and q = A p = A z + beta q (one pass)
                 const VT b_ = vt<VT>(beta);
                 double pq[1] = {0.0};
-                nodes([&](int, int, const NodeRef& nr) {
-                  const VT p = Zm[nr.gi] + b_ * Pv[nr.gi];
-                  const VT q = stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr) + b_ * Vv[nr.gi];
-                  Pv[nr.gi] = p;
-                  Vv[nr.gi] = q;
-                  pq[0] += (double)(p * q);
-                });
+                nodes2(
+                    [&](int, int, const NodeRef& nr) {
+                      return V2{Zm[nr.gi] + b_ * Pv[nr.gi], stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr) + b_ * Vv[nr.gi]};
+                    },
+                    [&](const NodeRef& nr, const V2& v) {
+                      Pv[nr.gi] = v.x;
+                      Vv[nr.gi] = v.y;
+                      pq[0] += (double)(v.x * v.y);
+                    });
                 block_sum<1, NWAVES>(pq, red, slot);
                 const VT a_ = vt<VT>(rho / pq[0]);
-                nodes([&](int, int, const NodeRef& nr) {
-                  Yv[nr.gi] += a_ * Pv[nr.gi];
-                  Rv[nr.gi] -= a_ * Vv[nr.gi];
-                });
+                nodes2(
+                    [&](int, int, const NodeRef& nr) {
+                      return V2{Yv[nr.gi] + a_ * Pv[nr.gi], Rv[nr.gi] - a_ * Vv[nr.gi]};
+                    },
+                    [&](const NodeRef& nr, const V2& v) {
+                      Yv[nr.gi] = v.x;
+                      Rv[nr.gi] = v.y;
+                    });
                 __syncthreads();
               }
             } else {
