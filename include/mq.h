@@ -187,6 +187,18 @@ typedef struct mq_parareal_desc {
   double tol;
 } mq_parareal_desc;
 
+/* The tail-splitting plan that the level runs use on the resident path
+ * (host arithmetic only; see mq_problem_desc.split_steps): a launch of n
+ * instances of steps[i] steps on `slots` persistent slots, with split_steps
+ * as in the descriptor.  *m_out receives the number of launch entries (n when
+ * nothing is split); the first min(m, cap) entries are written: entry e runs
+ * steps [first[e], first[e] + len[e]) of instance orig[e] and waits for entry
+ * dep[e] (-1: none).  makespan (nullable, [2]): the simulated launch length in
+ * steps without and with the plan (pieces counted with two extra steps of
+ * set-up).  Errors: n < 0, a step count < 1, slots < 1, split_steps < -1. */
+int mq_plan_split(int32_t n, const int32_t* steps, int32_t slots, int32_t split_steps, int32_t cap,
+                  int32_t* orig, int32_t* first, int32_t* len, int32_t* dep, double* makespan, int32_t* m_out);
+
 const char* mq_last_error(void);
 int mq_version(void);
 

@@ -160,6 +160,8 @@ SIGNATURES = {
                                     C.POINTER(CombinedDesc), C.POINTER(VP), C.POINTER(VP), VP, C.POINTER(RunStats),
                                     C.POINTER(CombinedStats)]),
     "mq_cost_model": (C.c_int, [C.POINTER(CostIn), C.POINTER(CostOut)]),
+    "mq_plan_split": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                PD, C.POINTER(C.c_int32)]),
     "mlmc_estimate": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(VP), C.POINTER(VP), VP, VP]),
     "mq_debug_apply": (C.c_int, [VP, C.c_int32, C.c_double, C.c_int32, VP, VP, VP]),
     "mq_server_create": (C.c_int, [C.POINTER(ServerDesc), VP, C.POINTER(VP)]),

@@ -204,6 +204,22 @@ def mlmc_combined_run(prob: Problem, levels: Sequence, xis: Sequence, n_slices: 
     return qfs, qcs, it, rc, st.as_dict(), cs.as_dict()
 
 
+def plan_split(steps: Sequence[int], slots: int, split_steps: int = 0) -> dict:
+    """The tail-splitting plan of a launch (mq_plan_split, host arithmetic): lists
+    orig, first, len, dep per launch entry and the simulated makespans (steps)."""
+    lib = L.load()
+    n = len(steps)
+    st = (C.c_int32 * max(n, 1))(*steps)
+    m = C.c_int32()
+    mk = (C.c_double * 2)()
+    L.check(lib.mq_plan_split(n, st, slots, split_steps, 0, None, None, None, None, mk, C.byref(m)))
+    cap = m.value
+    arrs = [(C.c_int32 * max(cap, 1))() for _ in range(4)]
+    L.check(lib.mq_plan_split(n, st, slots, split_steps, cap, *arrs, mk, C.byref(m)))
+    o, f, ln, d = ([int(x) for x in a[:cap]] for a in arrs)
+    return {"orig": o, "first": f, "len": ln, "dep": d, "makespan": (mk[0], mk[1])}
+
+
 def cost_model(C_l: Sequence[float], N_l: Sequence[float], K: int, M: int, n_cores: int) -> dict:
     """The combined method's cost model (mq_cost_model): Eqs. (15)-(19), (21)-(25)."""
     lib = L.load()

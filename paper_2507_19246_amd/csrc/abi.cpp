@@ -175,13 +175,100 @@ double queue_makespan(const std::vector<std::pair<int, int>>& items, size_t slot
   return mk;
 }
 
-// Tail splitting (resident path, linear material, plain instances, more
-// instances than slots): instances of at most a quarter (or half) of the longest one's steps
-// become chains of S-step pieces, queued after the other instances one round of
-// pieces at a time; the threshold whose simulated makespan is shortest (by more
-// than 2%, counting two steps per piece for its set-up) is used.  The pieces
-// carry the state through `buf` (per split instance: a, then the carry record)
-// and order themselves through `flags` (one per piece but the last).
+// Tail splitting: with more instances than slots, instances of at most a
+// quarter (or half) of the longest one's steps become chains of S-step pieces,
+// queued after the other instances one round of pieces at a time; the threshold
+// whose simulated makespan is shortest (by more than 2%, counting two steps per
+// piece for its set-up) is used.  Entry e of the plan runs steps
+// [first, first + len) of instance orig and waits for entry dep (-1: none).
+struct PiecePlan {
+  std::vector<int> orig, first, len, dep;
+  double mk0 = 0, mk = 0;
+  bool split = false;
+};
+
+PiecePlan plan_pieces(const std::vector<int>& steps, size_t slots, int S) {
+  PiecePlan pl;
+  const size_t n = steps.size();
+  std::vector<std::pair<int, int>> base;
+  int max_steps = 0;
+  for (int s : steps) {
+    base.push_back({s, -1});
+    max_steps = std::max(max_steps, s);
+  }
+  pl.mk0 = pl.mk = queue_makespan(base, std::max<size_t>(slots, 1));
+  auto whole = [&]() {
+    for (size_t i = 0; i < n; ++i) {
+      pl.orig.push_back((int)i);
+      pl.first.push_back(0);
+      pl.len.push_back(steps[i]);
+      pl.dep.push_back(-1);
+    }
+  };
+  if (S < 1 || n <= slots) {
+    whole();
+    return pl;
+  }
+  constexpr int SETUP = 2;
+  auto build = [&](int th, PiecePlan& out) {
+    std::vector<size_t> sp;
+    for (size_t i = 0; i < n; ++i) {
+      if (steps[i] <= th && steps[i] >= 2 * S) {
+        sp.push_back(i);
+      } else {
+        out.orig.push_back((int)i);
+        out.first.push_back(0);
+        out.len.push_back(steps[i]);
+        out.dep.push_back(-1);
+      }
+    }
+    std::vector<int> last(sp.size(), -1);
+    for (int k = 0;; ++k) {
+      bool any = false;
+      for (size_t a = 0; a < sp.size(); ++a) {
+        const int done = k * S;
+        if (done >= steps[sp[a]]) continue;
+        any = true;
+        out.orig.push_back((int)sp[a]);
+        out.first.push_back(done);
+        out.len.push_back(std::min(S, steps[sp[a]] - done));
+        out.dep.push_back(last[a]);
+        last[a] = (int)out.orig.size() - 1;
+      }
+      if (!any) break;
+    }
+    return !sp.empty();
+  };
+  double best = pl.mk0 * 0.98;
+  int best_th = 0;
+  for (int th : {max_steps / 4, max_steps / 2}) {
+    PiecePlan c;
+    if (!build(th, c)) continue;
+    std::vector<std::pair<int, int>> q;
+    for (size_t e = 0; e < c.orig.size(); ++e) {
+      const bool piece = c.len[e] != steps[c.orig[e]];
+      q.push_back({c.len[e] + (piece ? SETUP : 0), c.dep[e]});
+    }
+    const double mk = queue_makespan(q, slots);
+    if (mk < best) {
+      best = mk;
+      best_th = th;
+    }
+  }
+  if (best_th == 0) {
+    whole();
+    return pl;
+  }
+  build(best_th, pl);
+  pl.mk = best;
+  pl.split = true;
+  return pl;
+}
+
+// Launch entries of a tail-split plan (resident path, linear material, plain
+// instances).  The pieces of an instance carry the state through `buf` (per
+// split instance: a, then the carry record) and order themselves through
+// `flags` (one per piece but the last).
 struct Split {
   std::vector<Inst> pieces;
   std::vector<int> orig;  // original instance of each entry
@@ -197,91 +284,49 @@ int plan_split(mq_problem* p, const std::vector<Inst>& insts, Split& out, bool* 
   const int S = p->d.split_steps == 0 ? 32 : p->d.split_steps;
   if (p->d.split_steps < 0 || p->path != MQ_PATH_RESIDENT || p->d.material == MQ_MAT_NONLINEAR || n <= slots)
     return MQ_OK;
-  int max_steps = 0;
+  std::vector<int> steps;
   for (const Inst& in : insts) {
     if (in.n_chain > 0 || in.carry || in.dep_wait || in.dep_done) return MQ_OK;
-    max_steps = std::max(max_steps, in.n_steps);
+    steps.push_back(in.n_steps);
   }
-  constexpr int SETUP = 2;
-  std::vector<std::pair<int, int>> base;
-  for (const Inst& in : insts) base.push_back({in.n_steps, -1});
-  const double mk0 = queue_makespan(base, slots);
-  double best = mk0 * 0.98;
-  int best_th = 0;
-  for (int th : {max_steps / 4, max_steps / 2}) {
-    std::vector<std::pair<int, int>> q;
-    std::vector<size_t> sp;
-    for (size_t i = 0; i < n; ++i) {
-      if (insts[i].n_steps <= th && insts[i].n_steps >= 2 * S) sp.push_back(i);
-      else q.push_back({insts[i].n_steps, -1});
-    }
-    if (sp.empty()) continue;
-    std::vector<int> last(sp.size(), -1);
-    for (int k = 0;; ++k) {
-      bool any = false;
-      for (size_t a = 0; a < sp.size(); ++a) {
-        const int len = insts[sp[a]].n_steps - k * S;
-        if (len <= 0) continue;
-        any = true;
-        q.push_back({std::min(S, len) + SETUP, last[a]});
-        last[a] = (int)q.size() - 1;
-      }
-      if (!any) break;
-    }
-    const double mk = queue_makespan(q, slots);
-    if (mk < best) {
-      best = mk;
-      best_th = th;
-    }
-  }
-  if (best_th == 0) return MQ_OK;
-  // build the pieces
+  const PiecePlan pl = plan_pieces(steps, slots, S);
+  if (!pl.split) return MQ_OK;
+  const size_t m = pl.orig.size();
+  // per split instance a state buffer; per entry with a successor a flag
   const Geom& g = p->hm.g;
   const size_t FS = (size_t)g.N * g.P, per = 3 * FS + 1;
-  std::vector<size_t> sp;
-  for (size_t i = 0; i < n; ++i) {
-    if (insts[i].n_steps <= best_th && insts[i].n_steps >= 2 * S) sp.push_back(i);
-    else {
-      out.pieces.push_back(insts[i]);
-      out.orig.push_back((int)i);
-    }
+  std::vector<int> buf_of(n, -1), flag_of(m, -1);
+  int n_buf = 0, n_flags = 0;
+  for (size_t e = 0; e < m; ++e) {
+    const int o = pl.orig[e];
+    if (pl.len[e] == steps[o]) continue;
+    if (buf_of[o] < 0) buf_of[o] = n_buf++;
+    if (pl.first[e] + pl.len[e] < steps[o]) flag_of[e] = n_flags++;
   }
-  if (per * sp.size() * sizeof(double) > ((size_t)8 << 30)) {  // keep the state buffers modest
-    out.pieces.clear();
-    out.orig.clear();
-    return MQ_OK;
-  }
-  size_t n_flags = 0;
-  for (size_t i : sp) n_flags += (insts[i].n_steps + S - 1) / S - 1;
-  HIP_TRY(tmp_alloc(out.buf, per * sp.size(), p->stream));
-  HIP_TRY(tmp_alloc(out.flags, n_flags, p->stream));
-  HIP_TRY(launch_fill_zero_i(out.flags.get(), n_flags, p->stream));
-  std::vector<int*> prev(sp.size(), nullptr);
-  size_t fl = 0;
-  for (int k = 0;; ++k) {
-    bool any = false;
-    for (size_t a = 0; a < sp.size(); ++a) {
-      const Inst& o = insts[sp[a]];
-      const int done = k * S;
-      if (done >= o.n_steps) continue;
-      any = true;
-      const bool first = k == 0, lastp = done + S >= o.n_steps;
-      double* abuf = out.buf.get() + per * a;
-      Inst pc = o;
-      pc.k0 = o.k0 + done;
-      pc.n_steps = std::min(S, o.n_steps - done);
-      pc.a_init = first ? o.a_init : abuf;
-      pc.a_out = lastp ? o.a_out : abuf;
-      pc.q_out = lastp ? o.q_out : nullptr;
-      pc.carry = abuf + FS;
-      pc.carry_in = first ? 0 : 1;
-      pc.dep_wait = prev[a];
-      pc.dep_done = lastp ? nullptr : out.flags.get() + fl;
-      if (!lastp) prev[a] = out.flags.get() + fl++;
-      out.pieces.push_back(pc);
-      out.orig.push_back((int)sp[a]);
+  if (per * (size_t)n_buf * sizeof(double) > ((size_t)8 << 30)) return MQ_OK;  // keep the state buffers modest
+  HIP_TRY(tmp_alloc(out.buf, per * (size_t)n_buf, p->stream));
+  HIP_TRY(tmp_alloc(out.flags, (size_t)n_flags, p->stream));
+  HIP_TRY(launch_fill_zero_i(out.flags.get(), (size_t)n_flags, p->stream));
+  for (size_t e = 0; e < m; ++e) {
+    const Inst& o = insts[pl.orig[e]];
+    out.orig.push_back(pl.orig[e]);
+    if (pl.len[e] == o.n_steps) {
+      out.pieces.push_back(o);
+      continue;
     }
-    if (!any) break;
+    const bool first = pl.first[e] == 0, lastp = pl.first[e] + pl.len[e] == o.n_steps;
+    double* abuf = out.buf.get() + per * (size_t)buf_of[pl.orig[e]];
+    Inst pc = o;
+    pc.k0 = o.k0 + pl.first[e];
+    pc.n_steps = pl.len[e];
+    pc.a_init = first ? o.a_init : abuf;
+    pc.a_out = lastp ? o.a_out : abuf;
+    pc.q_out = lastp ? o.q_out : nullptr;
+    pc.carry = abuf + FS;
+    pc.carry_in = first ? 0 : 1;
+    pc.dep_wait = pl.dep[e] >= 0 ? out.flags.get() + flag_of[pl.dep[e]] : nullptr;
+    pc.dep_done = lastp ? nullptr : out.flags.get() + flag_of[e];
+    out.pieces.push_back(pc);
   }
   *used = true;
   return MQ_OK;
@@ -1211,6 +1256,31 @@ int mlmc_estimate(int32_t n_levels, const int32_t* n_per_level, const double* co
   HIP_TRY(hipMemcpyAsync(dqc.get(), qc.data(), n_levels * sizeof(double*), hipMemcpyHostToDevice, st));
   HIP_TRY(launch_level_stats(n_levels, dn.get(), dqf.get(), dqc.get(), out, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return MQ_OK;
+}
+
+int mq_plan_split(int32_t n, const int32_t* steps, int32_t slots, int32_t split_steps, int32_t cap,
+                  int32_t* orig, int32_t* first, int32_t* len, int32_t* dep, double* makespan, int32_t* m_out) {
+  if (n < 0 || (n > 0 && !steps) || slots < 1 || split_steps < -1 || cap < 0 || !m_out)
+    return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
+  if (cap > 0 && (!orig || !first || !len || !dep)) return fail(MQ_ERR_INVALID_ARG, "null output array");
+  std::vector<int> st(steps, steps + n);
+  for (int v : st)
+    if (v < 1) return fail(MQ_ERR_INVALID_ARG, "steps must be >= 1");
+  const int S = split_steps == 0 ? 32 : (split_steps < 0 ? 0 : split_steps);
+  const PiecePlan pl = plan_pieces(st, std::min<size_t>((size_t)n, (size_t)slots), S);
+  const int m = (int)pl.orig.size();
+  for (int e = 0; e < m && e < cap; ++e) {
+    orig[e] = pl.orig[e];
+    first[e] = pl.first[e];
+    len[e] = pl.len[e];
+    dep[e] = pl.dep[e];
+  }
+  if (makespan) {
+    makespan[0] = pl.mk0;
+    makespan[1] = pl.mk;
+  }
+  *m_out = m;
   return MQ_OK;
 }
 
