@@ -526,7 +526,7 @@ def main():
                     help="serving: requests of the stable-load run at 0.7 x the measured capacity (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library runs on one GPU only "
               "(samples would shard across GPUs with one final all-reduce of the level sums)",
               file=sys.stderr)
         sys.exit(2)
