@@ -215,6 +215,34 @@ def test_nonfinite_xi_rejected():
     p.close()
 
 
+def test_empty_and_malformed_inputs_rejected():
+    """Empty sample sets and malformed level or Parareal descriptions are
+    rejected on the host before any launch; the handle stays usable."""
+    mq, L = mqmod()
+    prob = W.Problem(9, W.Material(kind=W.MAT_KL))
+    p = mq.Problem(prob, L.MQ_PREC_MIXED)
+    empty = np.zeros((0, p.n_xi))
+    two = W.normals(0, 31, 0, range(2), p.n_xi)
+    bad = [
+        ("level, no samples", lambda: mq.mlmc_level_run(p, 8, 0, 1, empty)),
+        ("level, zero steps", lambda: mq.mlmc_level_run(p, 0, 0, 1, two)),
+        ("level, zero periods", lambda: mq.mlmc_level_run(p, 8, 4, 0, two)),
+        ("parareal, no samples", lambda: mq.parareal_run(p, 1, 4, 2, 1, 4, 1e-8, empty)),
+        ("parareal, no slices", lambda: mq.parareal_run(p, 1, 0, 2, 1, 4, 1e-8, two)),
+        ("parareal, k_max 0", lambda: mq.parareal_run(p, 1, 4, 2, 1, 0, 1e-8, two)),
+        ("parareal, negative tol", lambda: mq.parareal_run(p, 1, 4, 2, 1, 4, -1.0, two)),
+        ("estimate, empty level", lambda: mq.mlmc_estimate([torch.zeros(0, dtype=torch.float64, device="cuda")], [None])),
+    ]
+    for name, call in bad:
+        say(f"malformed input: {name}")
+        with pytest.raises(L.MQError) as e:
+            call()
+        assert e.value.code == L.MQ_ERR_INVALID_ARG, name
+    qf, _, _, rc, _ = mq.mlmc_level_run(p, 8, 0, 1, two)
+    assert rc == 0 and bool(torch.isfinite(qf).all())
+    p.close()
+
+
 def test_single_dof_mesh():
     mq, L = mqmod()
     prob = W.Problem(3, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0, 1, 0, 1), strip=(0, 1))
