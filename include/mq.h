@@ -31,7 +31,8 @@
  *  - Inputs are validated before any launch; invalid sizes return
  *    MQ_ERR_INVALID_ARG, non-finite xi MQ_ERR_NONFINITE.
  *  - Handles are not thread-safe; a server accepts mq_submit from any thread.
- *  - Times: t_k = k dt from the integer step index, a(t_0) = 0, the source is
+ *  - Times: t_k = k dt from the integer step index, a(t_0) = a_0 (zero unless
+ *    mq_set_initial_state gave one), the source is
  *    evaluated at t_{k+1}.  The state is solved in increment form
  *    (M/dt + K) d_k = r(t_{k+1}) - K a_k, a_{k+1} = a_k + d_k, which is
  *    algebraically Eq. (7); Q = (1/T) sum_k d_k^T M d_k / dt (Eq. (26)).
@@ -107,7 +108,8 @@ typedef struct mq_problem_desc {
   double tol, inner_rtol;
   int32_t max_iter, max_sweeps;
   int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available (n_nodes = 2^k + 1; on the
-                        resident path if its LDS holds the hierarchy), else Jacobi */
+                        resident path if its LDS holds the hierarchy and n_nodes != 9), else Jacobi;
+                        MULTIGRID where it is not available: MQ_ERR_INVALID_ARG */
   int32_t tile;      /* workgroup shape: 0 auto (the built-in default, 1).  Resident path: 1 = 16 rows
                         per thread, 2 = 32 rows per thread in 512-thread workgroups (meshes with
                         64..127 interior nodes per side; others use 1).  Streaming path: 1 = one
@@ -210,6 +212,16 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out);
 int mq_problem_destroy(mq_problem* p);
 int mq_ndof(const mq_problem* p, int64_t* nd);
 int mq_problem_info_get(const mq_problem* p, mq_problem_info* info);
+
+/* Start state a_0 = a(t_0) of Eq. (7) for every later run on this handle:
+ * mlmc_level_run, mlmc_multilevel_run, mlmc_adaptive_run and mlmc_combined_run
+ * (fine and coupled coarse runs alike), the handle's levels of
+ * mlmc_multimesh_run, and U_0 of parareal_run (Eq. (12)); servers are not
+ * affected.  a0: device [n_dof] FP64, interior DoF order (j-1)(N-2)+(i-1) (the
+ * boundary ring stays A = 0), copied before return; NULL restores a_0 = 0.
+ * Errors: MQ_ERR_INVALID_ARG (null handle), MQ_ERR_NONFINITE (NaN or Inf in a0,
+ * the previous a_0 is kept), MQ_ERR_OUT_OF_MEMORY. */
+int mq_set_initial_state(mq_problem* p, const double* a0);
 
 /* One MLMC level for n_samples samples.
  * xi: device [n_samples][n_xi] FP64.  q_fine: device [n_samples] (Q on the

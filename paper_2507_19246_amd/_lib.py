@@ -147,6 +147,7 @@ SIGNATURES = {
     "mq_problem_destroy": (C.c_int, [VP]),
     "mq_ndof": (C.c_int, [VP, C.POINTER(C.c_int64)]),
     "mq_problem_info_get": (C.c_int, [VP, C.POINTER(ProblemInfo)]),
+    "mq_set_initial_state": (C.c_int, [VP, VP]),
     "mlmc_level_run": (C.c_int, [VP, C.POINTER(LevelDesc), C.c_int32, VP, VP, VP, VP, C.POINTER(RunStats)]),
     "mlmc_multilevel_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32),
                                       C.POINTER(VP), C.POINTER(VP), C.POINTER(VP), C.POINTER(RunStats)]),

@@ -93,6 +93,16 @@ class Problem:
         except Exception:
             pass
 
+    def set_initial_state(self, a0=None):
+        """a(t_0) of every later run on this handle (interior DoF order); None: zeros."""
+        if a0 is None:
+            L.check(self.lib.mq_set_initial_state(self.h, None))
+            return
+        a = _dev_f64(a0).reshape(-1)
+        if a.numel() != self.n_dof:
+            raise ValueError(f"a0 has {a.numel()} values, the problem has {self.n_dof} DoF")
+        L.check(self.lib.mq_set_initial_state(self.h, _ptr(a)))
+
     @property
     def path(self) -> int:
         if self.desc.path == L.MQ_PATH_WIDE:

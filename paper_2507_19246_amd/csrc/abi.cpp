@@ -499,6 +499,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
     Inst in{};
     in.tab = lb.tables.get() + (size_t)s * tab_stride(g);
     in.src = lb.src_f.get();
+    in.a_init = p->a0.get();  // null: a_0 = 0
     in.a_out = want_state ? lb.afull_ptr[s] : nullptr;
     in.q_out = qf + s;
     in.q_scale = 1.0 / T;
@@ -564,7 +565,12 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   const bool want_mg = d->precond != MQ_PRECOND_JACOBI;
   const int lp = resident_lp(g0, p->tile);
   MGGeom rmg{};
-  const bool res_mg = want_mg && lp > 0 && d->path != MQ_PATH_STREAMING && build_mg(g0, lp, &rmg) &&
+  // the 9-node mesh (7 interior nodes, first coarse level 3 x 3) is left out of
+  // the resident multigrid: its FP64 solves diverged there (Q = inf) while 5-,
+  // 17- and 33-node meshes, mixed precision and the streaming multigrid on the
+  // same mesh agree with the reference; the cause is not found, so this mesh
+  // runs Jacobi-CG on the resident path (or multigrid on the streaming path)
+  const bool res_mg = want_mg && g0.n != 7 && lp > 0 && d->path != MQ_PATH_STREAMING && build_mg(g0, lp, &rmg) &&
                       resident_supported(g0, &rmg, d->precision, p->lds_limit, nullptr, p->tile);
   p->resident_ok = resident_supported(g0, res_mg ? &rmg : nullptr, d->precision, p->lds_limit, &p->lds_bytes, p->tile);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
@@ -586,7 +592,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   if (p->path == MQ_PATH_WIDE && p->mg.nlev < 1)
     return fail(MQ_ERR_INVALID_ARG, "the wide path needs n_nodes = 2^k + 1 (multigrid hierarchy)");
   if (d->precond == MQ_PRECOND_MULTIGRID && p->mg.nlev == 0)
-    return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS)");
+    return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS and n_nodes != 9)");
   p->precond = p->mg.nlev > 0 ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
   const double m[10] = {d->sigma0, d->nu_cond, d->nu_air, d->s_sigma, d->s_nu, d->s_kl, d->k1, d->k2, d->k3, d->s_k};
   std::memcpy(p->mat, m, sizeof(m));
@@ -619,6 +625,29 @@ int mq_problem_destroy(mq_problem* p) {
 int mq_ndof(const mq_problem* p, int64_t* nd) {
   if (!p || !nd) return fail(MQ_ERR_INVALID_ARG, "null argument");
   *nd = (int64_t)p->hm.g.n * p->hm.g.n;
+  return MQ_OK;
+}
+
+int mq_set_initial_state(mq_problem* p, const double* a0) {
+  if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
+  if (!a0) {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->a0.reset();
+    return MQ_OK;
+  }
+  const Geom& g = p->hm.g;
+  const size_t nd = (size_t)g.n * g.n, FS = (size_t)g.N * g.P;
+  int rc = check_finite(p, a0, nd);
+  if (rc == MQ_ERR_NONFINITE) return fail(rc, "a0 contains NaN or Inf");
+  if (rc) return rc;
+  if (!p->a0) HIP_TRY(dev_alloc(p->a0, FS));
+  HIP_TRY(launch_fill_zero(p->a0.get(), FS, p->stream));
+  TmpPtr<double*> dptr;
+  HIP_TRY(tmp_alloc(dptr, 1, p->stream));
+  double* full = p->a0.get();
+  HIP_TRY(copy_sync(dptr.get(), &full, sizeof(double*), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(launch_to_full(g, 1, a0, dptr.get(), p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
   return MQ_OK;
 }
 
@@ -934,6 +963,9 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
   auto U = [&](int s, int nn) { return states.get() + per * s + (size_t)nn * FS; };             // nn = 0..M-1
   auto F = [&](int s, int nn) { return states.get() + per * s + (size_t)(M + nn - 1) * FS; };   // nn = 1..M
   auto C = [&](int s, int nn) { return states.get() + per * s + (size_t)(2 * M + nn - 1) * FS; };  // nn = 1..M-1
+  if (p->a0)  // U_0 = a_0 for every sample
+    for (int s = 0; s < S; ++s)
+      HIP_TRY(hipMemcpyAsync(U(s, 0), p->a0.get(), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   const int kcap = std::min(pd->fixed_k > 0 ? pd->fixed_k : pd->k_max, M);
   RunOut ro;
   std::vector<int> active(S);
@@ -1124,6 +1156,15 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     }
     p->twin = tw;
     p->twin_stream = ts;
+  }
+  // the Parareal part starts from the same a_0 as the batched part
+  if (p->a0) {
+    const size_t FS = (size_t)p->hm.g.N * p->hm.g.P;
+    if (!p->twin->a0) HIP_TRY(dev_alloc(p->twin->a0, FS));
+    HIP_TRY(copy_sync(p->twin->a0.get(), p->a0.get(), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  } else if (p->twin->a0) {
+    HIP_TRY(hipStreamSynchronize(p->twin_stream));
+    p->twin->a0.reset();
   }
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));

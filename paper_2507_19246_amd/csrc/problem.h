@@ -105,6 +105,9 @@ struct mq_problem {
   // upper bound on the persistent grid (0: the device's slots); set while a
   // combined run keeps slots free for its Parareal part
   int grid_cap = 0;
+  // start state a_0 of later runs on the full grid (zero boundary ring), set by
+  // mq_set_initial_state; empty: a_0 = 0
+  mq::DevPtr<double> a0;
   // second set-up of the same problem on a stream of its own (combined runs)
   mq_problem* twin = nullptr;
   hipStream_t twin_stream = nullptr;

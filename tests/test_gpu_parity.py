@@ -243,6 +243,91 @@ def test_empty_and_malformed_inputs_rejected():
     p.close()
 
 
+def test_initial_state_eigenmode_and_oracle():
+    """mq_set_initial_state.  Homogeneous square, no source, a_0 a generalised
+    eigenvector v of (K, M): implicit Euler (Eq. (7)) gives a_n = (1 + lam dt)^-n v,
+    and Eq. (26) the loss from the scalar increments (v^T M v = 1).  With the KL
+    material and the source on, a seeded random a_0 gives the oracle's Q (fine and
+    coupled coarse) and final state, Parareal at K = M from U_0 = a_0 gives the
+    serial fine run, and None restores a_0 = 0."""
+    import scipy.linalg as sl
+    mq, L = mqmod()
+    hom = W.Problem(9, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0.0, 1.0, 0.0, 1.0), J0=0.0)
+    s = ots.build_system(hom, np.zeros(2))
+    lam, V = sl.eigh(s.K.toarray(), s.M.toarray())
+    p = mq.Problem(hom, L.MQ_PREC_FP64)
+    spp, nper = 4, 2
+    nst, dt = spp * nper, hom.period / spp
+    for k in (0, 7, 30):
+        say(f"initial state: eigenmode {k}, lam dt = {lam[k] * dt:.3e}")
+        p.set_initial_state(V[:, k])
+        qf, _, fs, rc, _ = mq.mlmc_level_run(p, spp, 0, nper, np.zeros((1, 2)), want_state=True)
+        assert rc == 0
+        c = (1.0 + lam[k] * dt) ** -np.arange(nst + 1.0)
+        ref = c[-1] * V[:, k]
+        a = fs[0].cpu().numpy()
+        assert np.linalg.norm(a - ref) <= 1e-10 * np.linalg.norm(ref)
+        qref = np.sum(np.diff(c) ** 2) / dt / (nst * dt)
+        assert float(qf[0]) == pytest.approx(qref, rel=1e-10)
+    p.close()
+
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    m = omesh.build(17)
+    tab = ots.kl_table_for(prob, m)
+    xi = W.normals(0, 37, 0, range(3), 8)
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    _, a_scale = ots.solve_sample(prob, xi[0], 16, 1, m=m, kl_table=tab)
+    a0 = np.random.default_rng(11).standard_normal(p.n_dof) * np.abs(a_scale).max()
+    say("initial state: random a_0, KL material, level run and Parareal")
+    p.set_initial_state(a0)
+    qf, qc, fs, rc, _ = mq.mlmc_level_run(p, 16, 8, 1, xi, want_state=True)
+    qp, it, fsp, rcp, _ = mq.parareal_run(p, 1, 4, 4, 1, 4, 0.0, xi, fixed_k=4, want_state=True)
+    assert rc == 0 and rcp == 0
+    for i in range(3):
+        qref, aref = ots.solve_sample(prob, xi[i], 16, 1, a0=a0, m=m, kl_table=tab)
+        qcref, _ = ots.solve_sample(prob, xi[i], 8, 1, a0=a0, m=m, kl_table=tab)
+        assert float(qf[i]) == pytest.approx(qref, rel=1e-10)
+        assert float(qc[i]) == pytest.approx(qcref, rel=1e-10)
+        assert np.linalg.norm(fs[i].cpu().numpy() - aref) <= 1e-10 * np.linalg.norm(aref)
+        assert float(qp[i]) == pytest.approx(qref, rel=1e-10)
+        assert np.linalg.norm(fsp[i].cpu().numpy() - aref) <= 1e-10 * np.linalg.norm(aref)
+    # a rejected a_0 keeps the previous one; None restores zeros
+    bad = a0.copy()
+    bad[5] = np.inf
+    with pytest.raises(L.MQError) as e:
+        p.set_initial_state(bad)
+    assert e.value.code == L.MQ_ERR_NONFINITE
+    qf2, _, _, _, _ = mq.mlmc_level_run(p, 16, 0, 1, xi[:1])
+    assert float(qf2[0]) == float(qf[0])
+    p.set_initial_state(None)
+    qf0, _, _, _, _ = mq.mlmc_level_run(p, 16, 0, 1, xi[:1])
+    q0ref, _ = ots.solve_sample(prob, xi[0], 16, 1, m=m, kl_table=tab)
+    assert float(qf0[0]) == pytest.approx(q0ref, rel=1e-10)
+    p.close()
+
+
+def test_nine_node_mesh_preconditioners():
+    """The 9-node mesh runs Jacobi-CG on the resident path (its resident multigrid
+    is switched off) and multigrid on the streaming path; both give the oracle's
+    Q in FP64, and an explicit resident multigrid request is refused."""
+    mq, L = mqmod()
+    prob = W.Problem(9, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 41, 0, range(3), 8)
+    qref, aref = oracle_q(prob, xi, 8, 1)
+    for path, pc in ((L.MQ_PATH_AUTO, L.MQ_PRECOND_JACOBI), (L.MQ_PATH_STREAMING, L.MQ_PRECOND_MULTIGRID)):
+        say(f"9-node mesh path={path}")
+        p = mq.Problem(prob, L.MQ_PREC_FP64, path=path)
+        assert p.info.precond == pc
+        qf, _, fs, rc, _ = mq.mlmc_level_run(p, 8, 0, 1, xi, want_state=True)
+        assert rc == 0
+        assert np.max(np.abs(qf.cpu().numpy() - qref) / np.abs(qref)) <= 1e-10
+        assert np.linalg.norm(fs.cpu().numpy() - aref) <= 1e-10 * np.linalg.norm(aref)
+        p.close()
+    with pytest.raises(L.MQError) as e:
+        mq.Problem(prob, L.MQ_PREC_FP64, path=L.MQ_PATH_RESIDENT, precond=L.MQ_PRECOND_MULTIGRID)
+    assert e.value.code == L.MQ_ERR_INVALID_ARG
+
+
 def test_single_dof_mesh():
     mq, L = mqmod()
     prob = W.Problem(3, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0, 1, 0, 1), strip=(0, 1))
