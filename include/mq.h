@@ -22,8 +22,9 @@
  *    last non-zero status of the calling thread.  No C++ exception crosses the
  *    boundary.
  *  - Array arguments marked "device" are HIP device pointers on the device that
- *    was current at fem_setup / mq_server_create; arrays marked "host" are host
- *    pointers.  The caller owns every array; the library owns its handles and
+ *    was current at fem_setup / mq_server_create (or host pointers on a handle
+ *    set up with mem_kind = MQ_MEM_HOST, see mq_problem_desc); arrays marked
+ *    "host" are host pointers.  The caller owns every array; the library owns its handles and
  *    the device memory it allocates, and frees both in the *_destroy calls.
  *  - `stream` arguments are hipStream_t passed as void* (NULL: default stream).
  *    Compute calls run on the problem's stream and return after the stream
@@ -73,6 +74,8 @@ enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2, MQ_PATH_WI
  * diagonal scaling; MULTIGRID is a geometric V(1,1)-cycle with damped-Jacobi
  * smoothing and Galerkin coarse operators (resident path, n_nodes = 2^k + 1) */
 enum { MQ_PRECOND_AUTO = 0, MQ_PRECOND_JACOBI = 1, MQ_PRECOND_MULTIGRID = 2 };
+/* where the array arguments of a handle's calls live (mq_problem_desc.mem_kind) */
+enum { MQ_MEM_DEVICE = 0, MQ_MEM_HOST = 1 };
 
 /* Problem description (Section II-A; materials per the workload).
  * Unit square, n_nodes x n_nodes nodes, each cell split along "/" into two P1
@@ -125,6 +128,12 @@ typedef struct mq_problem_desc {
                            the unsplit run).  0: 32; -1: never. */
   int32_t mg_block_min; /* multigrid coarse levels with at least this many interior nodes per side
                            run on the whole workgroup, smaller ones on one wavefront (0: 15) */
+  int32_t mem_kind;     /* MQ_MEM_DEVICE (0): array arguments are device pointers.  MQ_MEM_HOST:
+                           the arrays of mq_set_initial_state, mlmc_level_run, mlmc_multilevel_run
+                           and parareal_run are host pointers, staged through device copies
+                           (the call blocks; the rate includes the transfers); the handle's other
+                           calls return MQ_ERR_INVALID_ARG.  Servers built on such a description
+                           still take device memory only internally (requests carry xi inline). */
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;

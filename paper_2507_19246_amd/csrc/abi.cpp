@@ -117,6 +117,7 @@ int validate_desc(const mq_problem_desc* d) {
   if (d->precision != MQ_PREC_FP64 && d->precision != MQ_PREC_MIXED)
     return fail(MQ_ERR_INVALID_ARG, "unknown precision");
   if (d->path < 0 || d->path > 3) return fail(MQ_ERR_INVALID_ARG, "unknown path");
+  if (d->mem_kind != MQ_MEM_DEVICE && d->mem_kind != MQ_MEM_HOST) return fail(MQ_ERR_INVALID_ARG, "unknown mem_kind");
   if (!(d->conductor[0] < d->conductor[1]) || !(d->conductor[2] < d->conductor[3]))
     return fail(MQ_ERR_INVALID_ARG, "empty conductor box");
   if (!(d->strip[0] <= d->strip[1])) return fail(MQ_ERR_INVALID_ARG, "bad strip");
@@ -521,6 +522,15 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
   return MQ_OK;
 }
 
+// Handles set up with mem_kind = MQ_MEM_HOST take host arrays in the staged calls.
+bool host_mode(const mq_problem* p) { return p && p->d.mem_kind == MQ_MEM_HOST; }
+
+int refuse_host(const mq_problem* p) {
+  if (host_mode(p))
+    return fail(MQ_ERR_INVALID_ARG, "this call takes device pointers (the handle was set up with mem_kind = MQ_MEM_HOST)");
+  return MQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -628,7 +638,7 @@ int mq_ndof(const mq_problem* p, int64_t* nd) {
   return MQ_OK;
 }
 
-int mq_set_initial_state(mq_problem* p, const double* a0) {
+static int set_initial_state_dev(mq_problem* p, const double* a0) {
   if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
   if (!a0) {
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -675,8 +685,8 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   return MQ_OK;
 }
 
-int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
-                   double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                         double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
   if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
@@ -700,9 +710,9 @@ int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, co
   return ro.status;
 }
 
-int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
-                        const int32_t* n_samples, const double* const* xi, double* const* q_fine,
-                        double* const* q_coarse, mq_run_stats* st) {
+static int multilevel_run_dev(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
+                              const int32_t* n_samples, const double* const* xi, double* const* q_fine,
+                              double* const* q_coarse, mq_run_stats* st) {
   if (!p || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
   const double t0 = now_ms();
@@ -732,6 +742,7 @@ int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv
 int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_max,
                       const double* const* xi, double* const* q_fine, double* const* q_coarse,
                       const mq_adaptive_desc* ad, int32_t* n_used, double* out, mq_run_stats* st) {
+  if (int rh = refuse_host(p)) return rh;
   if (!p || !lv || !n_max || !xi || !q_fine || !q_coarse || !ad || !n_used || !out)
     return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
@@ -778,7 +789,7 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     }
     if (!lvs.empty()) {
       mq_run_stats s{};
-      const int rc = mlmc_multilevel_run(p, (int32_t)lvs.size(), lvs.data(), ns.data(), xs.data(), qf.data(),
+      const int rc = multilevel_run_dev(p, (int32_t)lvs.size(), lvs.data(), ns.data(), xs.data(), qf.data(),
                                          qc.data(), &s);
       if (rc < 0) return rc;
       if (rc > 0) status = rc;
@@ -839,6 +850,8 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
                        double* const* q_coarse, mq_run_stats* st) {
   if (!problems || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 1 || n_levels > 16) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 16]");
+  for (int m = 0; m < n_levels; ++m)
+    if (int rh = refuse_host(problems[m])) return rh;
   const int L = n_levels;
   for (int l = 0; l < L; ++l) {
     mq_problem* p = problems[l];
@@ -924,8 +937,8 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
   return status;
 }
 
-int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
-                 double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
+static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
+                            double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
   if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "Parareal runs on the resident or streaming path");
   if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
@@ -1112,6 +1125,7 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
 int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_samples,
                       const double* const* xi, const mq_combined_desc* cd, double* const* q_fine,
                       double* const* q_coarse, int32_t* para_iters, mq_run_stats* st, mq_combined_stats* cs) {
+  if (int rh = refuse_host(p)) return rh;
   if (!p || !lv || !n_samples || !xi || !cd || !q_fine || !q_coarse || !para_iters)
     return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 2 || n_levels > 16) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [2, 16]");
@@ -1217,7 +1231,7 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
   });
   const double tb0 = now_ms();
   const mq_parareal_desc pd{nper, M, (int32_t)(fine_total / M), (int32_t)(coarse_total / M), kmax, 0, cd->tol};
-  const int rcb = parareal_run(p->twin, &pd, n_samples[L], xi[L], q_fine[L], para_iters, nullptr, &sb);
+  const int rcb = parareal_run_dev(p->twin, &pd, n_samples[L], xi[L], q_fine[L], para_iters, nullptr, &sb);
   const std::string errb = rcb < 0 ? last_error() : std::string();
   const double ms_b = now_ms() - tb0;
   ta.join();
@@ -1327,6 +1341,7 @@ int mq_plan_split(int32_t n, const int32_t* steps, int32_t slots, int32_t split_
 
 int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const double* xi,
                    const double* x, double* y) {
+  if (int rh = refuse_host(p)) return rh;
   if (!p || !xi || !x || !y) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (which < 0 || which > 2 || n < 1 || !(dt > 0)) return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
   int rc = check_finite(p, xi, (size_t)n * p->n_xi);
@@ -1337,6 +1352,99 @@ int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const dou
   HIP_TRY(launch_apply(p->hm.g, which, dt, tables.get(), n, x, y, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return MQ_OK;
+}
+
+// ---- host-pointer forms (mem_kind = MQ_MEM_HOST): inputs copied to per-call
+// device buffers, the device form run, outputs copied back; blocking ----
+
+int mq_set_initial_state(mq_problem* p, const double* a0) {
+  if (!host_mode(p) || !a0) return set_initial_state_dev(p, a0);
+  const size_t nd = (size_t)p->hm.g.n * p->hm.g.n;
+  TmpPtr<double> d;
+  HIP_TRY(tmp_alloc(d, nd, p->stream));
+  HIP_TRY(copy_sync(d.get(), a0, nd * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  return set_initial_state_dev(p, d.get());
+}
+
+int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                   double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+  if (!host_mode(p)) return level_run_dev(p, lv, n_samples, xi, q_fine, q_coarse, final_state, st);
+  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  if (!xi || !q_fine) return fail(MQ_ERR_INVALID_ARG, "xi and q_fine are required");
+  const size_t n = (size_t)n_samples, nd = (size_t)p->hm.g.n * p->hm.g.n;
+  TmpPtr<double> dxi, dqf, dqc, dfs;
+  HIP_TRY(tmp_alloc(dxi, n * p->n_xi, p->stream));
+  HIP_TRY(copy_sync(dxi.get(), xi, n * p->n_xi * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(tmp_alloc(dqf, n, p->stream));
+  if (q_coarse) HIP_TRY(tmp_alloc(dqc, n, p->stream));
+  if (final_state) HIP_TRY(tmp_alloc(dfs, n * nd, p->stream));
+  const int rc = level_run_dev(p, lv, n_samples, dxi.get(), dqf.get(), q_coarse ? dqc.get() : nullptr,
+                               final_state ? dfs.get() : nullptr, st);
+  if (rc < 0) return rc;
+  HIP_TRY(hipMemcpyAsync(q_fine, dqf.get(), n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  if (q_coarse) HIP_TRY(hipMemcpyAsync(q_coarse, dqc.get(), n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  if (final_state)
+    HIP_TRY(hipMemcpyAsync(final_state, dfs.get(), n * nd * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return rc;
+}
+
+int mlmc_multilevel_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
+                        const int32_t* n_samples, const double* const* xi, double* const* q_fine,
+                        double* const* q_coarse, mq_run_stats* st) {
+  if (!host_mode(p)) return multilevel_run_dev(p, n_levels, lv, n_samples, xi, q_fine, q_coarse, st);
+  if (!lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
+  std::vector<TmpPtr<double>> dxi(n_levels), dqf(n_levels), dqc(n_levels);
+  std::vector<const double*> px(n_levels);
+  std::vector<double*> pf(n_levels), pc(n_levels, nullptr);
+  for (int l = 0; l < n_levels; ++l) {
+    if (n_samples[l] < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+    if (!xi[l] || !q_fine[l]) return fail(MQ_ERR_INVALID_ARG, "xi and q_fine are required");
+    const size_t n = (size_t)n_samples[l];
+    HIP_TRY(tmp_alloc(dxi[l], n * p->n_xi, p->stream));
+    HIP_TRY(copy_sync(dxi[l].get(), xi[l], n * p->n_xi * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(tmp_alloc(dqf[l], n, p->stream));
+    px[l] = dxi[l].get();
+    pf[l] = dqf[l].get();
+    if (q_coarse[l]) {
+      HIP_TRY(tmp_alloc(dqc[l], n, p->stream));
+      pc[l] = dqc[l].get();
+    }
+  }
+  const int rc = multilevel_run_dev(p, n_levels, lv, n_samples, px.data(), pf.data(), pc.data(), st);
+  if (rc < 0) return rc;
+  for (int l = 0; l < n_levels; ++l) {
+    const size_t b = (size_t)n_samples[l] * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(q_fine[l], pf[l], b, hipMemcpyDeviceToHost, p->stream));
+    if (pc[l]) HIP_TRY(hipMemcpyAsync(q_coarse[l], pc[l], b, hipMemcpyDeviceToHost, p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return rc;
+}
+
+int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
+                 double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
+  if (!host_mode(p)) return parareal_run_dev(p, pd, n_samples, xi, q, iters, final_state, st);
+  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
+  const size_t n = (size_t)n_samples, nd = (size_t)p->hm.g.n * p->hm.g.n;
+  TmpPtr<double> dxi, dq, dfs;
+  TmpPtr<int32_t> dit;
+  HIP_TRY(tmp_alloc(dxi, n * p->n_xi, p->stream));
+  HIP_TRY(copy_sync(dxi.get(), xi, n * p->n_xi * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(tmp_alloc(dq, n, p->stream));
+  HIP_TRY(tmp_alloc(dit, n, p->stream));
+  if (final_state) HIP_TRY(tmp_alloc(dfs, n * nd, p->stream));
+  const int rc = parareal_run_dev(p, pd, n_samples, dxi.get(), dq.get(), dit.get(),
+                                  final_state ? dfs.get() : nullptr, st);
+  if (rc < 0) return rc;
+  HIP_TRY(hipMemcpyAsync(q, dq.get(), n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(iters, dit.get(), n * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  if (final_state)
+    HIP_TRY(hipMemcpyAsync(final_state, dfs.get(), n * nd * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return rc;
 }
 
 }  // extern "C"

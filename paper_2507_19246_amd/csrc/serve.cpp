@@ -209,6 +209,7 @@ int make_class(mq_server* s, int n_nodes, std::unique_ptr<Class>* out) {
   auto c = std::make_unique<Class>();
   c->n_nodes = n_nodes;
   mq_problem_desc d = s->sd.base;
+  d.mem_kind = MQ_MEM_DEVICE;  // the server passes device buffers
   d.n_nodes = n_nodes;
   int64_t bytes = 0;
   for (int l = 0; l < s->lanes; ++l) {
@@ -453,6 +454,7 @@ void wide_worker(mq_server* s) {
       int rc = MQ_OK;
       if (!p) {
         mq_problem_desc d = s->sd.base;
+        d.mem_kind = MQ_MEM_DEVICE;  // the server passes device buffers
         d.n_nodes = r->rq.n_nodes;
         d.path = MQ_PATH_WIDE;
         rc = fem_setup(&d, (void*)st, &p);
@@ -648,6 +650,7 @@ int mq_server_create(const mq_server_desc* sd, void* stream, mq_server** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MQ_ERR_NO_DEVICE, "no HIP device");
   // validate the base description once on a tiny mesh
   mq_problem_desc d = sd->base;
+  d.mem_kind = MQ_MEM_DEVICE;
   d.n_nodes = 5;
   mq_problem* probe = nullptr;
   int rc = fem_setup(&d, nullptr, &probe);

@@ -328,6 +328,74 @@ def test_nine_node_mesh_preconditioners():
     assert e.value.code == L.MQ_ERR_INVALID_ARG
 
 
+def test_host_pointer_handle_matches_device_handle():
+    """mem_kind = MQ_MEM_HOST: initial state, level run, multilevel run and
+    Parareal take host arrays through the C ABI and give the device handle's
+    results bit for bit; the calls without a host form refuse such a handle."""
+    import ctypes as C
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = np.ascontiguousarray(W.normals(0, 43, 0, range(4), 8), dtype=np.float64)
+    pdv = mq.Problem(prob, L.MQ_PREC_MIXED)
+    ph = mq.Problem(prob, L.MQ_PREC_MIXED, mem_kind=L.MQ_MEM_HOST)
+    lib = ph.lib
+
+    def P(a):
+        return a.ctypes.data_as(C.c_void_p)
+
+    say("host handle: initial state + level run")
+    a0 = np.ascontiguousarray(np.random.default_rng(5).standard_normal(ph.n_dof) * 1e-4)
+    pdv.set_initial_state(a0)
+    assert lib.mq_set_initial_state(ph.h, P(a0)) == 0
+    qf_d, qc_d, fs_d, rc_d, _ = mq.mlmc_level_run(pdv, 16, 8, 1, xi, want_state=True)
+    qf, qc, fs = np.zeros(4), np.zeros(4), np.zeros((4, ph.n_dof))
+    lv = L.LevelDesc(16, 8, 1, 0)
+    st = L.RunStats()
+    rc = lib.mlmc_level_run(ph.h, C.byref(lv), 4, P(xi), P(qf), P(qc), P(fs), C.byref(st))
+    assert rc == rc_d == 0
+    np.testing.assert_array_equal(qf, qf_d.cpu().numpy())
+    np.testing.assert_array_equal(qc, qc_d.cpu().numpy())
+    np.testing.assert_array_equal(fs, fs_d.cpu().numpy())
+    pdv.set_initial_state(None)
+    assert lib.mq_set_initial_state(ph.h, None) == 0
+
+    say("host handle: multilevel run")
+    levels = [(8, 0, 1), (16, 8, 1)]
+    xs = [xi[:3].copy(), xi[1:].copy()]
+    qfs_d, qcs_d, rcm_d, _ = mq.mlmc_multilevel_run(pdv, levels, xs)
+    lvs = (L.LevelDesc * 2)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    ns = (C.c_int32 * 2)(3, 3)
+    qfh = [np.zeros(3), np.zeros(3)]
+    qch = [None, np.zeros(3)]
+    px = (C.c_void_p * 2)(*[x.ctypes.data for x in xs])
+    pf = (C.c_void_p * 2)(*[q.ctypes.data for q in qfh])
+    pc = (C.c_void_p * 2)(None, qch[1].ctypes.data)
+    assert lib.mlmc_multilevel_run(ph.h, 2, lvs, ns, px, pf, pc, C.byref(st)) == rcm_d == 0
+    for l in range(2):
+        np.testing.assert_array_equal(qfh[l], qfs_d[l].cpu().numpy())
+    np.testing.assert_array_equal(qch[1], qcs_d[1].cpu().numpy())
+
+    say("host handle: Parareal")
+    qp_d, it_d, fsp_d, rcp_d, _ = mq.parareal_run(pdv, 1, 4, 4, 1, 4, 1e-6, xi, want_state=True)
+    qp, itp, fsp = np.zeros(4), np.zeros(4, dtype=np.int32), np.zeros((4, ph.n_dof))
+    pd = L.PararealDesc(1, 4, 4, 1, 4, 0, 1e-6)
+    rcp = lib.parareal_run(ph.h, C.byref(pd), 4, P(xi), P(qp), P(itp), P(fsp), C.byref(st))
+    assert rcp == rcp_d
+    np.testing.assert_array_equal(qp, qp_d.cpu().numpy())
+    np.testing.assert_array_equal(itp, it_d.cpu().numpy())
+    np.testing.assert_array_equal(fsp, fsp_d.cpu().numpy())
+
+    say("host handle: calls without a host form")
+    with pytest.raises(L.MQError) as e:
+        mq.debug_apply(ph, 0, 1e-3, xi[:1], np.zeros((1, ph.n_dof)))
+    assert e.value.code == L.MQ_ERR_INVALID_ARG
+    with pytest.raises(L.MQError) as e:
+        mq.mlmc_combined_run(ph, [(8, 0, 1), (16, 8, 1)], xs)
+    assert e.value.code == L.MQ_ERR_INVALID_ARG
+    pdv.close()
+    ph.close()
+
+
 def test_single_dof_mesh():
     mq, L = mqmod()
     prob = W.Problem(3, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0, 1, 0, 1), strip=(0, 1))
