@@ -96,6 +96,40 @@ def _oracle_task(args):
     return q, spp * nper, time.perf_counter() - t
 
 
+def host_buffer_rate(w, levels, xis_np, knobs, L, qfs_dev, qcs_dev):
+    """One multilevel run of the same workload through a host-pointer handle
+    (mem_kind = MQ_MEM_HOST): xi goes in and Q comes out over PCIe inside the
+    timed call.  Results must equal the device-resident run's bit for bit."""
+    import ctypes as C
+    import numpy as np
+    from paper_2507_19246_amd import autotune
+    ph, _ = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED, **dict(knobs, mem_kind=L.MQ_MEM_HOST))
+    nl = len(levels)
+    lvs = (L.LevelDesc * nl)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    xs = [np.ascontiguousarray(x, dtype=np.float64) for x in xis_np]
+    ns = (C.c_int32 * nl)(*[x.shape[0] for x in xs])
+    qf = [np.zeros(x.shape[0]) for x in xs]
+    qc = [np.zeros(x.shape[0]) if levels[l][1] > 0 else None for l, x in enumerate(xs)]
+    px = (C.c_void_p * nl)(*[x.ctypes.data for x in xs])
+    pf = (C.c_void_p * nl)(*[q.ctypes.data for q in qf])
+    pc = (C.c_void_p * nl)(*[(q.ctypes.data if q is not None else None) for q in qc])
+    st = L.RunStats()
+    t0 = time.perf_counter()
+    rc = ph.lib.mlmc_multilevel_run(ph.h, nl, lvs, ns, px, pf, pc, C.byref(st))
+    wall = time.perf_counter() - t0
+    ph.close()
+    if rc < 0:
+        return {"error": rc}
+    same = all(np.array_equal(qf[l], qfs_dev[l].cpu().numpy()) for l in range(nl)) and all(
+        qc[l] is None or np.array_equal(qc[l], qcs_dev[l].cpu().numpy()) for l in range(nl))
+    in_b = sum(x.nbytes for x in xs)
+    out_b = sum(q.nbytes for q in qf) + sum(q.nbytes for q in qc if q is not None)
+    return {"value": st.sample_steps / wall, "unit": "sample-steps/s", "steps": 1,
+            "bytes_in": in_b, "bytes_out": out_b, "equal_to_device_run": bool(same),
+            "note": "multilevel run through a host-pointer handle (xi in, Q out over PCIe, blocking); "
+                    "the estimator is not part of it"}
+
+
 def cpu_baseline(w, xis, n_per_level=(12, 4, 2)):
     """Time the FP64 oracle on a bounded sample of the same workload."""
     import multiprocessing as mp
@@ -504,6 +538,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-host-buffers", action="store_true",
+                    help="skip the PCIe-inclusive run through a host-pointer handle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--workload", default="mlmc3",
@@ -587,6 +623,7 @@ def main():
     qfs, qcs, e, y, v, rc, st = out
     sample_steps = sum(s["sample_steps"] for s in stats)
     value = sample_steps / elapsed
+    pcie = None if args.no_host_buffers else host_buffer_rate(w, levels, xis_np, knobs, L, qfs, qcs)
     kern_ms = [s["kernel_ms"] for s in stats]
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     units = nd * (sum(s["inner_iters"] for s in stats) / len(stats))   # DoF-iterations per launch
@@ -672,6 +709,7 @@ def main():
                      "dof_iters_per_launch": units,
                      "hbm_equivalent_gbs": CG_BYTES_PER_DOF_ITER_FP32 * units / avg_kern_s / 1e9},
         "cpu_baseline": cpu,
+        "pcie_inclusive": pcie,
     }
     res.update(result)
     if fp64:
