@@ -76,6 +76,10 @@ enum { MQ_PATH_AUTO = 0, MQ_PATH_RESIDENT = 1, MQ_PATH_STREAMING = 2, MQ_PATH_WI
 enum { MQ_PRECOND_AUTO = 0, MQ_PRECOND_JACOBI = 1, MQ_PRECOND_MULTIGRID = 2 };
 /* where the array arguments of a handle's calls live (mq_problem_desc.mem_kind) */
 enum { MQ_MEM_DEVICE = 0, MQ_MEM_HOST = 1 };
+/* mass matrix (mq_problem_desc.mass): the consistent P1 matrix of Eq. (4), or its
+ * row-sum lumped diagonal (a test option: with it a sampled sine mode of the
+ * homogeneous square is an eigenvector with a closed-form eigenvalue) */
+enum { MQ_MASS_CONSISTENT = 0, MQ_MASS_LUMPED = 1 };
 
 /* Problem description (Section II-A; materials per the workload).
  * Unit square, n_nodes x n_nodes nodes, each cell split along "/" into two P1
@@ -134,6 +138,7 @@ typedef struct mq_problem_desc {
                            (the call blocks; the rate includes the transfers); the handle's other
                            calls return MQ_ERR_INVALID_ARG.  Servers built on such a description
                            still take device memory only internally (requests carry xi inline). */
+  int32_t mass;         /* MQ_MASS_CONSISTENT (0) or MQ_MASS_LUMPED */
 } mq_problem_desc;
 
 typedef struct mq_problem mq_problem;

@@ -27,6 +27,7 @@ MQ_APPLY_A, MQ_APPLY_M, MQ_APPLY_K = 0, 1, 2
 MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING, MQ_PATH_WIDE = 0, 1, 2, 3
 MQ_PRECOND_AUTO, MQ_PRECOND_JACOBI, MQ_PRECOND_MULTIGRID = 0, 1, 2
 MQ_MEM_DEVICE, MQ_MEM_HOST = 0, 1
+MQ_MASS_CONSISTENT, MQ_MASS_LUMPED = 0, 1
 
 
 class ProblemDesc(C.Structure):
@@ -45,6 +46,7 @@ class ProblemDesc(C.Structure):
         ("precond", C.c_int32), ("tile", C.c_int32), ("mg_omega", C.c_double),
         ("mg_levels", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
         ("split_steps", C.c_int32), ("mg_block_min", C.c_int32), ("mem_kind", C.c_int32),
+        ("mass", C.c_int32),
     ]
 
 

@@ -45,6 +45,7 @@ def default_desc(problem, precision: int, path: int = L.MQ_PATH_AUTO, **solver) 
     d.mg_block_min = sv.get("mg_block_min", 0)
     d.mg_omega = sv.get("mg_omega", 0.0)
     d.mem_kind = sv.get("mem_kind", L.MQ_MEM_DEVICE)
+    d.mass = sv.get("mass", L.MQ_MASS_CONSISTENT)
     return d
 
 

@@ -118,6 +118,7 @@ int validate_desc(const mq_problem_desc* d) {
     return fail(MQ_ERR_INVALID_ARG, "unknown precision");
   if (d->path < 0 || d->path > 3) return fail(MQ_ERR_INVALID_ARG, "unknown path");
   if (d->mem_kind != MQ_MEM_DEVICE && d->mem_kind != MQ_MEM_HOST) return fail(MQ_ERR_INVALID_ARG, "unknown mem_kind");
+  if (d->mass != MQ_MASS_CONSISTENT && d->mass != MQ_MASS_LUMPED) return fail(MQ_ERR_INVALID_ARG, "unknown mass kind");
   if (!(d->conductor[0] < d->conductor[1]) || !(d->conductor[2] < d->conductor[3]))
     return fail(MQ_ERR_INVALID_ARG, "empty conductor box");
   if (!(d->strip[0] <= d->strip[1])) return fail(MQ_ERR_INVALID_ARG, "bad strip");
@@ -449,6 +450,7 @@ int assemble(mq_problem* p, const double* xi, int n, TmpPtr<double>& tables) {
   HIP_TRY(tmp_alloc(tables, (size_t)n * tab_stride(g), p->stream));
   HIP_TRY(launch_assemble(g, p->hm.cr, p->dcond.get(), p->dkl.get(), p->hm.n_modes, p->d.material, xi,
                           p->n_xi, n, p->mat, tables.get(), p->stream));
+  if (p->d.mass == MQ_MASS_LUMPED) HIP_TRY(launch_lump_mass(g, n, tables.get(), p->stream));
   return MQ_OK;
 }
 

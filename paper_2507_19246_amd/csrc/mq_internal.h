@@ -188,6 +188,8 @@ hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double
                               const double* const* qc, double* out, hipStream_t st);
 hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
                         const double* const* u, double* out2, hipStream_t st);
+// Row-sum lumping of the mass planes of n_samples tables (mass = MQ_MASS_LUMPED).
+hipError_t launch_lump_mass(const Geom& g, int n_samples, double* tables, hipStream_t st);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_i(int* p, size_t n, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* bad, hipStream_t st);

@@ -358,6 +358,7 @@ int launch_lane(mq_server* s, Class& c, Lane& L, const std::vector<Req*>& pick) 
       HIP_TRY(hipMemcpyAsync(xi, hx, sizeof(double) * s->n_xi, hipMemcpyHostToDevice, L.stream));
       HIP_TRY(launch_assemble(g, L.p->hm.cr, L.p->dcond.get(), L.p->dkl.get(), L.p->hm.n_modes, d.material, xi,
                               s->n_xi, 1, L.p->mat, tab, L.stream));
+      if (d.mass == MQ_MASS_LUMPED) HIP_TRY(launch_lump_mass(g, 1, tab, L.stream));
       HIP_TRY(launch_fill_zero(a, c.FS, L.stream));
       r->initialised = true;
     }

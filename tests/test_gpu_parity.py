@@ -396,6 +396,36 @@ def test_host_pointer_handle_matches_device_handle():
     ph.close()
 
 
+def test_lumped_mass_sine_mode_closed_form():
+    """Lumped-mass option on the homogeneous square, no source: the sampled sine
+    mode v = sin(p pi x) sin(q pi y) is an eigenvector, so implicit Euler (Eq. (7))
+    gives a_n = (1 + lam dt)^-n v with lam = nu (4 - 2 cos(p pi h) - 2 cos(q pi h)) /
+    (sigma h^2), and Eq. (26) the loss sigma h^2 |v|^2 sum_k (c_{k+1} - c_k)^2 / (dt T)."""
+    import math
+    mq, L = mqmod()
+    for n, path in ((17, L.MQ_PATH_AUTO), (33, L.MQ_PATH_STREAMING)):
+        hom = W.Problem(n, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0.0, 1.0, 0.0, 1.0), J0=0.0)
+        p = mq.Problem(hom, L.MQ_PREC_FP64, path=path, mass=L.MQ_MASS_LUMPED)
+        h = 1.0 / (n - 1)
+        x = np.arange(1, n - 1) * h
+        sig, nu = hom.material.sigma0, hom.material.nu_cond
+        spp, nper = 8, 2
+        nst, dt = spp * nper, hom.period / spp
+        for pq in ((1, 1), (2, 3), (n - 3, 1)):
+            say(f"lumped mass n={n} path={path} mode={pq}")
+            v = np.outer(np.sin(pq[1] * math.pi * x), np.sin(pq[0] * math.pi * x)).ravel()  # row j, column i
+            lam = nu * (4 - 2 * math.cos(pq[0] * math.pi * h) - 2 * math.cos(pq[1] * math.pi * h)) / (sig * h * h)
+            p.set_initial_state(v)
+            qf, _, fs, rc, _ = mq.mlmc_level_run(p, spp, 0, nper, np.zeros((1, 2)), want_state=True)
+            assert rc == 0
+            c = (1.0 + lam * dt) ** -np.arange(nst + 1.0)
+            a = fs[0].cpu().numpy()
+            assert np.linalg.norm(a - c[-1] * v) <= 1e-10 * np.linalg.norm(c[-1] * v)
+            qref = sig * h * h * float(v @ v) * np.sum(np.diff(c) ** 2) / dt / (nst * dt)
+            assert float(qf[0]) == pytest.approx(qref, rel=1e-10)
+        p.close()
+
+
 def test_single_dof_mesh():
     mq, L = mqmod()
     prob = W.Problem(3, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0, 1, 0, 1), strip=(0, 1))
