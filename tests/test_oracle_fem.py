@@ -190,3 +190,23 @@ def test_kl_field_variance_bounded():
     T = kl.table(m.centroid[cond], p.conductor, 0.2, 8)
     v = np.sum(T ** 2, axis=1)
     assert np.all(v <= 1.0 + 1e-12) and np.all(v > 0.2)
+
+
+def test_lumped_row_sum_is_twice_consistent_diagonal():
+    """Row-sum lumping of the boundary-inclusive P1 mass matrix (Eq. (4)) equals
+    twice its diagonal at every interior node, for a heterogeneous sigma (KL field
+    in the conductor, zero in air): the identity the library's lumped-mass option
+    rests on."""
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 47, 0, range(1), 8)[0]
+    s = timestep.build_system(prob, xi)
+    n = prob.n_nodes
+    lump = np.zeros(n * n)
+    for k in range(3):
+        np.add.at(lump, s.mesh.tri[:, k], s.sigma * s.mesh.area / 3.0)
+    inner = s.mesh.dof >= 0
+    row = np.zeros(s.mesh.n_dof)
+    row[s.mesh.dof[inner]] = lump[inner]
+    diag = s.M.diagonal()
+    assert np.max(np.abs(row - 2.0 * diag)) <= 1e-12 * np.max(np.abs(row))
+    assert np.max(row) > 0.0
