@@ -30,7 +30,7 @@ def lib():
 def test_header_declares_the_boundary():
     fns = header_functions()
     for name in ["fem_setup", "mlmc_level_run", "parareal_run", "mlmc_estimate", "mlmc_adaptive_run", "mq_debug_apply",
-                 "mlmc_combined_run", "mq_cost_model",
+                 "mlmc_combined_run", "mq_cost_model", "mq_set_initial_state",
                  "mq_server_create", "mq_submit", "mq_poll", "mq_server_destroy", "mq_last_error"]:
         assert name in fns
 
@@ -63,6 +63,8 @@ def test_struct_layout_matches_c(tmp_path):
     lines.append('printf("off_wide_queue %zu\\n", offsetof(mq_server_desc, wide_queue));')
     lines.append('printf("off_s_nc %zu\\n", offsetof(mq_cost_out, s_nc));')
     lines.append('printf("off_level_slots %zu\\n", offsetof(mq_combined_stats, level_slots));')
+    lines.append('printf("off_mem_kind %zu\\n", offsetof(mq_problem_desc, mem_kind));')
+    lines.append('printf("off_mass %zu\\n", offsetof(mq_problem_desc, mass));')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -78,6 +80,8 @@ def test_struct_layout_matches_c(tmp_path):
     assert int(out["off_wide_queue"]) == _lib.ServerDesc.wide_queue.offset
     assert int(out["off_s_nc"]) == _lib.CostOut.s_nc.offset
     assert int(out["off_level_slots"]) == _lib.CombinedStats.level_slots.offset
+    assert int(out["off_mem_kind"]) == _lib.ProblemDesc.mem_kind.offset
+    assert int(out["off_mass"]) == _lib.ProblemDesc.mass.offset
 
 
 def test_no_device_and_invalid_arguments(lib):
