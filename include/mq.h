@@ -115,7 +115,7 @@ typedef struct mq_problem_desc {
   double tol, inner_rtol;
   int32_t max_iter, max_sweeps;
   int32_t precond;   /* MQ_PRECOND_*: AUTO = multigrid where available (n_nodes = 2^k + 1; on the
-                        resident path if its LDS holds the hierarchy and n_nodes != 9), else Jacobi;
+                        resident path if its LDS holds the hierarchy), else Jacobi;
                         MULTIGRID where it is not available: MQ_ERR_INVALID_ARG */
   int32_t tile;      /* workgroup shape: 0 auto (the built-in default, 1).  Resident path: 1 = 16 rows
                         per thread, 2 = 32 rows per thread in 512-thread workgroups (meshes with

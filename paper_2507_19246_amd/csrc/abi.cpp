@@ -577,12 +577,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   const bool want_mg = d->precond != MQ_PRECOND_JACOBI;
   const int lp = resident_lp(g0, p->tile);
   MGGeom rmg{};
-  // the 9-node mesh (7 interior nodes, first coarse level 3 x 3) is left out of
-  // the resident multigrid: its FP64 solves diverged there (Q = inf) while 5-,
-  // 17- and 33-node meshes, mixed precision and the streaming multigrid on the
-  // same mesh agree with the reference; the cause is not found, so this mesh
-  // runs Jacobi-CG on the resident path (or multigrid on the streaming path)
-  const bool res_mg = want_mg && g0.n != 7 && lp > 0 && d->path != MQ_PATH_STREAMING && build_mg(g0, lp, &rmg) &&
+  const bool res_mg = want_mg && lp > 0 && d->path != MQ_PATH_STREAMING && build_mg(g0, lp, &rmg) &&
                       resident_supported(g0, &rmg, d->precision, p->lds_limit, nullptr, p->tile);
   p->resident_ok = resident_supported(g0, res_mg ? &rmg : nullptr, d->precision, p->lds_limit, &p->lds_bytes, p->tile);
   if (d->path == MQ_PATH_RESIDENT && !p->resident_ok)
@@ -604,7 +599,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   if (p->path == MQ_PATH_WIDE && p->mg.nlev < 1)
     return fail(MQ_ERR_INVALID_ARG, "the wide path needs n_nodes = 2^k + 1 (multigrid hierarchy)");
   if (d->precond == MQ_PRECOND_MULTIGRID && p->mg.nlev == 0)
-    return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS and n_nodes != 9)");
+    return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS)");
   p->precond = p->mg.nlev > 0 ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
   const double m[10] = {d->sigma0, d->nu_cond, d->nu_air, d->s_sigma, d->s_nu, d->s_kl, d->k1, d->k2, d->k3, d->s_k};
   std::memcpy(p->mat, m, sizeof(m));

@@ -609,11 +609,12 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   double* Av = work + (size_t)blockIdx.x * ie_work_doubles(g);
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
+  const size_t PS = res_plane_doubles(g);   // thread-private planes hold SH * NT <= PS elements
   VT* Yv = reinterpret_cast<VT*>(Bv + FS);   // multigrid CG iterate, thread-private [k][tid] layout
-  double* Pv = Bv + 2 * FS;                  // previous increment (extrapolated start)
+  double* Pv = Bv + FS + PS;                 // previous increment (extrapolated start)
   double* Qv = Pv + FS;                      // Picard: increment of the last fixed-point iterate
   VT* Dv = reinterpret_cast<VT*>(Qv + FS);   // per-node D^{-1/2}, thread-private [k][tid] layout
-  double* Tslot = Qv + 2 * FS;               // Picard: this instance's FP64 tables (K re-assembled)
+  double* Tslot = Qv + FS + PS;              // Picard: this instance's FP64 tables (K re-assembled)
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   int slot = 0;
 
@@ -1404,6 +1405,8 @@ static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, 
                              int* grid_out, int* block_out, hipStream_t st) {
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   constexpr int NT = CW * NS;
+  // the thread-private [row][thread] planes of the work slot must hold SH * NT elements
+  if ((size_t)SH * NT > res_plane_doubles(g)) return hipErrorInvalidValue;
   const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP}, MG ? &mg : nullptr);
   auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG, NL>;
   hipError_t e0 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

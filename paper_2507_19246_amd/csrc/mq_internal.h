@@ -38,12 +38,23 @@ struct Geom {
 // the sample's nonlinear curve coefficients k1', k2', k3' (and one pad).
 enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
 __host__ __device__ inline size_t tab_stride(const Geom& g) { return (size_t)T_NPLANES * g.RW * g.RH + 4; }
+// doubles of one thread-private [row][thread] plane of the resident kernel
+// (multigrid iterate, per-node D^{-1/2}): one element per (row, thread) of the
+// resident workgroup shapes for this mesh (16 x 64, 16 x 256, then 16 x 1024 =
+// 32 x 512 threads), and at least a full-grid plane.  On small meshes the
+// workgroup spans more (row, thread) pairs than the grid has nodes.
+__host__ __device__ inline size_t res_plane_doubles(const Geom& g) {
+  const size_t fs = (size_t)g.N * g.P;
+  const size_t rows_x_threads = g.n <= 31 ? 1024 : g.n <= 63 ? 4096 : 16384;
+  return fs > rows_x_threads ? fs : rows_x_threads;
+}
 // doubles per slot of the time-stepping work buffer: state a, increment x,
-// right-hand side b, one plane for the VT iterate, previous increment,
-// Picard increment, per-node D^{-1/2}, then the instance's FP64 tables
-// (planes + k1', k2', k3')
+// right-hand side b (full-grid planes), the VT iterate plane (thread-private),
+// previous increment, Picard increment (full-grid), the per-node D^{-1/2}
+// plane (thread-private), then the instance's FP64 tables (planes + k1', k2',
+// k3')
 __host__ __device__ inline size_t ie_work_doubles(const Geom& g) {
-  return 7 * (size_t)g.N * g.P + (size_t)T_NPLANES * g.RW * g.RH + 3;
+  return 5 * (size_t)g.N * g.P + 2 * res_plane_doubles(g) + (size_t)T_NPLANES * g.RW * g.RH + 3;
 }
 
 // Element data over the cells that touch the box: full-grid cells
