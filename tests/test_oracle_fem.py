@@ -210,3 +210,47 @@ def test_lumped_row_sum_is_twice_consistent_diagonal():
     diag = s.M.diagonal()
     assert np.max(np.abs(row - 2.0 * diag)) <= 1e-12 * np.max(np.abs(row))
     assert np.max(row) > 0.0
+
+
+def test_load_shape_column_strip_closed_form():
+    """Eq. (5), r_i = int J N_i: on an 11-node mesh (h = 0.1) the strip
+    [0.1, 0.2] holds exactly the cell column x in [0.1, 0.2].  A P1 hat function
+    of the "/" mesh integrates to h^2 and is point-symmetric about its node, so
+    half of it (h^2 / 2) lies on either side of the node's vertical line.  Hence
+    S_i = h^2 / 2 for interior nodes on x = 0.1 and x = 0.2, and 0 elsewhere."""
+    n = 11
+    p = W.Problem(n, strip=(0.1, 0.2))
+    m = mesh.build(n)
+    S = fem.load_shape(p, m)
+    h = 0.1
+    for j in range(1, n - 1):
+        for i in range(1, n - 1):
+            d = m.dof[j * n + i]
+            want = h * h / 2 if i in (1, 2) else 0.0
+            assert S[d] == pytest.approx(want, rel=1e-13, abs=1e-18), (i, j)
+
+
+def test_load_shape_by_point_quadrature():
+    """Eq. (5) by a route that never forms |T|/3: each strip triangle's basis
+    functions are evaluated at its three edge midpoints (barycentric coordinates
+    from a 3x3 solve against the vertex coordinates), weighted by area/3 (the
+    midpoint rule, exact for P1 integrands), and scattered to interior nodes."""
+    n = 17
+    p = W.Problem(n)
+    m = mesh.build(n)
+    strip = mesh.strip_mask(m, p)
+    ref = np.zeros(m.n_dof)
+    for e in np.where(strip)[0]:
+        P = m.xy[m.tri[e]]
+        V = np.vstack([np.ones(3), P.T])               # columns: (1, x, y) of each vertex
+        area = 0.5 * abs(np.linalg.det(V))
+        mids = 0.5 * (P + np.roll(P, -1, axis=0))
+        for q in mids:
+            bary = np.linalg.solve(V, np.array([1.0, q[0], q[1]]))   # N_a(q)
+            for a in range(3):
+                d = m.dof[m.tri[e][a]]
+                if d >= 0:
+                    ref[d] += area / 3.0 * bary[a]
+    S = fem.load_shape(p, m)
+    assert np.max(np.abs(S - ref)) <= 1e-15 * np.max(np.abs(ref))
+    assert np.count_nonzero(ref) == np.count_nonzero(S)

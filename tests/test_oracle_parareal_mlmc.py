@@ -252,3 +252,32 @@ def test_adaptive_mlmc_on_a_scalar_surrogate():
     n_true = mlmc.optimal_samples(v_true, C, eps)
     assert np.all(np.abs(n - n_true) <= 0.35 * n_true)
     assert abs(e - 1.0 * 0.25) <= 4.0 * np.sqrt(np.sum(v / n))  # E[Q_2] = E[x] + E[x^2] / 4
+
+
+@pytest.mark.parametrize("r,L,K", [(10.0, 2, 2), (4.0, 3, 3), (2.0, 2, 1)])
+def test_speedup_finite_with_one_batch_per_level(r, L, K):
+    """The finite-core speedup after Eq. (25): with so many cores that every level
+    runs in one batch (b_l = 1) and C_l = r^l, its bracket is Eq. (15)'s tau_para
+    with M = n_c,para slices, tau_F = C_L and tau_C = C_{L-2}, so
+    s = sum_l C_l / (sum_{l<L} C_l + tau_para)."""
+    C = cm.exp_cost(1.0, r, L)
+    N = [40, 12, 5, 3][: L + 1]
+    n_c = 10 * N[L] * 2 * 64
+    b = cm.batches(C, N, n_c)
+    assert b == [1] * (L + 1)
+    n_p = cm.cores_per_parareal_sample(C, N, n_c)
+    tp = cm.tau_para(K, n_p, C[L], C[L - 2])
+    want = sum(C) / (sum(C[:L]) + tp)
+    assert cm.speedup_finite(C, N, n_c, K, r) == pytest.approx(want, rel=1e-14)
+
+
+def test_speedup_finite_hand_value():
+    """Hand-computed case of the expression after Eq. (25): r = 10, L = 2,
+    C = (1, 10, 100), N = (100, 10, 2), n_c = 64, K = 2.  Eq. (24): b = (2, 1, 1);
+    Eq. (25): n_c,para = floor(64 / 2.2) = 29; numerator 2 + 10 + 100 = 112;
+    denominator 12 + (2/29)(100 + 27.5) = 603/29; s = 3248/603."""
+    C = [1.0, 10.0, 100.0]
+    N = [100, 10, 2]
+    assert cm.batches(C, N, 64) == [2, 1, 1]
+    assert cm.cores_per_parareal_sample(C, N, 64) == 29
+    assert cm.speedup_finite(C, N, 64, 2, 10.0) == pytest.approx(3248.0 / 603.0, rel=1e-14)

@@ -169,3 +169,48 @@ def test_picard_fixed_point_satisfies_nonlinear_step():
         r = fem.source_value(prob, (k + 1) * dt) * S
         res = M @ (a1 - a0) / dt + K @ a1 - r
         assert np.linalg.norm(res) <= 1e-6 * np.linalg.norm(K @ a1)
+
+
+def test_b_squared_linear_field_and_hand_elements():
+    """|B_e|^2 = |grad a_h|^2 per element (Eq. (1) with B = curl(A e_z)).
+
+    (1) a = alpha x + beta y sampled on interior nodes: on every element with no
+    boundary vertex the P1 interpolant is that linear field, so |grad a|^2 =
+    alpha^2 + beta^2 exactly (up to rounding).
+    (2) Hand values on a 4-node mesh (h = 1/3), interior DoFs (1,1)=1, (2,1)=2,
+    (1,2)=3, (2,2)=5 (boundary zero).  In cell (1,1) the lower triangle
+    (1,1),(2,1),(2,2) has d/dx = (2-1)/h, d/dy = (5-2)/h, |g|^2 = 10/h^2 = 90;
+    the upper one (1,1),(2,2),(1,2) has d/dx = (5-3)/h, d/dy = (3-1)/h, 8/h^2 = 72.
+    In cell (0,0) the lower triangle (0,0),(1,0),(1,1) has d/dy = 1/h, 9; the upper
+    one (0,0),(1,1),(0,1) has d/dx = 1/h, 9.  In cell (2,0) the lower triangle
+    (2,0),(3,0),(3,1) is all boundary, 0; the upper one (2,0),(3,1),(2,1) has
+    d/dx = (0-2)/h, d/dy = (2-0)/h, 8/h^2 = 72."""
+    n = 9
+    m = mesh.build(n)
+    g = fem.basis_gradients(m)
+    alpha, beta = 0.37, -1.9
+    nd = n - 2
+    a = np.zeros(m.n_dof)
+    for j in range(1, n - 1):
+        for i in range(1, n - 1):
+            a[(j - 1) * nd + (i - 1)] = alpha * i * m.h + beta * j * m.h
+    b2 = picard.b_squared(m, g, a)
+    interior = np.all(m.dof[m.tri] >= 0, axis=1)
+    assert interior.sum() > 0
+    assert np.allclose(b2[interior], alpha ** 2 + beta ** 2, rtol=1e-12, atol=0)
+    assert np.all(np.abs(b2[~interior] - (alpha ** 2 + beta ** 2)) > 1e-6)
+
+    m4 = mesh.build(4)
+    g4 = fem.basis_gradients(m4)
+    b4 = picard.b_squared(m4, g4, np.array([1.0, 2.0, 3.0, 5.0]))
+
+    def elem(i, j, upper):
+        return 2 * (j * 3 + i) + (1 if upper else 0)
+
+    want = {(1, 1, 0): 90.0, (1, 1, 1): 72.0, (0, 0, 0): 9.0, (0, 0, 1): 9.0,
+            (2, 0, 0): 0.0, (2, 0, 1): 72.0}
+    for (i, j, up), v in want.items():
+        e = elem(i, j, up)
+        c = m4.centroid[e]
+        assert (c[0] - i / 3) * 3 == pytest.approx(2 / 3 if not up else 1 / 3)
+        assert b4[e] == pytest.approx(v, rel=1e-13, abs=1e-12), (i, j, up)
