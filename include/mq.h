@@ -218,6 +218,30 @@ int mq_plan_split(int32_t n, const int32_t* steps, int32_t slots, int32_t split_
 const char* mq_last_error(void);
 int mq_version(void);
 
+/* Per-instance flag bits (mq_last_flags; mq_run_stats counts them). */
+enum {
+  MQ_FLAG_NOT_CONVERGED = 1, /* a step ended at max_iter / max_sweeps above tol (results are those of
+                                the last sweep) */
+  MQ_FLAG_FAILED = 2,        /* a non-finite residual: the instance's results are not valid; the
+                                other instances of the call are unaffected */
+  MQ_FLAG_PICARD_CAP = 4,    /* a step's Picard iteration stopped at picard_max above picard_tol
+                                (counted in n_not_converged) */
+  MQ_FLAG_PARAREAL_KMAX = 8  /* Parareal stopped at k_max above tol (Section II-C) */
+};
+
+/* Per-instance flags of the calling thread's last mlmc_level_run,
+ * mlmc_multilevel_run or parareal_run (any handle), so that a caller given
+ * MQ_WARN_NOT_CONVERGED can tell which results to distrust.  Order: level run:
+ * the n fine instances by sample, then (coupled level) the n coarse ones;
+ * multilevel run: the same per level, levels in order; Parareal: one entry per
+ * sample, the OR of its fine and coarse instances plus MQ_FLAG_PARAREAL_KMAX.
+ * After any other run call, or a run call that failed before its launch, the
+ * list is empty.  flags: host [cap] (nullable when cap = 0); *n_out: host, the
+ * list's length (entries beyond cap are not written).  The list belongs to the
+ * calling thread.  Errors: MQ_ERR_INVALID_ARG (n_out null, cap < 0, flags null
+ * with cap > 0). */
+int mq_last_flags(int32_t* flags, int64_t cap, int64_t* n_out);
+
 /* Build the mesh, masks, KL basis, load shape and device tables.
  * d: host; stream: hipStream_t or NULL; *out receives the handle.
  * Errors: MQ_ERR_INVALID_ARG (n_nodes < 3, bad boxes, tolerances), MQ_ERR_NO_DEVICE,

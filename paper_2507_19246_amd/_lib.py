@@ -28,6 +28,7 @@ MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING, MQ_PATH_WIDE = 0, 1, 2, 3
 MQ_PRECOND_AUTO, MQ_PRECOND_JACOBI, MQ_PRECOND_MULTIGRID = 0, 1, 2
 MQ_MEM_DEVICE, MQ_MEM_HOST = 0, 1
 MQ_MASS_CONSISTENT, MQ_MASS_LUMPED = 0, 1
+MQ_FLAG_NOT_CONVERGED, MQ_FLAG_FAILED, MQ_FLAG_PICARD_CAP, MQ_FLAG_PARAREAL_KMAX = 1, 2, 4, 8
 
 
 class ProblemDesc(C.Structure):
@@ -146,6 +147,7 @@ PD = C.POINTER(C.c_double)
 SIGNATURES = {
     "mq_last_error": (C.c_char_p, []),
     "mq_version": (C.c_int, []),
+    "mq_last_flags": (C.c_int, [C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
     "fem_setup": (C.c_int, [C.POINTER(ProblemDesc), VP, C.POINTER(VP)]),
     "mq_problem_destroy": (C.c_int, [VP]),
     "mq_ndof": (C.c_int, [VP, C.POINTER(C.c_int64)]),

@@ -263,6 +263,19 @@ def parareal_run(prob: Problem, n_periods: int, n_slices: int, fine_steps_per_sl
     return q, it, fs, rc, st.as_dict()
 
 
+def last_flags():
+    """Per-instance MQ_FLAG_* bits of this thread's last level, multilevel or
+    Parareal run (numpy int32; order as documented for mq_last_flags)."""
+    import numpy as np
+    lib = L.load()
+    n = C.c_int64()
+    L.check(lib.mq_last_flags(None, 0, C.byref(n)))
+    out = np.zeros(n.value, dtype=np.int32)
+    if n.value:
+        L.check(lib.mq_last_flags(out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+    return out
+
+
 def mlmc_estimate(q_fine: Sequence[torch.Tensor], q_coarse: Sequence[Optional[torch.Tensor]]):
     """Eq. (9) on the device: returns (E, level means, level variances) as a float64 tensor split."""
     lib = L.load()

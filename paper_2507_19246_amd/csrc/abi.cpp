@@ -22,6 +22,12 @@ std::string& last_error() {
   thread_local std::string e;
   return e;
 }
+// per-instance FLAG_* bits of the calling thread's last level, multilevel or
+// Parareal run (empty after any other run call)
+std::vector<int32_t>& last_flags() {
+  thread_local std::vector<int32_t> f;
+  return f;
+}
 }  // namespace mq
 
 namespace {
@@ -154,6 +160,7 @@ int check_finite(mq_problem* p, const double* x, size_t n) {
 
 struct RunOut {
   int status = MQ_OK;
+  std::vector<int> flags;  // FLAG_* bits per instance, appended by each run_instances call in its order
   double kernel_ms = 0;
   int grid = 0, block = 0;
 };
@@ -341,7 +348,7 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   if (p->path == MQ_PATH_WIDE) {
     (void)stat_host;
     int status = MQ_OK;
-    const int rc = run_wide(p, insts, st, &status);
+    const int rc = run_wide(p, insts, st, &status, &ro->flags);
     if (rc) return rc;
     ro->status = std::max(ro->status, status);
     return MQ_OK;
@@ -429,11 +436,12 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   for (int i = 0; i < n; ++i) {
     if (st) {
       st->n_instances += 1;
-      if (oflags[i] & FLAG_NOT_CONVERGED) st->n_not_converged++;
+      if (oflags[i] & (FLAG_NOT_CONVERGED | FLAG_PICARD_CAP)) st->n_not_converged++;
       if (oflags[i] & FLAG_FAILED) st->n_failed++;
     }
-    if (oflags[i] & (FLAG_NOT_CONVERGED | FLAG_FAILED)) ro->status = MQ_WARN_NOT_CONVERGED;
+    if (oflags[i] & FLAG_WARN) ro->status = MQ_WARN_NOT_CONVERGED;
   }
+  ro->flags.insert(ro->flags.end(), oflags.begin(), oflags.end());
   if (st) {
     st->path = p->path;
     st->grid = ro->grid;
@@ -527,6 +535,12 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
 // Handles set up with mem_kind = MQ_MEM_HOST take host arrays in the staged calls.
 bool host_mode(const mq_problem* p) { return p && p->d.mem_kind == MQ_MEM_HOST; }
 
+// mq_last_flags reports level, multilevel and Parareal runs only: the other run
+// calls leave its list empty whichever inner runs they made.
+struct FlagsClearedOnReturn {
+  ~FlagsClearedOnReturn() { last_flags().clear(); }
+};
+
 int refuse_host(const mq_problem* p) {
   if (host_mode(p))
     return fail(MQ_ERR_INVALID_ARG, "this call takes device pointers (the handle was set up with mem_kind = MQ_MEM_HOST)");
@@ -538,6 +552,14 @@ int refuse_host(const mq_problem* p) {
 extern "C" {
 
 const char* mq_last_error(void) { return last_error().c_str(); }
+
+int mq_last_flags(int32_t* flags, int64_t cap, int64_t* n_out) {
+  if (!n_out || cap < 0 || (cap > 0 && !flags)) return fail(MQ_ERR_INVALID_ARG, "invalid arguments");
+  const std::vector<int32_t>& f = last_flags();
+  *n_out = (int64_t)f.size();
+  for (int64_t i = 0; i < cap && i < (int64_t)f.size(); ++i) flags[i] = f[i];
+  return MQ_OK;
+}
 
 int mq_version(void) { return 1; }
 
@@ -586,8 +608,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
     return fail(MQ_ERR_INVALID_ARG, "the nonlinear (Picard) material runs on the resident path only");
   p->path = (d->path == MQ_PATH_STREAMING || !p->resident_ok) ? MQ_PATH_STREAMING : MQ_PATH_RESIDENT;
   if (d->path == MQ_PATH_WIDE) {
-    if (d->material == MQ_MAT_NONLINEAR || !want_mg)
-      return fail(MQ_ERR_INVALID_ARG, "the wide path needs a linear material and the multigrid preconditioner");
+    if (d->material == MQ_MAT_NONLINEAR) return fail(MQ_ERR_INVALID_ARG, "the wide path needs a linear material");
     p->path = MQ_PATH_WIDE;
   }
   p->mg = MGGeom{};
@@ -596,8 +617,6 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   } else if (want_mg && !build_mg(g0, 0, &p->mg)) {
     p->mg = MGGeom{};
   }
-  if (p->path == MQ_PATH_WIDE && p->mg.nlev < 1)
-    return fail(MQ_ERR_INVALID_ARG, "the wide path needs n_nodes = 2^k + 1 (multigrid hierarchy)");
   if (d->precond == MQ_PRECOND_MULTIGRID && p->mg.nlev == 0)
     return fail(MQ_ERR_INVALID_ARG, "multigrid needs n_nodes = 2^k + 1 (and, on the resident path, room in LDS)");
   p->precond = p->mg.nlev > 0 ? MQ_PRECOND_MULTIGRID : MQ_PRECOND_JACOBI;
@@ -684,6 +703,7 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
 
 static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
                          double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+  last_flags().clear();
   if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
@@ -696,6 +716,7 @@ static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_sampl
   RunOut ro;
   rc = run_instances(p, all, st, &ro, nullptr);
   if (rc) return rc;
+  last_flags().assign(ro.flags.begin(), ro.flags.end());  // fine 0..n-1, then coarse 0..n-1
   if (final_state) {
     TmpPtr<double*> dptr;
     HIP_TRY(tmp_alloc(dptr, lb.afull_ptr.size(), p->stream));
@@ -710,28 +731,39 @@ static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_sampl
 static int multilevel_run_dev(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
                               const int32_t* n_samples, const double* const* xi, double* const* q_fine,
                               double* const* q_coarse, mq_run_stats* st) {
+  last_flags().clear();
   if (!p || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 1 || n_levels > 64) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
   std::vector<LevelBufs> lbs(n_levels);
   std::vector<Inst> all;
-  std::vector<std::pair<int64_t, Inst>> keyed;
+  // (steps, position in the caller's flag order, instance): per level its fine
+  // instances, then its coarse ones
+  struct Keyed {
+    int64_t steps;
+    int pos;
+    Inst in;
+  };
+  std::vector<Keyed> keyed;
   int group0 = 0;
   for (int l = 0; l < n_levels; ++l) {
     std::vector<Inst> f, c;
     int rc = prepare_level(p, &lv[l], n_samples[l], xi[l], q_fine[l], q_coarse[l], false, lbs[l], f, c, group0);
     group0 += n_samples[l];
     if (rc) return rc;
-    for (auto& i : f) keyed.push_back({i.n_steps, i});
-    for (auto& i : c) keyed.push_back({i.n_steps, i});
+    for (auto& i : f) keyed.push_back({i.n_steps, (int)keyed.size(), i});
+    for (auto& i : c) keyed.push_back({i.n_steps, (int)keyed.size(), i});
   }
   // longest instances first; stable so that equal lengths keep their order
-  std::stable_sort(keyed.begin(), keyed.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  for (auto& k : keyed) all.push_back(k.second);
+  std::stable_sort(keyed.begin(), keyed.end(), [](const Keyed& a, const Keyed& b) { return a.steps > b.steps; });
+  for (auto& k : keyed) all.push_back(k.in);
   RunOut ro;
   int rc = run_instances(p, all, st, &ro, nullptr);
   if (rc) return rc;
+  std::vector<int32_t>& lf = last_flags();
+  lf.assign(keyed.size(), 0);
+  for (size_t i = 0; i < keyed.size(); ++i) lf[keyed[i].pos] = ro.flags[i];
   if (st) st->total_ms = now_ms() - t0;
   return ro.status;
 }
@@ -739,6 +771,7 @@ static int multilevel_run_dev(mq_problem* p, int32_t n_levels, const mq_level_de
 int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_max,
                       const double* const* xi, double* const* q_fine, double* const* q_coarse,
                       const mq_adaptive_desc* ad, int32_t* n_used, double* out, mq_run_stats* st) {
+  const FlagsClearedOnReturn no_flags;
   if (int rh = refuse_host(p)) return rh;
   if (!p || !lv || !n_max || !xi || !q_fine || !q_coarse || !ad || !n_used || !out)
     return fail(MQ_ERR_INVALID_ARG, "null argument");
@@ -845,6 +878,7 @@ int mlmc_adaptive_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
 int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_level_desc* lv,
                        const int32_t* n_samples, const double* const* xi, double* const* q_fine,
                        double* const* q_coarse, mq_run_stats* st) {
+  const FlagsClearedOnReturn no_flags;
   if (!problems || !lv || !n_samples || !xi || !q_fine || !q_coarse) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (n_levels < 1 || n_levels > 16) return fail(MQ_ERR_INVALID_ARG, "n_levels must be in [1, 16]");
   for (int m = 0; m < n_levels; ++m)
@@ -936,6 +970,7 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
 
 static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
                             double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
+  last_flags().clear();
   if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
   if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "Parareal runs on the resident or streaming path");
   if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
@@ -981,7 +1016,11 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
   std::vector<int> active(S);
   for (int s = 0; s < S; ++s) active[s] = s;
   std::vector<int> Kout(S, 0);
+  std::vector<int32_t> pflags(S, 0);  // per sample: its instances' flags OR-ed
   bool warn = false;
+  auto collect = [&](const std::vector<Inst>& insts, size_t off) {
+    for (size_t i = 0; i < insts.size(); ++i) pflags[insts[i].sample] |= ro.flags[off + i];
+  };
 
   auto launch_chain = [&](const std::vector<int>& smp, int first, bool initial) -> int {
     if (first > M - 1 || smp.empty()) return MQ_OK;
@@ -1015,7 +1054,10 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
       in.sample = smp[a];
       insts.push_back(in);
     }
-    return run_instances(p, insts, st, &ro, nullptr);
+    const size_t off = ro.flags.size();
+    const int rc2 = run_instances(p, insts, st, &ro, nullptr);
+    if (rc2 == MQ_OK) collect(insts, off);
+    return rc2;
   };
 
   // initial coarse pass U_n = C(U_{n-1}), n = 1..M-1
@@ -1041,8 +1083,10 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
         in.group = s;
         insts.push_back(in);
       }
+    const size_t off = ro.flags.size();
     rc = run_instances(p, insts, st, &ro, nullptr);
     if (rc) return rc;
+    collect(insts, off);
     // interface jumps over n = j..M-1
     std::vector<int> still;
     if (j < M) {
@@ -1075,7 +1119,10 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
         const bool done = (pd->fixed_k == 0 && J <= pd->tol) || j == kcap;
         if (done) {
           Kout[s] = j;
-          if (pd->fixed_k == 0 && J > pd->tol) warn = true;
+          if (pd->fixed_k == 0 && J > pd->tol) {
+            warn = true;
+            pflags[s] |= FLAG_PARAREAL_KMAX;
+          }
         } else {
           still.push_back(s);
         }
@@ -1111,6 +1158,7 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
     HIP_TRY(launch_to_interior(g, S, dfp.get(), final_state, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
+  last_flags() = pflags;
   if (st) st->total_ms = now_ms() - t_start;
   if (warn) {
     last_error() = "Parareal reached k_max above the tolerance for some samples";
@@ -1122,6 +1170,7 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
 int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_samples,
                       const double* const* xi, const mq_combined_desc* cd, double* const* q_fine,
                       double* const* q_coarse, int32_t* para_iters, mq_run_stats* st, mq_combined_stats* cs) {
+  const FlagsClearedOnReturn no_flags;
   if (int rh = refuse_host(p)) return rh;
   if (!p || !lv || !n_samples || !xi || !cd || !q_fine || !q_coarse || !para_iters)
     return fail(MQ_ERR_INVALID_ARG, "null argument");

@@ -2463,6 +2463,22 @@ __global__ __launch_bounds__(WIDE_BX) void k_w_post(Geom g, WidePtrs w, VT om) {
   wide_partial<2>(v, w.part);
 }
 
+// Jacobi preconditioner in place of the V-cycle: the system is already scaled
+// to unit diagonal, so z = r (into T); partials r.z and r.r
+template <typename VT>
+__global__ __launch_bounds__(WIDE_BX) void k_w_jz(Geom g, WidePtrs w) {
+  if (w.sc->done) return;
+  WIDE_NODE;
+  double v[2] = {0.0, 0.0};
+  if (act) {
+    const VT r = ((const VT*)w.R)[nr.gi];
+    ((VT*)w.T)[nr.gi] = r;
+    v[0] = (double)(r * r);
+    v[1] = v[0];
+  }
+  wide_partial<2>(v, w.part);
+}
+
 // p = z + beta p, q = A z + beta q (z in T); partial p.q
 template <typename VT>
 __global__ __launch_bounds__(WIDE_BX) void k_w_pq(Geom g, WidePtrs w) {
@@ -2570,6 +2586,14 @@ static hipError_t wide_iteration_t(const WideCtx& c, hipStream_t st) {
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   const VT om = (VT)c.sv.mg_omega, air = (VT)c.air;
   const dim3 gr = wide_grid(c), bl(WIDE_BX);
+  if (c.mg.nlev == 0) {  // Jacobi-preconditioned CG
+    hipLaunchKernelGGL((k_w_jz<VT>), gr, bl, 0, st, c.g, c.w);
+    hipLaunchKernelGGL((k_w_reduce<WRED_RZ, 2>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+    hipLaunchKernelGGL((k_w_pq<VT>), gr, bl, 0, st, c.g, c.w);
+    hipLaunchKernelGGL((k_w_reduce<WRED_PQ, 1>), dim3(1), dim3(1024), 0, st, c.w, c.sv, c.nblk, 0.0);
+    hipLaunchKernelGGL((k_w_yr<VT>), gr, bl, 0, st, c.g, c.w);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_w_pre<VT>), gr, bl, 0, st, c.g, c.w, om);
   hipLaunchKernelGGL((k_w_restrict1<VT>), dim3(wide_cblocks(c.mg, 1)), bl, 0, st, c.g, c.mg, c.w, om, air);
   for (int l = 1; l < c.lt; ++l) {

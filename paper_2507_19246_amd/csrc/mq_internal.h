@@ -139,7 +139,9 @@ struct Solver {
   int mg_block_min;      // coarse levels with at least this many nodes per side use the whole workgroup
 };
 
-enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4 };
+enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4, FLAG_PARAREAL_KMAX = 8 };
+// bits that make a call return MQ_WARN_NOT_CONVERGED
+constexpr int FLAG_WARN = FLAG_NOT_CONVERGED | FLAG_FAILED | FLAG_PICARD_CAP;
 enum { STAT_N = 17 };
 
 // Wide path (one instance over the whole device): solver scalars in device

@@ -129,6 +129,7 @@ std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_tota
 // min(n, max_slots(p)) slots.
 int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block);
 // Wide path (wide.cpp): run the instances one after the other over the whole device.
-int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status);
+// flags (nullable): receives one entry of FLAG_* bits per instance, in insts order
+int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status, std::vector<int>* flags);
 
 }  // namespace mq

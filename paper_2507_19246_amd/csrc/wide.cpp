@@ -29,9 +29,8 @@ struct GraphExec {
 
 }  // namespace
 
-int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status) {
+int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status, std::vector<int>* flags_out) {
   const Geom& g = p->hm.g;
-  if (p->mg.nlev < 1) return fail(MQ_ERR_INVALID_ARG, "the wide path needs the multigrid hierarchy");
   for (const Inst& in : insts)
     if (in.n_chain > 0 || in.carry) return fail(MQ_ERR_INVALID_ARG, "the wide path runs plain level instances only");
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -166,6 +165,7 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
     HIP_TRY(wide_finish(c, in.q_scale, in.q_out, in.a_out, ws));
     HIP_TRY(read_sc());
     flags |= h.flags;
+    if (flags_out) flags_out->push_back(flags);
     if (st) {
       st->n_instances += 1;
       st->sample_steps += in.n_steps;
@@ -174,7 +174,7 @@ int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* sta
       if (flags & FLAG_NOT_CONVERGED) st->n_not_converged++;
       if (flags & FLAG_FAILED) st->n_failed++;
     }
-    if (flags & (FLAG_NOT_CONVERGED | FLAG_FAILED)) *status = MQ_WARN_NOT_CONVERGED;
+    if (flags & FLAG_WARN) *status = MQ_WARN_NOT_CONVERGED;
   }
   HIP_TRY(hipEventRecord(e1, ws));
   HIP_TRY(hipEventSynchronize(e1));

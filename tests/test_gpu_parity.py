@@ -193,13 +193,132 @@ def test_parareal_matches_oracle(path):
         a = fs[s].cpu().numpy()
         assert np.linalg.norm(a - ref["state"]) <= 1e-10 * np.linalg.norm(ref["state"])
     assert np.all(it.cpu().numpy() == 6)
-    # tolerance mode: K and Q as the oracle
+    # tolerance mode: K as the oracle (within one: the stop test compares a
+    # jump near tol), and Q as the oracle's Parareal stopped at the same K
     q, it, fs, rc, st = mq.parareal_run(p, 1, 8, 8, 1, 8, 1e-5, xi)
     for s in range(3):
         ref = opara.run(prob, xi[s], 1, 8, 8, 1, k_max=8, tol=1e-5)
         assert abs(int(it[s]) - ref["K"]) <= 1
-        if int(it[s]) == ref["K"]:
-            assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-9)
+        if int(it[s]) != ref["K"]:
+            ref = opara.run(prob, xi[s], 1, 8, 8, 1, k_max=8, tol=1e-5, fixed_k=int(it[s]))
+        assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-9)
+    p.close()
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_parareal_fixed_k_below_m_matches_oracle(path):
+    """Parareal stopped at a fixed k < M (Eq. (12)): the slices after k are not
+    yet exact, so Q and the final state depend on every coarse correction
+    F + (C_new - C_old) made so far.  They match the oracle's Parareal at the
+    same k within 1e-10 (FP64), and differ from the serial fine run by far
+    more than that, so the comparison sees the correction."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 24, 0, range(3), 8)
+    p = mq.Problem(prob, L.MQ_PREC_FP64, path=path)
+    m = omesh.build(17)
+    tab = ots.kl_table_for(prob, m)
+    for k in (1, 2, 3):
+        say(f"parareal fixed_k={k} of M=6, path={path}")
+        q, it, fs, rc, st = mq.parareal_run(p, 1, 6, 4, 1, 6, 0.0, xi, fixed_k=k, want_state=True)
+        assert rc == 0 and np.all(it.cpu().numpy() == k)
+        assert np.all(mq.last_flags() == 0)
+        for s in range(3):
+            ref = opara.run(prob, xi[s], 1, 6, 4, 1, k_max=6, tol=0.0, fixed_k=k, m=m, kl_table=tab)
+            ser = opara.serial_fine(prob, xi[s], 1, 6, 4, m=m, kl_table=tab)
+            assert ref["K"] == k
+            assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-10)
+            a = fs[s].cpu().numpy()
+            assert np.linalg.norm(a - ref["state"]) <= 1e-10 * np.linalg.norm(ref["state"])
+            assert np.linalg.norm(ref["state"] - ser["state"]) > 1e-6 * np.linalg.norm(ser["state"])
+    p.close()
+
+
+def test_parareal_kmax_warning_flags_every_sample():
+    """Tolerance mode with k_max = 2 and a tolerance no sample reaches: the call
+    returns MQ_WARN_NOT_CONVERGED, every sample carries MQ_FLAG_PARAREAL_KMAX,
+    and Q is the oracle's Parareal stopped at k = 2."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 25, 0, range(2), 8)
+    p = mq.Problem(prob, L.MQ_PREC_FP64)
+    q, it, _, rc, _ = mq.parareal_run(p, 1, 6, 4, 1, 2, 1e-14, xi)
+    assert rc == L.MQ_WARN_NOT_CONVERGED
+    f = mq.last_flags()
+    assert len(f) == 2 and np.all(f == L.MQ_FLAG_PARAREAL_KMAX)
+    for s in range(2):
+        ref = opara.run(prob, xi[s], 1, 6, 4, 1, k_max=2, tol=1e-14)
+        assert int(it[s]) == ref["K"] == 2
+        assert float(q[s]) == pytest.approx(ref["Q"], rel=1e-10)
+    p.close()
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_solver_caps_flag_instances(path):
+    """Tiny max_iter and max_sweeps: every step stops at the cap, the call
+    returns MQ_WARN_NOT_CONVERGED, every instance carries MQ_FLAG_NOT_CONVERGED
+    (fine instances, then coarse, per level) and the results stay finite."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 26, 0, range(3), 8)
+    p = mq.Problem(prob, L.MQ_PREC_FP64, path=path, max_iter=2, max_sweeps=1)
+    say(f"solver caps path={path}")
+    qf, qc, _, rc, st = mq.mlmc_level_run(p, 8, 4, 1, xi)
+    assert rc == L.MQ_WARN_NOT_CONVERGED
+    f = mq.last_flags()
+    assert len(f) == 6 and np.all(f == L.MQ_FLAG_NOT_CONVERGED)
+    assert st["n_not_converged"] == 6 and st["n_failed"] == 0
+    assert bool(torch.isfinite(qf).all()) and bool(torch.isfinite(qc).all())
+    qfs, qcs, rcm, stm = mq.mlmc_multilevel_run(p, [(4, 0, 1), (8, 4, 1)], [xi[:2], xi])
+    assert rcm == L.MQ_WARN_NOT_CONVERGED and stm["n_not_converged"] == 2 + 6
+    assert len(mq.last_flags()) == 2 + 6
+    p.close()
+
+
+def test_picard_cap_flags_and_matches_oracle():
+    """picard_max = 1: every step makes one Picard iteration (nu lagged at a_k)
+    and stops at the cap.  The call returns MQ_WARN_NOT_CONVERGED, every
+    instance carries MQ_FLAG_PICARD_CAP, and Q is the oracle's with the same
+    cap (FP64, 1e-9)."""
+    from oracle import picard as opic
+    mq, L = mqmod()
+    prob = W.Problem(33, W.Material(kind=W.MAT_NONLINEAR, k2=5.0e2, picard_max=1))
+    xi = W.normals(0, 27, 0, range(3), 3)
+    p = mq.Problem(prob, L.MQ_PREC_FP64, tol=1e-12, inner_rtol=1e-9)
+    qf, _, _, rc, st = mq.mlmc_level_run(p, 16, 0, 1, xi)
+    assert rc == L.MQ_WARN_NOT_CONVERGED
+    f = mq.last_flags()
+    assert len(f) == 3 and np.all(f & L.MQ_FLAG_PICARD_CAP) and st["n_not_converged"] == 3
+    assert st["picard_iters"] == 3 * 16
+    m = omesh.build(33)
+    for s in range(3):
+        Q, a, counts, flagged = opic.solve_sample(prob, xi[s], 16, 1, m=m, return_counts=True)
+        assert flagged and np.all(counts == 1)
+        assert float(qf[s]) == pytest.approx(Q, rel=1e-9)
+    p.close()
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_nonfinite_instance_leaves_others_correct(path):
+    """A finite input whose conductivity overflows (sigma = inf) gives that
+    instance a non-finite residual: it carries MQ_FLAG_FAILED and a non-finite
+    Q, the call returns MQ_WARN_NOT_CONVERGED, and the other instances of the
+    same launch still match the oracle within 1e-10 (FP64)."""
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 28, 0, range(4), 8)
+    xi[2, 0] = 1.0e4  # exp(0.3 sqrt(lambda_1) phi_1 xi) overflows on the conductor
+    p = mq.Problem(prob, L.MQ_PREC_FP64, path=path, max_iter=400)
+    say(f"non-finite instance path={path}")
+    qf, _, _, rc, st = mq.mlmc_level_run(p, 8, 0, 1, xi)
+    assert rc == L.MQ_WARN_NOT_CONVERGED
+    f = mq.last_flags()
+    assert f[2] & L.MQ_FLAG_FAILED and st["n_failed"] == 1
+    assert not np.isfinite(float(qf[2]))
+    good = [0, 1, 3]
+    assert np.all(f[good] == 0)
+    qref, _ = oracle_q(prob, xi[good], 8, 1)
+    assert np.max(np.abs(qf.cpu().numpy()[good] - qref) / qref) <= 1e-10
     p.close()
 
 
@@ -328,6 +447,104 @@ def test_small_mesh_resident_multigrid_fp64(n):
         assert rc == 0 and st["n_failed"] == 0
         assert np.max(np.abs(qf.cpu().numpy() - qref) / np.abs(qref)) <= 1e-10
         assert np.linalg.norm(fs.cpu().numpy() - aref) <= 1e-10 * np.linalg.norm(aref)
+        p.close()
+
+
+def test_host_pointer_handle_matches_device_handle():
+    """mem_kind = MQ_MEM_HOST: initial state, level run, multilevel run and
+    Parareal take host arrays through the C ABI and give the device handle's
+    results bit for bit; the calls without a host form refuse such a handle."""
+    import ctypes as C
+    mq, L = mqmod()
+    prob = W.Problem(17, W.Material(kind=W.MAT_KL))
+    xi = np.ascontiguousarray(W.normals(0, 43, 0, range(4), 8), dtype=np.float64)
+    pdv = mq.Problem(prob, L.MQ_PREC_MIXED)
+    ph = mq.Problem(prob, L.MQ_PREC_MIXED, mem_kind=L.MQ_MEM_HOST)
+    lib = ph.lib
+
+    def P(a):
+        return a.ctypes.data_as(C.c_void_p)
+
+    say("host handle: initial state + level run")
+    a0 = np.ascontiguousarray(np.random.default_rng(5).standard_normal(ph.n_dof) * 1e-4)
+    pdv.set_initial_state(a0)
+    assert lib.mq_set_initial_state(ph.h, P(a0)) == 0
+    qf_d, qc_d, fs_d, rc_d, _ = mq.mlmc_level_run(pdv, 16, 8, 1, xi, want_state=True)
+    qf, qc, fs = np.zeros(4), np.zeros(4), np.zeros((4, ph.n_dof))
+    lv = L.LevelDesc(16, 8, 1, 0)
+    st = L.RunStats()
+    rc = lib.mlmc_level_run(ph.h, C.byref(lv), 4, P(xi), P(qf), P(qc), P(fs), C.byref(st))
+    assert rc == rc_d == 0
+    np.testing.assert_array_equal(qf, qf_d.cpu().numpy())
+    np.testing.assert_array_equal(qc, qc_d.cpu().numpy())
+    np.testing.assert_array_equal(fs, fs_d.cpu().numpy())
+    pdv.set_initial_state(None)
+    assert lib.mq_set_initial_state(ph.h, None) == 0
+
+    say("host handle: multilevel run")
+    levels = [(8, 0, 1), (16, 8, 1)]
+    xs = [xi[:3].copy(), xi[1:].copy()]
+    qfs_d, qcs_d, rcm_d, _ = mq.mlmc_multilevel_run(pdv, levels, xs)
+    lvs = (L.LevelDesc * 2)(*[L.LevelDesc(a, b, c, 0) for a, b, c in levels])
+    ns = (C.c_int32 * 2)(3, 3)
+    qfh = [np.zeros(3), np.zeros(3)]
+    qch = [None, np.zeros(3)]
+    px = (C.c_void_p * 2)(*[x.ctypes.data for x in xs])
+    pf = (C.c_void_p * 2)(*[q.ctypes.data for q in qfh])
+    pc = (C.c_void_p * 2)(None, qch[1].ctypes.data)
+    assert lib.mlmc_multilevel_run(ph.h, 2, lvs, ns, px, pf, pc, C.byref(st)) == rcm_d == 0
+    for l in range(2):
+        np.testing.assert_array_equal(qfh[l], qfs_d[l].cpu().numpy())
+    np.testing.assert_array_equal(qch[1], qcs_d[1].cpu().numpy())
+
+    say("host handle: Parareal")
+    qp_d, it_d, fsp_d, rcp_d, _ = mq.parareal_run(pdv, 1, 4, 4, 1, 4, 1e-6, xi, want_state=True)
+    qp, itp, fsp = np.zeros(4), np.zeros(4, dtype=np.int32), np.zeros((4, ph.n_dof))
+    pd = L.PararealDesc(1, 4, 4, 1, 4, 0, 1e-6)
+    rcp = lib.parareal_run(ph.h, C.byref(pd), 4, P(xi), P(qp), P(itp), P(fsp), C.byref(st))
+    assert rcp == rcp_d
+    np.testing.assert_array_equal(qp, qp_d.cpu().numpy())
+    np.testing.assert_array_equal(itp, it_d.cpu().numpy())
+    np.testing.assert_array_equal(fsp, fsp_d.cpu().numpy())
+
+    say("host handle: calls without a host form")
+    with pytest.raises(L.MQError) as e:
+        mq.debug_apply(ph, 0, 1e-3, xi[:1], np.zeros((1, ph.n_dof)))
+    assert e.value.code == L.MQ_ERR_INVALID_ARG
+    with pytest.raises(L.MQError) as e:
+        mq.mlmc_combined_run(ph, [(8, 0, 1), (16, 8, 1)], xs)
+    assert e.value.code == L.MQ_ERR_INVALID_ARG
+    pdv.close()
+    ph.close()
+
+
+def test_lumped_mass_sine_mode_closed_form():
+    """Lumped-mass option on the homogeneous square, no source: the sampled sine
+    mode v = sin(p pi x) sin(q pi y) is an eigenvector, so implicit Euler (Eq. (7))
+    gives a_n = (1 + lam dt)^-n v with lam = nu (4 - 2 cos(p pi h) - 2 cos(q pi h)) /
+    (sigma h^2), and Eq. (26) the loss sigma h^2 |v|^2 sum_k (c_{k+1} - c_k)^2 / (dt T)."""
+    import math
+    mq, L = mqmod()
+    for n, path in ((17, L.MQ_PATH_AUTO), (33, L.MQ_PATH_STREAMING)):
+        hom = W.Problem(n, W.Material(kind=W.MAT_LOGNORMAL_SCALAR), conductor=(0.0, 1.0, 0.0, 1.0), J0=0.0)
+        p = mq.Problem(hom, L.MQ_PREC_FP64, path=path, mass=L.MQ_MASS_LUMPED)
+        h = 1.0 / (n - 1)
+        x = np.arange(1, n - 1) * h
+        sig, nu = hom.material.sigma0, hom.material.nu_cond
+        spp, nper = 8, 2
+        nst, dt = spp * nper, hom.period / spp
+        for pq in ((1, 1), (2, 3), (n - 3, 1)):
+            say(f"lumped mass n={n} path={path} mode={pq}")
+            v = np.outer(np.sin(pq[1] * math.pi * x), np.sin(pq[0] * math.pi * x)).ravel()  # row j, column i
+            lam = nu * (4 - 2 * math.cos(pq[0] * math.pi * h) - 2 * math.cos(pq[1] * math.pi * h)) / (sig * h * h)
+            p.set_initial_state(v)
+            qf, _, fs, rc, _ = mq.mlmc_level_run(p, spp, 0, nper, np.zeros((1, 2)), want_state=True)
+            assert rc == 0
+            c = (1.0 + lam * dt) ** -np.arange(nst + 1.0)
+            a = fs[0].cpu().numpy()
+            assert np.linalg.norm(a - c[-1] * v) <= 1e-10 * np.linalg.norm(c[-1] * v)
+            qref = sig * h * h * float(v @ v) * np.sum(np.diff(c) ** 2) / dt / (nst * dt)
+            assert float(qf[0]) == pytest.approx(qref, rel=1e-10)
         p.close()
 
 

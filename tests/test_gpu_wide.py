@@ -148,4 +148,31 @@ def test_wide_rejects_what_it_does_not_run():
         mq.parareal_run(p, 1, 4, 8, 1, 4, 1e-8, xi)
     p.close()
     with pytest.raises(Exception):
-        mq.Problem(W.Problem(34, W.Material(kind=W.MAT_KL)), L.MQ_PREC_MIXED, path=L.MQ_PATH_WIDE)
+        mq.Problem(W.Problem(33, W.Material(kind=W.MAT_NONLINEAR)), L.MQ_PREC_MIXED, path=L.MQ_PATH_WIDE)
+    with pytest.raises(Exception):
+        mq.Problem(W.Problem(34, W.Material(kind=W.MAT_KL)), L.MQ_PREC_MIXED, path=L.MQ_PATH_WIDE,
+                   precond=L.MQ_PRECOND_MULTIGRID)
+
+
+@pytest.mark.parametrize("n,pc", [(33, 1), (34, 0)])
+def test_wide_jacobi_fp64_matches_oracle(n, pc):
+    """The wide path with Jacobi-preconditioned CG (the plain one-sample-per-launch
+    FP64 form; chosen automatically where the mesh has no multigrid hierarchy):
+    Q and the final state within 1e-10 of the oracle."""
+    import paper_2507_19246_amd as mq
+    from paper_2507_19246_amd import _lib as L
+    prob = W.Problem(n, W.Material(kind=W.MAT_KL))
+    xi = W.normals(0, 36, 0, range(2), 8)
+    say(f"wide jacobi fp64 n={n}")
+    p = mq.Problem(prob, L.MQ_PREC_FP64, path=L.MQ_PATH_WIDE, precond=pc)
+    assert p.path == L.MQ_PATH_WIDE and p.info.precond == L.MQ_PRECOND_JACOBI
+    qf, qc, a, rc, st = mq.mlmc_level_run(p, 16, 8, 1, xi, want_state=True)
+    assert rc == 0 and st["path"] == L.MQ_PATH_WIDE and st["n_instances"] == 4
+    qref, aref = oracle_q(prob, xi, 16, 1)
+    qcref, _ = oracle_q(prob, xi, 8, 1)
+    eq = max(np.max(np.abs(qf.cpu().numpy() - qref) / qref), np.max(np.abs(qc.cpu().numpy() - qcref) / qcref))
+    ea = np.linalg.norm(a.cpu().numpy() - aref) / np.linalg.norm(aref)
+    say("err q", eq, "err a", ea, "iters/step", st["inner_iters"] / st["sample_steps"])
+    assert eq <= 1e-10 and ea <= 1e-10
+    assert np.all(mq.last_flags() == 0)
+    p.close()
