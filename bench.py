@@ -51,6 +51,27 @@ CG_FLOPS_PER_DOF_ITER = 26          # 7-point scaled stencil (14) + CG vector up
 # plus the coarse levels (1/4 + 1/16 + ... of that work)
 MG_FLOPS_PER_DOF_ITER = 26 + (28 + 6 + 8) * 4.0 / 3.0
 CG_BYTES_PER_DOF_ITER_FP32 = 72     # modelled streaming traffic of one FP32 CG iteration
+# algorithmic HBM bytes of the mixed-precision path per DoF (the method's own
+# traffic with every vector streamed once per pass): one FP32 CG iteration
+# (stencil 7 x 4 + vectors 16, fused updates 28), one FP64 refinement residual
+# (M and K coefficients, state and increment), one time step's outer work
+# (K a_k, M d, state and increment updates)
+ALG_BYTES_CG_ITER_FP32 = 72
+ALG_BYTES_FP64_RESIDUAL = 120
+ALG_BYTES_STEP = 150
+# MI355X LDS: 128 B per clock per compute unit (the CDNA3 figure, kept as the
+# conservative bound for CDNA4), 256 compute units at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
+# the paper's own results (one 180-core CPU machine, Julia + GetDP, no GPU):
+# context for the numbers of this line, not a target
+PAPER_CONTEXT = {
+    "speedup_of_mlmc_from_parareal": "12-45% (1.12x FE model, 1.45x circuit model)",
+    "extra_effort_core_seconds": "15-18% (1.18x FE model, 1.15x circuit model)",
+    "single_sample_parareal_speedup": "2.69 (FE model, 16 cores per sample), 2.93 (circuit model)",
+    "hardware": "one machine with 180 CPU cores; Julia (DifferentialEquations.jl, MultilevelEstimators.jl, "
+                "Distributed.jl) with GetDP/Gmsh; no GPU; precision not stated",
+    "source": "Sec. III (results), Sec. IV (conclusions), Table II",
+}
 # streaming multigrid CG, algorithmic HBM bytes per fine DoF and iteration (FP32
 # vectors, each vector element read/written once per pass): pre-smoothing and
 # residual 12, restriction 6, prolongation 9, post-smoothing 12, p/q update 20,
@@ -66,6 +87,12 @@ def _kernel_source_hash() -> str:
     h = hashlib.sha256()
     h.update(open(os.path.join(ROOT, "paper_2507_19246_amd", "csrc", "kernels.hip"), "rb").read())
     return h.hexdigest()[:16]
+
+
+def profile_value(name: str, key: str):
+    """A figure from a committed profile summary (`key: value` lines), or None when
+    the kernel source changed since it was taken."""
+    return measured_traffic(name, key)
 
 
 def measured_traffic(name: str, key: str = "traffic_bytes_per_launch"):
@@ -538,6 +565,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--fp64-samples", type=int, default=4,
+                    help="samples of the plain FP64 one-sample-per-call baseline")
     ap.add_argument("--no-host-buffers", action="store_true",
                     help="skip the PCIe-inclusive run through a host-pointer handle")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -626,10 +655,17 @@ def main():
     pcie = None if args.no_host_buffers else host_buffer_rate(w, levels, xis_np, knobs, L, qfs, qcs)
     kern_ms = [s["kernel_ms"] for s in stats]
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
-    units = nd * (sum(s["inner_iters"] for s in stats) / len(stats))   # DoF-iterations per launch
+    per_launch = lambda k: sum(s[k] for s in stats) / len(stats)
+    inner_l, sweeps_l, steps_l = per_launch("inner_iters"), per_launch("sweeps"), per_launch("sample_steps")
+    units = nd * inner_l   # DoF-iterations per launch
+    resid_l = sweeps_l + steps_l   # FP64 residual passes: one per sweep plus the converged check
+    alg_bytes = nd * (ALG_BYTES_CG_ITER_FP32 * inner_l + ALG_BYTES_FP64_RESIDUAL * resid_l + ALG_BYTES_STEP * steps_l)
+    alg_gbs = alg_bytes / avg_kern_s / 1e9
     flops_unit = MG_FLOPS_PER_DOF_ITER if prob.info.precond == L.MQ_PRECOND_MULTIGRID else CG_FLOPS_PER_DOF_ITER
     achieved_tflops = flops_unit * units / avg_kern_s / 1e12
-    traffic = measured_traffic("ie_resident_mlmc3_129_hbm_counters.md")
+    prof = "ie_resident_mlmc3_129_hbm_counters.md"
+    traffic = measured_traffic(prof)
+    lds_bytes = profile_value("ie_resident_mlmc3_129_lds_counters.md", "lds_bytes_per_launch")
 
     # QoI error of the mixed path against FP64 references
     q_mixed = [q.cpu().numpy() for q in qfs]
@@ -637,11 +673,12 @@ def main():
     result = {}
     fp64 = None
     if not args.no_fp64_baseline:
-        # plain FP64 GPU path: one sample per launch, Jacobi-preconditioned FP64 CG
-        # (streaming kernel, S = 1)
-        p64 = mq.Problem(w.problem, L.MQ_PREC_FP64, precond=L.MQ_PRECOND_JACOBI)
+        # plain FP64 GPU path: one sample per call over the whole device, grid-wide
+        # Jacobi-preconditioned FP64 CG passes driven by a host loop (wide path, S = 1)
+        p64 = mq.Problem(w.problem, L.MQ_PREC_FP64, path=L.MQ_PATH_WIDE, precond=L.MQ_PRECOND_JACOBI)
         lv = w.levels[0]
-        nb = 4
+        nb = args.fp64_samples
+        mq.mlmc_level_run(p64, lv.steps_per_period, 0, 1, xis[0][:1])  # warm-up (graph capture, buffers)
         lat, errs, steps64 = [], [], 0
         torch.cuda.synchronize()
         tb = time.perf_counter()
@@ -657,7 +694,12 @@ def main():
         fp64 = {"value": steps64 / wall64, "unit": "sample-steps/s",
                 "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
                 "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
-                "samples": nb, "path": "FP64 Jacobi-CG, one sample per launch, streaming kernel",
+                "samples": nb, "sample_steps_each": lv.steps_per_period * lv.n_periods,
+                "cg_iters_per_sample_step": st64["inner_iters"] / st64["sample_steps"],
+                "path": "FP64 Jacobi-PCG, one sample per call over the whole device (grid-wide passes, "
+                        "host-driven loop, batches of 4 iterations replayed from a captured graph); "
+                        "level-0 samples of the same workload",
+                "latency_definition": "call start to return (Q in device memory)",
                 "qoi_max_rel_err_mixed_vs_fp64": max(errs)}
         result["plain_fp64_gpu"] = fp64
 
@@ -694,26 +736,44 @@ def main():
                    "knobs": dict(knobs, tile=prob.info.tile, precond=prob.info.precond)},
         "p50_latency_ms": st["lat_p50_ms"],
         "p99_latency_ms": st["lat_p99_ms"],
+        "latency_definition": "per sample: call start on the host to its Q (fine and coupled coarse) "
+                              "readable in host memory (completion records in coherent pinned memory, "
+                              "polled during the launch); last timed step",
         "qoi_max_rel_err_vs_fp64_oracle": qerr_oracle,
         "mlmc_estimate": float(e),
         "cg_iters_per_sample_step": stats[-1]["inner_iters"] / stats[-1]["sample_steps"],
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+        "roofline": {"bound": "hbm", "achieved": alg_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_gbs / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": ("k_ie_resident<float,128,%d,%d,64,%s>" % (
                          16 if prob.info.tile != 2 else 32, 8 if prob.info.tile != 2 else 4,
                          "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi")),
                      "avg_launch_ms": 1e3 * avg_kern_s,
-                     "flops_per_dof_iter": flops_unit,
-                     "precond": "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi",
-                     "dof_iters_per_launch": units,
-                     "hbm_equivalent_gbs": CG_BYTES_PER_DOF_ITER_FP32 * units / avg_kern_s / 1e9},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "bytes_per_dof": {"fp32_cg_iteration": ALG_BYTES_CG_ITER_FP32,
+                                       "fp64_residual": ALG_BYTES_FP64_RESIDUAL, "time_step": ALG_BYTES_STEP},
+                     "units_per_launch": {"dof": nd, "cg_iterations": inner_l, "fp64_residuals": resid_l,
+                                          "sample_steps": steps_l},
+                     "measured_hbm_gbs": None if traffic is None else traffic / avg_kern_s / 1e9,
+                     "measured_hbm_frac": None if traffic is None else traffic / avg_kern_s / 1e9 / HBM_PEAK_GBS,
+                     "note": "achieved = the algorithmic bytes of the work done (as if every vector were "
+                             "streamed from HBM) per launch time; this kernel keeps the CG vectors in "
+                             "registers and LDS, so measured HBM traffic (counters) is lower",
+                     "on_chip": None if lds_bytes is None else {
+                         "bound": "lds", "achieved": lds_bytes / avg_kern_s / 1e9, "peak": LDS_PEAK_GBS,
+                         "unit": "GB/s", "frac": lds_bytes / avg_kern_s / 1e9 / LDS_PEAK_GBS,
+                         "lds_bytes_per_launch": lds_bytes},
+                     "alu": {"achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "flops_per_dof_iter": flops_unit},
+                     "precond": "multigrid" if prob.info.precond == L.MQ_PRECOND_MULTIGRID else "jacobi"},
+        "paper_context": PAPER_CONTEXT,
         "cpu_baseline": cpu,
         "pcie_inclusive": pcie,
     }
     res.update(result)
     if fp64:
         res["speedup_vs_plain_fp64"] = value / fp64["value"]
+        res["p99_latency_vs_plain_fp64"] = st["lat_p99_ms"] / fp64["p99_latency_ms"]
     prob.close()
     print(json.dumps(res), flush=True)
 

@@ -171,8 +171,14 @@ typedef struct mq_run_stats {
   int32_t grid, block;         /* launch shape of the time-stepping kernel */
   double kernel_ms;            /* device time of the time-stepping launches */
   double total_ms;             /* wall time of the call */
-  double lat_p50_ms, lat_p99_ms, lat_max_ms; /* per-sample completion time after the first
-                                                instance started (device clock, last launch) */
+  double lat_p50_ms, lat_p99_ms, lat_max_ms; /* per-sample latency.  Level and multilevel runs:
+                                                from the call's start on the host until the
+                                                sample's Q (fine and coupled coarse) is readable
+                                                in host memory (each instance writes its Q and a
+                                                completion flag to coherent pinned memory, polled
+                                                by the calling thread).  Other runs: device-clock
+                                                completion after the first instance started, last
+                                                launch */
   double phase_ms[8];  /* resident-path phases summed over instances (one thread's clock):
                           multigrid fine descent, coarse levels, fine ascent, CG apply +
                           reductions; right-hand side, refinement residuals, increment

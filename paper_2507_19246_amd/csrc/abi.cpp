@@ -160,6 +160,9 @@ int check_finite(mq_problem* p, const double* x, size_t n) {
 
 struct RunOut {
   int status = MQ_OK;
+  // host time (now_ms) of the call's start: when > 0, run_instances reports
+  // latency as the time from it until a sample's Q is readable in host memory
+  double t_submit_ms = 0;
   std::vector<int> flags;  // FLAG_* bits per instance, appended by each run_instances call in its order
   double kernel_ms = 0;
   int grid = 0, block = 0;
@@ -363,6 +366,24 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   HIP_TRY(tmp_alloc(dstat, (size_t)nr * STAT_N, p->stream));
   HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)nr * STAT_N, p->stream));
   for (int i = 0; i < nr; ++i) run[i].stat = dstat.get() + STAT_N * i;
+  // host-visible completion records (coherent pinned memory)
+  HostDone* rec = nullptr;
+  if (ro->t_submit_ms > 0) {
+    if (p->done_cap < (size_t)nr) {
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      p->done_rec.reset();
+      p->done_cap = 0;
+      HostDone* h = nullptr;
+      HIP_TRY(hipHostMalloc((void**)&h, (size_t)nr * sizeof(HostDone), hipHostMallocCoherent | hipHostMallocMapped));
+      p->done_rec.reset(h);
+      p->done_cap = (size_t)nr;
+    }
+    rec = p->done_rec.get();
+    std::memset((void*)rec, 0, (size_t)nr * sizeof(HostDone));
+    HostDone* drec = nullptr;
+    HIP_TRY(hipHostGetDevicePointer((void**)&drec, rec, 0));
+    for (int i = 0; i < nr; ++i) run[i].host_done = drec + i;
+  }
   TmpPtr<Inst> dinst;
   HIP_TRY(tmp_alloc(dinst, nr, p->stream));
   HIP_TRY(hipMemcpyAsync(dinst.get(), run.data(), nr * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
@@ -380,6 +401,29 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     return rc;
   }
   HIP_TRY(hipEventRecord(e1, p->stream));
+  // host time at which each entry's record became visible (polled while the
+  // launch runs; the stream's end also ends the wait)
+  std::vector<double> seen;
+  if (rec) {
+    seen.assign(nr, -1.0);
+    int left = nr;
+    for (;;) {
+      for (int i = 0; i < nr; ++i)
+        if (seen[i] < 0 && __atomic_load_n(&rec[i].done, __ATOMIC_ACQUIRE)) {
+          seen[i] = now_ms();
+          --left;
+        }
+      if (left == 0) break;
+      const hipError_t q = hipStreamQuery(p->stream);
+      if (q != hipErrorNotReady) {
+        const double t = now_ms();
+        for (int i = 0; i < nr; ++i)
+          if (seen[i] < 0) seen[i] = t;
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
   std::vector<int> sh((size_t)nr * STAT_N);
   HIP_TRY(hipMemcpyAsync(sh.data(), dstat.get(), sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -396,15 +440,18 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   uint64_t t_first = ~0ull;
   for (int i = 0; i < nr; ++i) t_first = std::min(t_first, stamp(i, 0));
   {
-    std::vector<std::pair<int, uint64_t>> done;
-    for (int i = 0; i < nr; ++i) done.push_back({run[i].group, stamp(i, 1)});
+    // per group (sample): host-visible completion after the call's start, or
+    // device time after the first entry started
+    std::vector<std::pair<int, double>> done;
+    for (int i = 0; i < nr; ++i)
+      done.push_back({run[i].group, rec ? seen[i] - ro->t_submit_ms : (double)(stamp(i, 1) - t_first) / p->wall_khz});
     std::sort(done.begin(), done.end());
     std::vector<double> lat;
     for (size_t a = 0; a < done.size();) {
-      uint64_t e = 0;
+      double e = 0;
       size_t b = a;
       for (; b < done.size() && done[b].first == done[a].first; ++b) e = std::max(e, done[b].second);
-      lat.push_back((double)(e - t_first) / p->wall_khz);
+      lat.push_back(e);
       a = b;
     }
     if (st && !lat.empty()) {
@@ -714,6 +761,7 @@ static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_sampl
   std::vector<Inst> all = fine;
   all.insert(all.end(), coarse.begin(), coarse.end());
   RunOut ro;
+  ro.t_submit_ms = t0;
   rc = run_instances(p, all, st, &ro, nullptr);
   if (rc) return rc;
   last_flags().assign(ro.flags.begin(), ro.flags.end());  // fine 0..n-1, then coarse 0..n-1
@@ -759,6 +807,7 @@ static int multilevel_run_dev(mq_problem* p, int32_t n_levels, const mq_level_de
   std::stable_sort(keyed.begin(), keyed.end(), [](const Keyed& a, const Keyed& b) { return a.steps > b.steps; });
   for (auto& k : keyed) all.push_back(k.in);
   RunOut ro;
+  ro.t_submit_ms = t0;
   int rc = run_instances(p, all, st, &ro, nullptr);
   if (rc) return rc;
   std::vector<int32_t>& lf = last_flags();
@@ -1099,23 +1148,22 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
           up[k] = U(s, nn);
         }
       TmpPtr<const double*> dfp, dup;
-      TmpPtr<double> dj;
+      TmpPtr<double> dj, djmax;
+      const int na = (int)active.size();
       HIP_TRY(tmp_alloc(dfp, npair, p->stream));
       HIP_TRY(tmp_alloc(dup, npair, p->stream));
       HIP_TRY(tmp_alloc(dj, 2 * (size_t)npair, p->stream));
+      HIP_TRY(tmp_alloc(djmax, na, p->stream));
       HIP_TRY(copy_sync(dfp.get(), fp.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
       HIP_TRY(copy_sync(dup.get(), up.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
       HIP_TRY(launch_jumps(g, npair, dfp.get(), dup.get(), dj.get(), p->stream));
-      jump_host.assign(2 * (size_t)npair, 0.0);
-      HIP_TRY(hipMemcpyAsync(jump_host.data(), dj.get(), jump_host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(launch_jump_max(dj.get(), M - j, na, djmax.get(), p->stream));
+      jump_host.assign(na, 0.0);
+      HIP_TRY(hipMemcpyAsync(jump_host.data(), djmax.get(), na * sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIP_TRY(hipStreamSynchronize(p->stream));
       k = 0;
       for (int s : active) {
-        double J = 0.0;
-        for (int nn = j; nn < M; ++nn, ++k) {
-          const double r = jump_host[2 * k + 1] > 0 ? std::sqrt(jump_host[2 * k] / jump_host[2 * k + 1]) : std::sqrt(jump_host[2 * k]);
-          J = std::max(J, r);
-        }
+        const double J = jump_host[k++];
         const bool done = (pd->fixed_k == 0 && J <= pd->tol) || j == kcap;
         if (done) {
           Kout[s] = j;
@@ -1138,16 +1186,8 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
     rc = launch_chain(active, j + 1, false);
     if (rc) return rc;
   }
-  // Q = sum_n q_n / T in slice order (FP64, host)
-  std::vector<double> qh((size_t)S * M);
-  HIP_TRY(copy_sync(qh.data(), qn.get(), qh.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  std::vector<double> Q(S);
-  for (int s = 0; s < S; ++s) {
-    double acc = 0.0;
-    for (int nn = 0; nn < M; ++nn) acc += qh[(size_t)s * M + nn];
-    Q[s] = acc / T;
-  }
-  HIP_TRY(copy_sync(q, Q.data(), S * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  // Q = sum_n q_n / T in slice order (FP64, on the device)
+  HIP_TRY(launch_slice_qoi(qn.get(), M, S, T, q, p->stream));
   HIP_TRY(copy_sync(iters, Kout.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   if (final_state) {
     std::vector<const double*> fp(S);

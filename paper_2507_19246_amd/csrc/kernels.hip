@@ -234,6 +234,16 @@ __device__ inline void block_sum(double (&v)[NV], double* red, int& slot) {
 // CG uses the single-reduction recurrences of Chronopoulos and Gear (J. Comput.
 // Appl. Math. 25 (1989)): s = A p and w = A r are carried so each iteration
 // needs one stencil apply and one fused reduction of (r.r, w.r).
+// Completion record of a launch entry in coherent pinned host memory: the
+// value and flags first, then done with a system-scope release store, so a host
+// thread that sees done (acquire) also sees q.
+__device__ inline void publish_done(HostDone* hd, double q, int flags) {
+  if (!hd) return;
+  hd->q = q;
+  hd->flags = flags;
+  __hip_atomic_store(&hd->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <typename VT>
 __device__ inline VT vt(double x) { return (VT)x; }
 
@@ -1269,6 +1279,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         for (int q = 0; q < 8; ++q) in.stat[8 + q] = (int)(ph[q] >> 4);  // units of 16 ticks
         in.stat[16] = pic_total;
       }
+      publish_done(in.host_done, qsum * in.q_scale, flags);
     }
     __syncthreads();
   }
@@ -1688,6 +1699,44 @@ hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f, cons
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_jumps, dim3(n_pairs), dim3(256), 0, st, g, f, u, out2);
+  return hipGetLastError();
+}
+
+// Per sample of a Parareal sweep: the largest relative interface jump
+// max_n sqrt(|F_n - U_n|^2 / |F_n|^2) over its `per` consecutive pairs of
+// out2 (absolute where |F_n| = 0), in interface order.
+__global__ void k_jump_max(const double* __restrict__ out2, int per, int n_samples, double* __restrict__ jmax) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_samples) return;
+  double J = 0.0;
+  for (int k = s * per; k < (s + 1) * per; ++k) {
+    const double a = out2[2 * k], b = out2[2 * k + 1];
+    J = fmax(J, b > 0.0 ? sqrt(a / b) : sqrt(a));
+  }
+  jmax[s] = J;
+}
+
+hipError_t launch_jump_max(const double* out2, int per, int n_samples, double* jmax, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
+  if (n_samples == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jump_max, dim3((n_samples + 255) / 256), dim3(256), 0, st, out2, per, n_samples, jmax);
+  return hipGetLastError();
+}
+
+// Parareal QoI per sample: Q = (sum_n q_n) / T over its M slice sums in slice
+// order (FP64).
+__global__ void k_slice_qoi(const double* __restrict__ qn, int M, int n_samples, double T, double* __restrict__ q) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_samples) return;
+  double acc = 0.0;
+  for (int n = 0; n < M; ++n) acc += qn[(size_t)s * M + n];
+  q[s] = acc / T;
+}
+
+hipError_t launch_slice_qoi(const double* qn, int M, int n_samples, double T, double* q, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
+  if (n_samples == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_qoi, dim3((n_samples + 255) / 256), dim3(256), 0, st, qn, M, n_samples, T, q);
   return hipGetLastError();
 }
 
@@ -2117,6 +2166,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
         in.stat[6] = (int)(t_end & 0xffffffffull);
         in.stat[7] = (int)(t_end >> 32);
       }
+      publish_done(in.host_done, qsum * in.q_scale, flags);
     }
     __syncthreads();
   }

@@ -99,6 +99,17 @@ struct Inst {
   // one with dep_done sets that flag once its a_out and carry are written.
   const int* dep_wait;
   int* dep_done;
+  // Completion record in coherent pinned host memory (null: none), written
+  // by the entry's last action so that the host sees Q as soon as it exists.
+  struct HostDone* host_done;
+};
+
+// One launch entry's completion as the host sees it: the kernel stores q and
+// flags, then sets done with a system-scope release store.
+struct HostDone {
+  double q;
+  int flags;
+  int done;
 };
 
 // Longest wait of a piece for its predecessor, 5 s of the device wall clock
@@ -201,6 +212,10 @@ hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double
                               const double* const* qc, double* out, hipStream_t st);
 hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
                         const double* const* u, double* out2, hipStream_t st);
+// per sample: the largest relative jump over its `per` consecutive (|F-U|^2, |F|^2) pairs
+hipError_t launch_jump_max(const double* out2, int per, int n_samples, double* jmax, hipStream_t st);
+// per sample: Q = (sum of its M slice sums, in order) / T
+hipError_t launch_slice_qoi(const double* qn, int M, int n_samples, double T, double* q, hipStream_t st);
 // Row-sum lumping of the mass planes of n_samples tables (mass = MQ_MASS_LUMPED).
 hipError_t launch_lump_mass(const Geom& g, int n_samples, double* tables, hipStream_t st);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);

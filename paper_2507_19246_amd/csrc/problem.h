@@ -46,6 +46,15 @@ hipError_t dev_alloc(DevPtr<T>& out, size_t count) {
   return e;
 }
 
+// Pinned host allocation owned by a unique_ptr.
+struct PinnedFree {
+  void operator()(void* p) const {
+    if (p) (void)hipHostFree(p);
+  }
+};
+template <class T>
+using PinPtr = std::unique_ptr<T, PinnedFree>;
+
 // Per-call device buffer, allocated and freed in the order of one stream
 // (hipMallocAsync / hipFreeAsync): unlike hipFree, releasing it does not wait
 // for the work of other streams, so calls on different streams overlap.
@@ -108,6 +117,10 @@ struct mq_problem {
   // start state a_0 of later runs on the full grid (zero boundary ring), set by
   // mq_set_initial_state; empty: a_0 = 0
   mq::DevPtr<double> a0;
+  // completion records of the last launch's entries (coherent pinned host
+  // memory, grown on demand; see HostDone)
+  mq::PinPtr<mq::HostDone> done_rec;
+  size_t done_cap = 0;
   // second set-up of the same problem on a stream of its own (combined runs)
   mq_problem* twin = nullptr;
   hipStream_t twin_stream = nullptr;
