@@ -276,6 +276,26 @@ int mq_set_initial_state(mq_problem* p, const double* a0);
 int mlmc_level_run(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
                    double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st);
 
+/* Allocation-free form of mlmc_level_run, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * errors as mlmc_level_run (results bitwise equal); every per-call buffer
+ * (sample tables, source tables, instance table, statistics, the persistent
+ * kernel's work slots) is carved from a fixed device workspace of
+ * MQ_NOALLOC_WORKSPACE_BYTES that the library holds on each device it runs on
+ * until the process ends; the call makes no hipMalloc/hipFree or other
+ * allocation (its instances are never split into pieces, and kernel_ms is
+ * taken with the host clock).  The work slots are as many as fit after the
+ * inputs, so a large batch may run on fewer than all compute units.
+ * Limits: a run whose inputs plus one work slot exceed the workspace returns
+ * MQ_ERR_INVALID_ARG before any launch; the wide path is refused; the handle
+ * must take device pointers.  Every call on a device shares that device's
+ * workspace, which keeps the last call's contents: calls that overlap on one
+ * device (other threads or streams) race and must be serialised by the caller. */
+#define MQ_NOALLOC_WORKSPACE_BYTES 268435456 /* 256 MiB */
+int mlmc_level_run_noalloc(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                           double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st);
+
 /* Several levels in ONE persistent launch (instances of all levels share the
  * device work queue, longest first).  lv, n_samples, xi, q_fine, q_coarse are
  * host arrays of n_levels entries; the pointers inside are device pointers as

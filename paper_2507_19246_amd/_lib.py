@@ -27,6 +27,7 @@ MQ_APPLY_A, MQ_APPLY_M, MQ_APPLY_K = 0, 1, 2
 MQ_PATH_AUTO, MQ_PATH_RESIDENT, MQ_PATH_STREAMING, MQ_PATH_WIDE = 0, 1, 2, 3
 MQ_PRECOND_AUTO, MQ_PRECOND_JACOBI, MQ_PRECOND_MULTIGRID = 0, 1, 2
 MQ_MEM_DEVICE, MQ_MEM_HOST = 0, 1
+MQ_NOALLOC_WORKSPACE_BYTES = 268435456
 MQ_MASS_CONSISTENT, MQ_MASS_LUMPED = 0, 1
 MQ_FLAG_NOT_CONVERGED, MQ_FLAG_FAILED, MQ_FLAG_PICARD_CAP, MQ_FLAG_PARAREAL_KMAX = 1, 2, 4, 8
 
@@ -154,6 +155,8 @@ SIGNATURES = {
     "mq_problem_info_get": (C.c_int, [VP, C.POINTER(ProblemInfo)]),
     "mq_set_initial_state": (C.c_int, [VP, VP]),
     "mlmc_level_run": (C.c_int, [VP, C.POINTER(LevelDesc), C.c_int32, VP, VP, VP, VP, C.POINTER(RunStats)]),
+    "mlmc_level_run_noalloc": (C.c_int, [VP, C.POINTER(LevelDesc), C.c_int32, VP, VP, VP, VP,
+                                         C.POINTER(RunStats)]),
     "mlmc_multilevel_run": (C.c_int, [VP, C.c_int32, C.POINTER(LevelDesc), C.POINTER(C.c_int32),
                                       C.POINTER(VP), C.POINTER(VP), C.POINTER(VP), C.POINTER(RunStats)]),
     "parareal_run": (C.c_int, [VP, C.POINTER(PararealDesc), C.c_int32, VP, VP, VP, VP, C.POINTER(RunStats)]),

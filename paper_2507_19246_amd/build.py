@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmq.so")
 ARCH = os.environ.get("MQ_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["kernels.hip", "mass.hip"]
+HIP_SOURCES = ["kernels.hip", "mass.hip", "noalloc.hip"]
 HOST_SOURCES = ["abi.cpp", "setup.cpp", "serve.cpp", "wide.cpp", "costmodel.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-mcode-object-version=5",

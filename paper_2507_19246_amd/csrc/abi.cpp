@@ -84,15 +84,21 @@ size_t max_slots(const mq_problem* p) {
   return (size_t)p->num_cu * per_cu;
 }
 
-int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block) {
+int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block, double* work,
+                      size_t work_slots) {
+  if (!work) {
+    work = p->work.get();
+    work_slots = p->work_slots;
+  }
   size_t slots = std::min<size_t>((size_t)n, max_slots(p));
   if (p->grid_cap > 0) slots = std::min<size_t>(slots, (size_t)p->grid_cap);
-  if (p->work_slots < slots) return fail(MQ_ERR_INVALID_ARG, "work buffer smaller than the launch");
+  slots = std::min(slots, work_slots);
+  if (slots < 1) return fail(MQ_ERR_INVALID_ARG, "work buffer smaller than the launch");
   HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
   const Solver sv = solver_of(p);
   // the slot layout of the work buffer is fixed by its allocation (work_slots);
   // the grid is the occupancy-limited slot count
-  hipError_t le = launch_ie(p->hm.g, p->mg, sv, dinst, n, p->dcounter.get(), p->work.get(), (int)p->work_slots,
+  hipError_t le = launch_ie(p->hm.g, p->mg, sv, dinst, n, p->dcounter.get(), work, (int)work_slots,
                             (int)slots, p->dS.get(), p->path, p->d.precision, p->hm.cr, p->dcond.get(), p->mat,
                             grid, block, p->stream);
   if (le != hipSuccess) return fail(MQ_ERR_DEVICE, std::string("time-stepping launch: ") + hipGetErrorString(le));
@@ -344,11 +350,16 @@ int plan_split(mq_problem* p, const std::vector<Inst>& insts, Split& out, bool* 
   return MQ_OK;
 }
 
+// fixed (nullable): a CallMem over a fixed region; the launch then takes its
+// instance table, statistics and work slots from it (as many slots as fit),
+// splits nothing, creates no events and allocates nothing.
 int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, RunOut* ro,
-                  std::vector<int>* stat_host) {
+                  std::vector<int>* stat_host, CallMem* fixed = nullptr) {
   const int n = (int)insts.size();
   if (n == 0) return MQ_OK;
+  if (fixed && !fixed->fixed()) fixed = nullptr;
   if (p->path == MQ_PATH_WIDE) {
+    if (fixed) return fail(MQ_ERR_INVALID_ARG, "the wide path allocates its own workspace");
     (void)stat_host;
     int status = MQ_OK;
     const int rc = run_wide(p, insts, st, &status, &ro->flags);
@@ -358,17 +369,20 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   }
   Split spl;
   bool split = false;
-  int rc = stat_host ? MQ_OK : plan_split(p, insts, spl, &split);
+  int rc = (stat_host || fixed) ? MQ_OK : plan_split(p, insts, spl, &split);
   if (rc) return rc;
   std::vector<Inst>& run = split ? spl.pieces : insts;
   const int nr = (int)run.size();
-  TmpPtr<int> dstat;
-  HIP_TRY(tmp_alloc(dstat, (size_t)nr * STAT_N, p->stream));
-  HIP_TRY(launch_fill_zero_i(dstat.get(), (size_t)nr * STAT_N, p->stream));
-  for (int i = 0; i < nr; ++i) run[i].stat = dstat.get() + STAT_N * i;
+  CallMem own;
+  own.use_stream(p->stream);
+  CallMem& mem = fixed ? *fixed : own;
+  int* dstat = nullptr;
+  HIP_TRY(mem.get(dstat, (size_t)nr * STAT_N));
+  HIP_TRY(launch_fill_zero_i(dstat, (size_t)nr * STAT_N, p->stream));
+  for (int i = 0; i < nr; ++i) run[i].stat = dstat + STAT_N * i;
   // host-visible completion records (coherent pinned memory)
   HostDone* rec = nullptr;
-  if (ro->t_submit_ms > 0) {
+  if (ro->t_submit_ms > 0 && !fixed) {
     if (p->done_cap < (size_t)nr) {
       HIP_TRY(hipStreamSynchronize(p->stream));
       p->done_rec.reset();
@@ -384,23 +398,42 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     HIP_TRY(hipHostGetDevicePointer((void**)&drec, rec, 0));
     for (int i = 0; i < nr; ++i) run[i].host_done = drec + i;
   }
-  TmpPtr<Inst> dinst;
-  HIP_TRY(tmp_alloc(dinst, nr, p->stream));
-  HIP_TRY(hipMemcpyAsync(dinst.get(), run.data(), nr * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
-  const size_t slots = std::min<size_t>((size_t)nr, max_slots(p));
-  rc = ensure_work(p, slots);
-  if (rc) return rc;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, p->stream));
-  rc = launch_persistent(p, dinst.get(), nr, &ro->grid, &ro->block);
+  Inst* dinst = nullptr;
+  HIP_TRY(mem.get(dinst, nr));
+  HIP_TRY(hipMemcpyAsync(dinst, run.data(), nr * sizeof(Inst), hipMemcpyHostToDevice, p->stream));
+  size_t slots = std::min<size_t>((size_t)nr, max_slots(p));
+  double* fwork = nullptr;
+  if (fixed) {
+    // as many work slots as the region has left (zeroed: the kernels rely on a
+    // zero boundary ring, and the region holds whatever the last call left)
+    const size_t sd = slot_doubles(p);
+    slots = std::min(slots, mem.left() / CallMem::rounded(sd * sizeof(double)));
+    if (slots < 1) return fail(MQ_ERR_INVALID_ARG, "the fixed workspace has no room for a work slot");
+    HIP_TRY(mem.get(fwork, slots * sd));
+    HIP_TRY(launch_fill_zero(fwork, slots * sd, p->stream));
+  } else {
+    rc = ensure_work(p, slots);
+    if (rc) return rc;
+  }
+  // launch timing: events on the stream, or (fixed) the host clock around the
+  // launch and the stream's end
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double t_launch = 0;
+  if (!fixed) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, p->stream));
+  } else {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    t_launch = now_ms();
+  }
+  rc = launch_persistent(p, dinst, nr, &ro->grid, &ro->block, fwork, fixed ? slots : 0);
   if (rc) {
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     return rc;
   }
-  HIP_TRY(hipEventRecord(e1, p->stream));
+  if (e1) HIP_TRY(hipEventRecord(e1, p->stream));
   // host time at which each entry's record became visible (polled while the
   // launch runs; the stream's end also ends the wait)
   std::vector<double> seen;
@@ -425,12 +458,18 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     }
   }
   std::vector<int> sh((size_t)nr * STAT_N);
-  HIP_TRY(hipMemcpyAsync(sh.data(), dstat.get(), sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
   float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (fixed) {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    ms = (float)(now_ms() - t_launch);
+  }
+  HIP_TRY(hipMemcpyAsync(sh.data(), dstat, sh.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (!fixed) {
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   ro->kernel_ms += ms;
   // per-entry device wall-clock stamps -> per-group completion latency
   auto stamp = [&](int i, int w) {
@@ -500,17 +539,27 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   return MQ_OK;
 }
 
-int assemble(mq_problem* p, const double* xi, int n, TmpPtr<double>& tables) {
+// Assemble the tables of n samples into `tables` ([n][tab_stride], device).
+int assemble_into(mq_problem* p, const double* xi, int n, double* tables) {
   const Geom& g = p->hm.g;
-  HIP_TRY(tmp_alloc(tables, (size_t)n * tab_stride(g), p->stream));
   HIP_TRY(launch_assemble(g, p->hm.cr, p->dcond.get(), p->dkl.get(), p->hm.n_modes, p->d.material, xi,
-                          p->n_xi, n, p->mat, tables.get(), p->stream));
-  if (p->d.mass == MQ_MASS_LUMPED) HIP_TRY(launch_lump_mass(g, n, tables.get(), p->stream));
+                          p->n_xi, n, p->mat, tables, p->stream));
+  if (p->d.mass == MQ_MASS_LUMPED) HIP_TRY(launch_lump_mass(g, n, tables, p->stream));
   return MQ_OK;
 }
 
+int assemble(mq_problem* p, const double* xi, int n, TmpPtr<double>& tables) {
+  HIP_TRY(tmp_alloc(tables, (size_t)n * tab_stride(p->hm.g), p->stream));
+  return assemble_into(p, xi, n, tables.get());
+}
+
+// Inputs of one level run; `mem` owns them (or slices a fixed region).
 struct LevelBufs {
-  TmpPtr<double> tables, src_f, src_c, afull;
+  CallMem mem;
+  double* tables = nullptr;
+  double* src_f = nullptr;
+  double* src_c = nullptr;
+  double* afull = nullptr;
   std::vector<double*> afull_ptr;
 };
 
@@ -529,34 +578,36 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
   if (nf > (1 << 24) || nc > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
   int rc = check_finite(p, xi, (size_t)n * p->n_xi);
   if (rc) return rc;
-  rc = assemble(p, xi, n, lb.tables);
-  if (rc) return rc;
+  if (!lb.mem.fixed()) lb.mem.use_stream(p->stream);
   const Geom& g = p->hm.g;
+  HIP_TRY(lb.mem.get(lb.tables, (size_t)n * tab_stride(g)));
+  rc = assemble_into(p, xi, n, lb.tables);
+  if (rc) return rc;
   const double T = lv->n_periods / p->d.freq;
   const double dtf = 1.0 / (p->d.freq * lv->steps_per_period);
   auto sf = source_table(p->d, dtf, (int)nf);
-  HIP_TRY(tmp_alloc(lb.src_f, sf.size(), p->stream));
-  HIP_TRY(hipMemcpyAsync(lb.src_f.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(lb.mem.get(lb.src_f, sf.size()));
+  HIP_TRY(hipMemcpyAsync(lb.src_f, sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   double dtc = 0;
   if (nc > 0) {
     dtc = 1.0 / (p->d.freq * lv->coarse_steps_per_period);
     auto sc = source_table(p->d, dtc, (int)nc);
-    HIP_TRY(tmp_alloc(lb.src_c, sc.size(), p->stream));
-    HIP_TRY(hipMemcpyAsync(lb.src_c.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(lb.mem.get(lb.src_c, sc.size()));
+    HIP_TRY(hipMemcpyAsync(lb.src_c, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
     // the copy's host vector must outlive the async copy
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
   const size_t FS = (size_t)g.N * g.P;
   if (want_state) {
-    HIP_TRY(tmp_alloc(lb.afull, FS * n, p->stream));
+    HIP_TRY(lb.mem.get(lb.afull, FS * n));
     lb.afull_ptr.resize(n);
-    for (int s = 0; s < n; ++s) lb.afull_ptr[s] = lb.afull.get() + FS * s;
+    for (int s = 0; s < n; ++s) lb.afull_ptr[s] = lb.afull + FS * s;
   }
   for (int s = 0; s < n; ++s) {
     Inst in{};
-    in.tab = lb.tables.get() + (size_t)s * tab_stride(g);
-    in.src = lb.src_f.get();
+    in.tab = lb.tables + (size_t)s * tab_stride(g);
+    in.src = lb.src_f;
     in.a_init = p->a0.get();  // null: a_0 = 0
     in.a_out = want_state ? lb.afull_ptr[s] : nullptr;
     in.q_out = qf + s;
@@ -568,7 +619,7 @@ int prepare_level(mq_problem* p, const mq_level_desc* lv, int n, const double* x
     fine.push_back(in);
     if (nc > 0) {
       Inst ic = in;
-      ic.src = lb.src_c.get();
+      ic.src = lb.src_c;
       ic.a_out = nullptr;
       ic.q_out = qc + s;
       ic.dt = dtc;
@@ -680,6 +731,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
   }
   HIP_TRY(dev_alloc(p->dcounter, 1));
   HIP_TRY(dev_alloc(p->dflag, 1));
+  HIP_TRY(noalloc_workspace(p->device, &p->scratch));
   (void)g;
   *out = p.release();
   return MQ_OK;
@@ -748,32 +800,51 @@ int mq_problem_info_get(const mq_problem* p, mq_problem_info* info) {
   return MQ_OK;
 }
 
+// region (nullable): take every per-call buffer from this fixed device region
+// instead of allocating (the allocation-free entry point).
 static int level_run_dev(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
-                         double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+                         double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st,
+                         char* region = nullptr, size_t region_bytes = 0) {
   last_flags().clear();
   if (!p) return fail(MQ_ERR_INVALID_ARG, "null problem");
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
   LevelBufs lb;
+  if (region) lb.mem.use_region(region, region_bytes);
   std::vector<Inst> fine, coarse;
   int rc = prepare_level(p, lv, n_samples, xi, q_fine, q_coarse, final_state != nullptr, lb, fine, coarse, 0);
   if (rc) return rc;
+  double** dptr = nullptr;
+  if (final_state) HIP_TRY(lb.mem.get(dptr, lb.afull_ptr.size()));
   std::vector<Inst> all = fine;
   all.insert(all.end(), coarse.begin(), coarse.end());
   RunOut ro;
-  ro.t_submit_ms = t0;
-  rc = run_instances(p, all, st, &ro, nullptr);
+  if (!region) ro.t_submit_ms = t0;
+  rc = run_instances(p, all, st, &ro, nullptr, region ? &lb.mem : nullptr);
   if (rc) return rc;
   last_flags().assign(ro.flags.begin(), ro.flags.end());  // fine 0..n-1, then coarse 0..n-1
   if (final_state) {
-    TmpPtr<double*> dptr;
-    HIP_TRY(tmp_alloc(dptr, lb.afull_ptr.size(), p->stream));
-    HIP_TRY(hipMemcpyAsync(dptr.get(), lb.afull_ptr.data(), lb.afull_ptr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(launch_to_interior(p->hm.g, n_samples, dptr.get(), final_state, p->stream));
+    HIP_TRY(hipMemcpyAsync(dptr, lb.afull_ptr.data(), lb.afull_ptr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(launch_to_interior(p->hm.g, n_samples, dptr, final_state, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
   if (st) st->total_ms = now_ms() - t0;
   return ro.status;
+}
+
+// Bytes that a level run takes from the fixed workspace before its work slots
+// (the slices level_run_dev carves, in its order), plus one work slot.
+static size_t noalloc_need(const mq_problem* p, int64_t n, int64_t nf, int64_t nc, bool state) {
+  const Geom& g = p->hm.g;
+  const size_t FS = (size_t)g.N * g.P;
+  const int64_t n_inst = nc > 0 ? 2 * n : n;
+  size_t b = CallMem::rounded(n * tab_stride(g) * sizeof(double));
+  b += CallMem::rounded((nf + 1) * sizeof(double));
+  if (nc > 0) b += CallMem::rounded((nc + 1) * sizeof(double));
+  if (state) b += CallMem::rounded(FS * n * sizeof(double)) + CallMem::rounded(n * sizeof(double*));
+  b += CallMem::rounded(n_inst * STAT_N * sizeof(int)) + CallMem::rounded(n_inst * sizeof(Inst));
+  b += CallMem::rounded(slot_doubles(p) * sizeof(double));
+  return b;
 }
 
 static int multilevel_run_dev(mq_problem* p, int32_t n_levels, const mq_level_desc* lv,
@@ -1438,6 +1509,28 @@ int mq_debug_apply(mq_problem* p, int32_t which, double dt, int32_t n, const dou
   HIP_TRY(launch_apply(p->hm.g, which, dt, tables.get(), n, x, y, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return MQ_OK;
+}
+
+int mlmc_level_run_noalloc(mq_problem* p, const mq_level_desc* lv, int32_t n_samples, const double* xi,
+                           double* q_fine, double* q_coarse, double* final_state, mq_run_stats* st) {
+  last_flags().clear();
+  if (int rh = refuse_host(p)) return rh;
+  if (!p || !lv) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "the wide path allocates its own workspace");
+  if (!p->scratch) return fail(MQ_ERR_DEVICE, "the fixed workspace of this device was not found at set-up");
+  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  if (lv->steps_per_period < 1 || lv->n_periods < 1 || lv->coarse_steps_per_period < 0)
+    return fail(MQ_ERR_INVALID_ARG, "steps_per_period, n_periods >= 1 and coarse_steps_per_period >= 0 required");
+  const int64_t nf = (int64_t)lv->steps_per_period * lv->n_periods;
+  const int64_t nc = (int64_t)lv->coarse_steps_per_period * lv->n_periods;
+  if (nf > (1 << 24) || nc > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
+  const size_t need = noalloc_need(p, n_samples, nf, nc, final_state != nullptr);
+  if (need > (size_t)MQ_NOALLOC_WORKSPACE_BYTES)
+    return fail(MQ_ERR_INVALID_ARG, "the run needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                        std::to_string((size_t)MQ_NOALLOC_WORKSPACE_BYTES) +
+                                        " of the allocation-free call (use mlmc_level_run or fewer samples)");
+  return level_run_dev(p, lv, n_samples, xi, q_fine, q_coarse, final_state, st, p->scratch,
+                       (size_t)MQ_NOALLOC_WORKSPACE_BYTES);
 }
 
 // ---- host-pointer forms (mem_kind = MQ_MEM_HOST): inputs copied to per-call

@@ -212,6 +212,9 @@ hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double
                               const double* const* qc, double* out, hipStream_t st);
 hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
                         const double* const* u, double* out2, hipStream_t st);
+// Device address of the allocation-free call's workspace on `device` (looked
+// up once per device with that device current; noalloc.hip).
+hipError_t noalloc_workspace(int device, char** ptr);
 // per sample: the largest relative jump over its `per` consecutive (|F-U|^2, |F|^2) pairs
 hipError_t launch_jump_max(const double* out2, int per, int n_samples, double* jmax, hipStream_t st);
 // per sample: Q = (sum of its M slice sums, in order) / T

@@ -75,6 +75,44 @@ hipError_t tmp_alloc(TmpPtr<T>& out, size_t count, hipStream_t s) {
   return e;
 }
 
+// Per-call device memory: stream-ordered allocations that live as long as this
+// object, or consecutive 256-byte-aligned slices of a fixed region (then
+// nothing is allocated: the allocation-free entry point).
+class CallMem {
+ public:
+  void use_stream(hipStream_t s) { s_ = s; }
+  void use_region(char* base, size_t cap) {
+    base_ = base;
+    cap_ = cap;
+    used_ = 0;
+  }
+  bool fixed() const { return base_ != nullptr; }
+  size_t left() const { return cap_ - used_; }
+  static size_t rounded(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+  template <class T>
+  hipError_t get(T*& out, size_t count) {
+    const size_t bytes = rounded((count > 0 ? count : 1) * sizeof(T));
+    if (base_) {
+      if (bytes > cap_ - used_) return hipErrorOutOfMemory;
+      out = reinterpret_cast<T*>(base_ + used_);
+      used_ += bytes;
+      return hipSuccess;
+    }
+    TmpPtr<char> t;
+    const hipError_t e = tmp_alloc(t, bytes, s_);
+    if (e != hipSuccess) return e;
+    out = reinterpret_cast<T*>(t.get());
+    owned_.push_back(std::move(t));
+    return hipSuccess;
+  }
+
+ private:
+  hipStream_t s_ = nullptr;
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::vector<TmpPtr<char>> owned_;
+};
+
 // Copy ordered on stream s, complete when it returns.
 inline hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
@@ -121,6 +159,9 @@ struct mq_problem {
   // memory, grown on demand; see HostDone)
   mq::PinPtr<mq::HostDone> done_rec;
   size_t done_cap = 0;
+  // this device's fixed workspace of the allocation-free entry point
+  // (MQ_NOALLOC_WORKSPACE_BYTES, shared by every handle on the device)
+  char* scratch = nullptr;
   // second set-up of the same problem on a stream of its own (combined runs)
   mq_problem* twin = nullptr;
   hipStream_t twin_stream = nullptr;
@@ -140,7 +181,9 @@ std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_tota
 // Launch one persistent time-stepping kernel over the device instance table
 // `dinst` on p->stream without waiting.  The work buffer must already hold
 // min(n, max_slots(p)) slots.
-int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block);
+// work (nullable): use these work_slots slots instead of the handle's work buffer.
+int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block, double* work = nullptr,
+                      size_t work_slots = 0);
 // Wide path (wide.cpp): run the instances one after the other over the whole device.
 // flags (nullable): receives one entry of FLAG_* bits per instance, in insts order
 int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status, std::vector<int>* flags);
