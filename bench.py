@@ -518,6 +518,19 @@ def _serve(mq, L, W, np, torch, reqs, limit_s, label, wide_min_nodes=0, wide_loa
     srv.close()
     lat = np.array([(r.t_done_ns - r.t_submit_ns) / 1e6 for r in done.values()])
     steps = sum(reqs[r.user_id].steps_per_period * reqs[r.user_id].n_periods for r in done.values())
+    # algorithmic bytes of the work done (same per-DoF figures as the batched lines)
+    alg = {}
+    for r in done.values():
+        q = reqs[r.user_id]
+        nd = (q.n_nodes - 2) ** 2
+        st_ = q.steps_per_period * q.n_periods
+        b = nd * (ALG_BYTES_CG_ITER_FP32 * r.inner_iters + ALG_BYTES_FP64_RESIDUAL * (r.sweeps + st_)
+                  + ALG_BYTES_STEP * st_)
+        a = alg.setdefault(q.n_nodes, {"bytes": 0.0, "steps": 0, "cg_iters": 0, "wide": 0})
+        a["bytes"] += b
+        a["steps"] += st_
+        a["cg_iters"] += r.inner_iters
+        a["wide"] += int(r.path == L.MQ_PATH_WIDE)
     by_mesh = {}
     for r in done.values():
         by_mesh.setdefault(reqs[r.user_id].n_nodes, []).append((r.t_done_ns - r.t_submit_ns) / 1e6)
@@ -527,6 +540,7 @@ def _serve(mq, L, W, np, torch, reqs, limit_s, label, wide_min_nodes=0, wide_loa
         "failed": sum(1 for r in done.values() if r.status < 0),
         "latency_ms_by_mesh": {str(k): {"n": len(v), "p50": float(np.percentile(v, 50)),
                                         "p99": float(np.percentile(v, 99))} for k, v in sorted(by_mesh.items())},
+        "algorithmic": alg,
     }
 
 
@@ -553,9 +567,61 @@ def bench_serving(args, mq, L, W, np, torch):
                     args.serving_limit_s, "stable load", args.wide_min_nodes, args.wide_load_limit)
         st["rate_req_per_s"] = rate
         st["requests"] = args.stable_requests
+        st.pop("algorithmic", None)
         res["stable_load"] = st
-    res.update({"roofline": None, "cpu_baseline": None})
+    alg = sat["algorithmic"]
+    tot = sum(a["bytes"] for a in alg.values())
+    gbs = tot / sat["wall_s"] / 1e9
+    res["roofline"] = {
+        "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+        "traffic": None, "kernel": "k_ie_resident (65, 129), k_ie_stream (257, 513 batched), k_w_* (513 wide lane)",
+        "scope": "whole job: algorithmic bytes of all served requests over the run's wall time (launches of "
+                 "several lanes overlap, so per-launch durations do not add up to it)",
+        "bytes_per_dof": {"fp32_cg_iteration": ALG_BYTES_CG_ITER_FP32, "fp64_residual": ALG_BYTES_FP64_RESIDUAL,
+                          "time_step": ALG_BYTES_STEP},
+        "by_mesh": {str(k): {"algorithmic_bytes": a["bytes"], "sample_steps": a["steps"],
+                             "cg_iters_per_step": a["cg_iters"] / max(1, a["steps"]), "wide_lane_requests": a["wide"],
+                             "share_of_bytes": a["bytes"] / tot} for k, a in sorted(alg.items())}}
+    res["cpu_baseline"] = None if args.no_cpu_baseline else serving_cpu_baseline(reqs)
     return res
+
+
+def _serving_oracle_task(args):
+    n_nodes, xi, spp = args
+    import workloads as W
+    from oracle import timestep
+    prob = W.Problem(n_nodes, W.Material(kind=W.MAT_KL))
+    t = time.perf_counter()
+    timestep.solve_sample(prob, xi, spp, 1)
+    return n_nodes, spp, time.perf_counter() - t
+
+
+def serving_cpu_baseline(reqs, per_mesh=((65, 4), (129, 2), (257, 1), (513, 1)), spp=64):
+    """Oracle on a bounded sample of the stream: per mesh size, its first requests
+    run for one period at 64 steps per period (one factorisation, 64 solves); the
+    per-core rate of each mesh size is applied to every request of the stream."""
+    import numpy as np
+    tasks = []
+    for n_nodes, k in per_mesh:
+        mine = [r for r in reqs if r.n_nodes == n_nodes][:k]
+        tasks += [(n_nodes, np.asarray(r.xi), spp) for r in mine]
+    out, wall, cores = _oracle_pool(tasks, _serving_oracle_task)
+    per_core = {}
+    for n_nodes, s_, t in out:
+        a = per_core.setdefault(n_nodes, [0, 0.0])
+        a[0] += s_
+        a[1] += t
+    rate = {n: a[0] / a[1] for n, a in per_core.items()}
+    steps = sum(r.steps_per_period * r.n_periods for r in reqs)
+    core_s = sum(r.steps_per_period * r.n_periods / rate[r.n_nodes] for r in reqs)
+    return {"value": cores * steps / core_s, "unit": "sample-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"per mesh size the first {dict(per_mesh)} requests of the stream, one period at {spp} steps "
+                      f"per period each ({sum(a[1] for a in per_core.values()):.1f} core-s, banded-Cholesky FP64); "
+                      "the measured per-core rate of each mesh size applied to all requests (factorisation "
+                      "amortised over 64 steps: an upper bound on the oracle's time for longer requests), spread "
+                      "over the cores",
+            "per_core_sample_steps_per_s": {str(n): r_ for n, r_ in sorted(rate.items())},
+            "extrapolated_stream_core_s": core_s}
 
 
 def main():
@@ -575,7 +641,7 @@ def main():
                     choices=["mlmc3", "parareal", "nonlinear", "serving", "adaptive", "combined"])
     ap.add_argument("--para-tol", type=float, default=1e-8, help="combined: Parareal jump tolerance")
     ap.add_argument("--target-rmse", type=float, default=50.0, help="adaptive: target RMSE of the estimate (W/m)")
-    ap.add_argument("--requests", type=int, default=512, help="serving: requests taken from the stream")
+    ap.add_argument("--requests", type=int, default=4096, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--wide-min-nodes", type=int, default=0,
                     help="serving: smallest mesh of the wide lane (0: the library default 513; -1: no wide lane)")
@@ -583,7 +649,7 @@ def main():
                     help="serving: batched requests above which the wide lane is not used (0: library default)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="serving: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0: leave as set)")
-    ap.add_argument("--serving-limit-s", type=float, default=420.0, help="serving: wall-clock cap of the run")
+    ap.add_argument("--serving-limit-s", type=float, default=720.0, help="serving: wall-clock cap of the run")
     ap.add_argument("--no-serial", action="store_true", help="parareal: skip the batched serial comparison run")
     ap.add_argument("--coarse-steps", type=int, default=0,
                     help="parareal: coarse IE steps per slice (0: the workload's 1; 8 = the level L-2 grid)")

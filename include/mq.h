@@ -179,10 +179,11 @@ typedef struct mq_run_stats {
                                                 by the calling thread).  Other runs: device-clock
                                                 completion after the first instance started, last
                                                 launch */
-  double phase_ms[8];  /* resident-path phases summed over instances (one thread's clock):
-                          multigrid fine descent, coarse levels, fine ascent, CG apply +
-                          reductions; right-hand side, refinement residuals, increment
-                          updates, QoI + state update */
+  double phase_ms[8];  /* resident and streaming paths: phases summed over instances (one
+                          thread's clock): multigrid fine descent (pre-smoothing), restriction +
+                          coarse levels, fine ascent (prolongation + post-smoothing), CG apply +
+                          updates + reductions; right-hand side, refinement residuals,
+                          increment updates, QoI + state update */
   double busy_ms;      /* sum over instances of their device time (start to end) */
   int64_t n_pieces;    /* launch entries when instances ran as dependent pieces (split_steps),
                           else 0 */
@@ -475,7 +476,9 @@ typedef struct mq_result {
   int32_t status;            /* MQ_OK, MQ_WARN_NOT_CONVERGED, or an error: MQ_ERR_BUSY when the
                                 request alone does not fit the budget, MQ_ERR_NONFINITE when
                                 the solve produced NaN/Inf, MQ_ERR_DEVICE / _OUT_OF_MEMORY */
-  int32_t inner_iters;
+  int32_t inner_iters;       /* inner CG iterations, summed over the request's steps */
+  int32_t sweeps;            /* refinement sweeps, summed over the request's steps */
+  int32_t path;              /* MQ_PATH_RESIDENT / _STREAMING (batched lane) or MQ_PATH_WIDE */
   int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock ns: mq_submit, first launch,
                                                  QoI copied to the host */
   char message[64];          /* status < 0: what failed (NUL-terminated, truncated) */

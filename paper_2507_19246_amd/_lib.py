@@ -109,7 +109,7 @@ class Request(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("user_id", C.c_uint64), ("q", C.c_double),
-                ("status", C.c_int32), ("inner_iters", C.c_int32),
+                ("status", C.c_int32), ("inner_iters", C.c_int32), ("sweeps", C.c_int32), ("path", C.c_int32),
                 ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64),
                 ("message", C.c_char * 64)]
 

@@ -11,6 +11,7 @@
 #include <queue>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "problem.h"
@@ -1088,6 +1089,24 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
   return status;
 }
 
+// Parareal (Section II-C, Eq. (12)) for n_samples samples in ONE persistent
+// launch.  The launch's work queue holds, per sample, the initial coarse chain,
+// then per iteration j = 1..kcap the fine slices n = j..M and the coarse chain
+// of iteration j, which first takes the stopping decision from the interface
+// jumps of Section II-C and then corrects U_n = F_n + (C_new - C_old), n =
+// j+1..M-1.  Entries wait on flags in device memory:
+//   fine (j, n)   waits for U_{n-1}^(j-1): the chain of iteration j-1 (segment
+//                 n-1, or its first step U_{j-1} = F_{j-1} for n = j; the
+//                 initial chain for j = 1; U_0 needs no wait);
+//   chain (j)     waits for the chain of iteration j-1, then for the fine slices
+//                 n = j..M of iteration j, one by one, while it sums the jumps.
+// Every wait is for an entry queued before the waiting one, so every wait ends;
+// and the sweep of iteration j+1 overlaps the correction chain of iteration j
+// (fine (j+1, n) starts once the chain has passed slice n-1).  A sample that
+// stops at iteration K skips its later entries; the executed work is exactly
+// the sequential algorithm's (Eqs. (13)-(14)).  Fine end states alternate
+// between two buffers by the parity of j, because fine (j+1, n) can finish
+// before chain (j) has read F_n^(j).
 static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
                             double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
   last_flags().clear();
@@ -1098,7 +1117,7 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
   const int M = pd->n_slices, fs = pd->fine_steps_per_slice, cs = pd->coarse_steps_per_slice;
   if (M < 1 || fs < 1 || cs < 1 || pd->n_periods < 1 || pd->k_max < 1 || pd->fixed_k < 0 || !(pd->tol >= 0))
     return fail(MQ_ERR_INVALID_ARG, "invalid Parareal description");
-  if ((int64_t)M * fs > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
+  if ((int64_t)M * fs > (1 << 24) || (int64_t)M * cs > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
   const double t_start = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
   int rc = check_finite(p, xi, (size_t)n_samples * p->n_xi);
@@ -1112,165 +1131,258 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
   const double dtf = T / ((double)M * fs), dtc = T / ((double)M * cs);
   auto sf = source_table(p->d, dtf, M * fs);
   auto sc = source_table(p->d, dtc, M * cs);
-  TmpPtr<double> dsf, dsc;
-  HIP_TRY(tmp_alloc(dsf, sf.size(), p->stream));
-  HIP_TRY(tmp_alloc(dsc, sc.size(), p->stream));
-  HIP_TRY(copy_sync(dsf.get(), sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(copy_sync(dsc.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
-  // states: U_0..U_{M-1} (U_0 = 0), F_1..F_M, C_old_1..C_old_{M-1}, per sample
   const int S = n_samples;
-  const size_t per = (size_t)(M + M + M) * FS;
-  TmpPtr<double> states, qn;
-  HIP_TRY(tmp_alloc(states, per * S, p->stream));
-  HIP_TRY(launch_fill_zero(states.get(), per * S, p->stream));
-  HIP_TRY(tmp_alloc(qn, (size_t)S * M, p->stream));
-  HIP_TRY(launch_fill_zero(qn.get(), (size_t)S * M, p->stream));
-  auto U = [&](int s, int nn) { return states.get() + per * s + (size_t)nn * FS; };             // nn = 0..M-1
-  auto F = [&](int s, int nn) { return states.get() + per * s + (size_t)(M + nn - 1) * FS; };   // nn = 1..M
-  auto C = [&](int s, int nn) { return states.get() + per * s + (size_t)(2 * M + nn - 1) * FS; };  // nn = 1..M-1
-  if (p->a0)  // U_0 = a_0 for every sample
-    for (int s = 0; s < S; ++s)
-      HIP_TRY(hipMemcpyAsync(U(s, 0), p->a0.get(), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   const int kcap = std::min(pd->fixed_k > 0 ? pd->fixed_k : pd->k_max, M);
-  RunOut ro;
-  std::vector<int> active(S);
-  for (int s = 0; s < S; ++s) active[s] = s;
-  std::vector<int> Kout(S, 0);
-  std::vector<int32_t> pflags(S, 0);  // per sample: its instances' flags OR-ed
-  bool warn = false;
-  auto collect = [&](const std::vector<Inst>& insts, size_t off) {
-    for (size_t i = 0; i < insts.size(); ++i) pflags[insts[i].sample] |= ro.flags[off + i];
-  };
+  CallMem mem;
+  mem.use_stream(p->stream);
+  double *dsf, *dsc, *Ub, *Fb, *Cb, *qb, *Jb;
+  int *segd, *fdone, *chd, *Kd, *pfl, *abortf;
+  ParaCtl* dctl;
+  HIP_TRY(mem.get(dsf, sf.size()));
+  HIP_TRY(mem.get(dsc, sc.size()));
+  HIP_TRY(copy_sync(dsf, sf.data(), sf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(copy_sync(dsc, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  const size_t nU = (size_t)S * M * FS, nF = 2 * (size_t)S * M * FS, nC = (size_t)S * M * FS;
+  const size_t nq = (size_t)S * kcap * M;
+  const size_t nseg = (size_t)(kcap + 1) * S * M, nfd = (size_t)(kcap + 1) * S * (M + 1), nch = (size_t)(kcap + 1) * S;
+  HIP_TRY(mem.get(Ub, nU));
+  HIP_TRY(mem.get(Fb, nF));
+  HIP_TRY(mem.get(Cb, nC));
+  HIP_TRY(mem.get(qb, nq));
+  HIP_TRY(mem.get(Jb, (size_t)S * kcap));
+  HIP_TRY(mem.get(segd, nseg));
+  HIP_TRY(mem.get(fdone, nfd));
+  HIP_TRY(mem.get(chd, nch));
+  HIP_TRY(mem.get(Kd, S));
+  HIP_TRY(mem.get(pfl, S));
+  HIP_TRY(mem.get(abortf, 1));
+  HIP_TRY(mem.get(dctl, 1));
+  HIP_TRY(launch_fill_zero(Ub, nU, p->stream));
+  HIP_TRY(launch_fill_zero(Fb, nF, p->stream));
+  HIP_TRY(launch_fill_zero(Cb, nC, p->stream));
+  HIP_TRY(launch_fill_zero(qb, nq, p->stream));
+  HIP_TRY(launch_fill_zero(Jb, (size_t)S * kcap, p->stream));
+  HIP_TRY(launch_fill_zero_i(segd, nseg, p->stream));
+  HIP_TRY(launch_fill_zero_i(fdone, nfd, p->stream));
+  HIP_TRY(launch_fill_zero_i(chd, nch, p->stream));
+  HIP_TRY(launch_fill_zero_i(Kd, S, p->stream));
+  HIP_TRY(launch_fill_zero_i(pfl, S, p->stream));
+  HIP_TRY(launch_fill_zero_i(abortf, 1, p->stream));
+  auto U = [&](int s_, int n_) { return Ub + ((size_t)s_ * M + n_) * FS; };                       // n = 0..M-1
+  auto F = [&](int j_, int s_, int n_) { return Fb + (((size_t)(j_ & 1) * S + s_) * M + (n_ - 1)) * FS; };  // n = 1..M
+  auto C = [&](int s_, int n_) { return Cb + ((size_t)s_ * M + n_) * FS; };                       // n = 1..M-1
+  auto QS = [&](int s_, int j_, int n_) { return qb + ((size_t)s_ * kcap + (j_ - 1)) * M + (n_ - 1); };
+  auto SEG = [&](int j_, int s_, int n_) { return segd + ((size_t)j_ * S + s_) * M + n_; };        // U_n^(j) written
+  auto FD = [&](int j_, int s_, int n_) { return fdone + ((size_t)j_ * S + s_) * (M + 1) + n_; };   // fine (j, n) done
+  auto CH = [&](int j_, int s_) { return chd + (size_t)j_ * S + s_; };                              // chain (j) done
+  if (p->a0)  // U_0 = a_0 for every sample
+    for (int s_ = 0; s_ < S; ++s_)
+      HIP_TRY(hipMemcpyAsync(U(s_, 0), p->a0.get(), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  ParaCtl hctl{Kd, Jb, pfl, abortf, pd->tol, pd->fixed_k, kcap};
+  HIP_TRY(copy_sync(dctl, &hctl, sizeof(ParaCtl), hipMemcpyHostToDevice, p->stream));
 
-  auto launch_chain = [&](const std::vector<int>& smp, int first, bool initial) -> int {
-    if (first > M - 1 || smp.empty()) return MQ_OK;
-    const int nseg = M - first;
-    const size_t L = (size_t)smp.size() * nseg;
-    std::vector<double*> arr(3 * L);
-    for (size_t a = 0; a < smp.size(); ++a)
-      for (int k = 0; k < nseg; ++k) {
-        const int nn = first + k;
-        arr[a * nseg + k] = U(smp[a], nn);
-        arr[L + a * nseg + k] = initial ? nullptr : F(smp[a], nn);
-        arr[2 * L + a * nseg + k] = C(smp[a], nn);
-      }
-    TmpPtr<double*> darr;
-    HIP_TRY(tmp_alloc(darr, arr.size(), p->stream));
-    HIP_TRY(copy_sync(darr.get(), arr.data(), arr.size() * sizeof(double*), hipMemcpyHostToDevice, p->stream));
-    std::vector<Inst> insts;
-    for (size_t a = 0; a < smp.size(); ++a) {
-      Inst in{};
-      in.tab = tables.get() + (size_t)smp[a] * tab_stride(g);
-      in.src = dsc.get();
-      in.a_init = U(smp[a], first - 1);
+  // pointer arrays of the entries (one device array, offsets into it)
+  std::vector<const void*> ptrs;
+  std::vector<Inst> insts;
+  std::vector<std::pair<size_t, const void*>> fix;  // (entry, field) resolved after the copy
+  auto put = [&](const std::vector<const void*>& v) {
+    const size_t o = ptrs.size();
+    ptrs.insert(ptrs.end(), v.begin(), v.end());
+    return o;
+  };
+  struct Arr {
+    size_t cu = SIZE_MAX, cf = SIZE_MAX, cc = SIZE_MAX, sd = SIZE_MAX, jf = SIZE_MAX, ju = SIZE_MAX, jw = SIZE_MAX;
+  };
+  std::vector<Arr> arrs;
+  auto base = [&](int s_) {
+    Inst in{};
+    in.tab = tables.get() + (size_t)s_ * tab_stride(g);
+    in.sample = s_;
+    in.group = s_;
+    in.para = dctl;
+    return in;
+  };
+  // initial coarse chain U_n^(0) = C(U_{n-1}^(0)), n = 1..M-1
+  if (M >= 2)
+    for (int s_ = 0; s_ < S; ++s_) {
+      Inst in = base(s_);
+      in.src = dsc;
+      in.a_init = U(s_, 0);
       in.dt = dtc;
       in.n_steps = cs;
-      in.k0 = (first - 1) * cs;
-      in.n_chain = nseg;
-      in.group = (int)a;
-      in.chain_u = darr.get() + a * nseg;
-      in.chain_f = darr.get() + L + a * nseg;
-      in.chain_c = darr.get() + 2 * L + a * nseg;
-      in.sample = smp[a];
+      in.k0 = 0;
+      in.n_chain = M - 1;
+      in.para_iter = 0;
+      in.para_chain = 1;
+      in.dep_done = CH(0, s_);
+      Arr a;
+      std::vector<const void*> cu, cf, cc, sd;
+      for (int n_ = 1; n_ <= M - 1; ++n_) {
+        cu.push_back(U(s_, n_));
+        cf.push_back(nullptr);
+        cc.push_back(C(s_, n_));
+        sd.push_back(SEG(0, s_, n_));
+      }
+      a.cu = put(cu);
+      a.cf = put(cf);
+      a.cc = put(cc);
+      a.sd = put(sd);
       insts.push_back(in);
+      arrs.push_back(a);
     }
-    const size_t off = ro.flags.size();
-    const int rc2 = run_instances(p, insts, st, &ro, nullptr);
-    if (rc2 == MQ_OK) collect(insts, off);
-    return rc2;
-  };
-
-  // initial coarse pass U_n = C(U_{n-1}), n = 1..M-1
-  rc = launch_chain(active, 1, true);
-  if (rc) return rc;
-  std::vector<double> jump_host;
-  for (int j = 1; j <= kcap && !active.empty(); ++j) {
-    // fine sweep over slices j..M of the active samples
-    std::vector<Inst> insts;
-    for (int s : active)
-      for (int nn = j; nn <= M; ++nn) {
-        Inst in{};
-        in.tab = tables.get() + (size_t)s * tab_stride(g);
-        in.src = dsf.get();
-        in.a_init = U(s, nn - 1);
-        in.a_out = F(s, nn);
-        in.q_out = qn.get() + (size_t)s * M + (nn - 1);
+  for (int j_ = 1; j_ <= kcap; ++j_) {
+    // fine sweep of iteration j over slices n = j..M (slice-major: the earliest
+    // inputs first)
+    for (int n_ = j_; n_ <= M; ++n_)
+      for (int s_ = 0; s_ < S; ++s_) {
+        Inst in = base(s_);
+        in.src = dsf;
+        in.a_init = U(s_, n_ - 1);
+        in.a_out = F(j_, s_, n_);
+        in.q_out = QS(s_, j_, n_);
         in.q_scale = 1.0;
         in.dt = dtf;
         in.n_steps = fs;
-        in.k0 = (nn - 1) * fs;
-        in.sample = s;
-        in.group = s;
+        in.k0 = (n_ - 1) * fs;
+        in.para_iter = j_;
+        in.para_chain = 0;
+        in.dep_wait = (n_ == 1) ? nullptr : SEG(j_ - 1, s_, n_ - 1);
+        in.dep_done = FD(j_, s_, n_);
         insts.push_back(in);
+        arrs.push_back(Arr{});
       }
-    const size_t off = ro.flags.size();
-    rc = run_instances(p, insts, st, &ro, nullptr);
-    if (rc) return rc;
-    collect(insts, off);
-    // interface jumps over n = j..M-1
-    std::vector<int> still;
-    if (j < M) {
-      const int npair = (int)active.size() * (M - j);
-      std::vector<const double*> fp(npair), up(npair);
-      int k = 0;
-      for (int s : active)
-        for (int nn = j; nn < M; ++nn, ++k) {
-          fp[k] = F(s, nn);
-          up[k] = U(s, nn);
-        }
-      TmpPtr<const double*> dfp, dup;
-      TmpPtr<double> dj, djmax;
-      const int na = (int)active.size();
-      HIP_TRY(tmp_alloc(dfp, npair, p->stream));
-      HIP_TRY(tmp_alloc(dup, npair, p->stream));
-      HIP_TRY(tmp_alloc(dj, 2 * (size_t)npair, p->stream));
-      HIP_TRY(tmp_alloc(djmax, na, p->stream));
-      HIP_TRY(copy_sync(dfp.get(), fp.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
-      HIP_TRY(copy_sync(dup.get(), up.data(), npair * sizeof(double*), hipMemcpyHostToDevice, p->stream));
-      HIP_TRY(launch_jumps(g, npair, dfp.get(), dup.get(), dj.get(), p->stream));
-      HIP_TRY(launch_jump_max(dj.get(), M - j, na, djmax.get(), p->stream));
-      jump_host.assign(na, 0.0);
-      HIP_TRY(hipMemcpyAsync(jump_host.data(), djmax.get(), na * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-      HIP_TRY(hipStreamSynchronize(p->stream));
-      k = 0;
-      for (int s : active) {
-        const double J = jump_host[k++];
-        const bool done = (pd->fixed_k == 0 && J <= pd->tol) || j == kcap;
-        if (done) {
-          Kout[s] = j;
-          if (pd->fixed_k == 0 && J > pd->tol) {
-            warn = true;
-            pflags[s] |= FLAG_PARAREAL_KMAX;
-          }
-        } else {
-          still.push_back(s);
-        }
+    // coarse chain of iteration j: stopping decision, then the correction
+    for (int s_ = 0; s_ < S; ++s_) {
+      Inst in = base(s_);
+      in.src = dsc;
+      in.dt = dtc;
+      in.n_steps = cs;
+      in.k0 = j_ * cs;
+      in.para_iter = j_;
+      in.para_chain = 1;
+      in.dep_wait = (j_ == 1 && M < 2) ? nullptr : CH(j_ - 1, s_);  // no initial chain when M = 1
+      in.dep_done = CH(j_, s_);
+      in.n_jump = M - j_;
+      const bool last = j_ >= kcap;
+      in.n_chain = last ? 0 : std::max(0, M - 1 - j_);
+      if (!last && j_ <= M - 1) {
+        in.a_init = U(s_, j_);
+        in.u_first = U(s_, j_);
+        in.f_first = F(j_, s_, j_);
+        in.first_done = SEG(j_, s_, j_);
       }
-    } else {
-      for (int s : active) Kout[s] = j;
+      Arr a;
+      std::vector<const void*> jf, ju, jw;
+      for (int n_ = j_; n_ <= M - 1; ++n_) {
+        jf.push_back(F(j_, s_, n_));
+        ju.push_back(U(s_, n_));
+      }
+      for (int n_ = j_; n_ <= M; ++n_) jw.push_back(FD(j_, s_, n_));
+      a.jf = put(jf);
+      a.ju = put(ju);
+      a.jw = put(jw);
+      if (in.n_chain > 0) {
+        std::vector<const void*> cu, cf, cc, sd;
+        for (int n_ = j_ + 1; n_ <= M - 1; ++n_) {
+          cu.push_back(U(s_, n_));
+          cf.push_back(F(j_, s_, n_));
+          cc.push_back(C(s_, n_));
+          sd.push_back(SEG(j_, s_, n_));
+        }
+        a.cu = put(cu);
+        a.cf = put(cf);
+        a.cc = put(cc);
+        a.sd = put(sd);
+      }
+      insts.push_back(in);
+      arrs.push_back(a);
     }
-    active = still;
-    if (active.empty()) break;
-    // correction: U_j = F_j, then the coarse chain over j+1..M-1
-    for (int s : active)
-      HIP_TRY(hipMemcpyAsync(U(s, j), F(s, j), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-    rc = launch_chain(active, j + 1, false);
-    if (rc) return rc;
   }
-  // Q = sum_n q_n / T in slice order (FP64, on the device)
-  HIP_TRY(launch_slice_qoi(qn.get(), M, S, T, q, p->stream));
-  HIP_TRY(copy_sync(iters, Kout.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  // Every flag an entry waits on must be set by an entry queued before it.
+  {
+    std::unordered_map<const void*, size_t> setter;
+    for (size_t e = 0; e < insts.size(); ++e) {
+      const Inst& in = insts[e];
+      if (in.dep_done) setter[in.dep_done] = e;
+      if (in.first_done) setter[in.first_done] = e;
+      if (arrs[e].sd != SIZE_MAX)
+        for (int k = 0; k < in.n_chain; ++k) setter[ptrs[arrs[e].sd + k]] = e;
+    }
+    auto before = [&](const void* f, size_t e) {
+      auto it = setter.find(f);
+      return it != setter.end() && it->second < e;
+    };
+    for (size_t e = 0; e < insts.size(); ++e) {
+      const Inst& in = insts[e];
+      bool ok = !in.dep_wait || before(in.dep_wait, e);
+      if (arrs[e].jw != SIZE_MAX)
+        for (int k = 0; k <= in.n_jump; ++k) ok = ok && before(ptrs[arrs[e].jw + k], e);
+      if (!ok) return fail(MQ_ERR_DEVICE, "internal: Parareal entry waits on a later entry");
+    }
+  }
+  const void** dptrs = nullptr;
+  HIP_TRY(mem.get(dptrs, ptrs.size()));
+  HIP_TRY(copy_sync(dptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice, p->stream));
+  for (size_t e = 0; e < insts.size(); ++e) {
+    Inst& in = insts[e];
+    const Arr& a = arrs[e];
+    if (a.cu != SIZE_MAX) {
+      in.chain_u = (double* const*)(dptrs + a.cu);
+      in.chain_f = (const double* const*)(dptrs + a.cf);
+      in.chain_c = (double* const*)(dptrs + a.cc);
+      in.seg_done = (int* const*)(dptrs + a.sd);
+    }
+    if (a.jf != SIZE_MAX) {
+      in.jump_f = (const double* const*)(dptrs + a.jf);
+      in.jump_u = (const double* const*)(dptrs + a.ju);
+      in.jump_wait = (const int* const*)(dptrs + a.jw);
+    }
+  }
+  RunOut ro;
+  rc = run_instances(p, insts, st, &ro, nullptr);
+  if (rc) return rc;
+  std::vector<int> Kh(S), ph(S);
+  HIP_TRY(hipMemcpyAsync(Kh.data(), Kd, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(ph.data(), pfl, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  bool warn = false;
+  std::vector<int32_t> pflags(S, 0);
+  for (size_t e = 0; e < insts.size(); ++e) pflags[insts[e].sample] |= ro.flags[e];
+  for (int s_ = 0; s_ < S; ++s_) {
+    pflags[s_] |= ph[s_];
+    if (Kh[s_] < 1 || Kh[s_] > kcap) {  // no decision reached (a timed-out wait)
+      pflags[s_] |= FLAG_FAILED;
+      Kh[s_] = std::max(1, std::min(kcap, Kh[s_]));
+    }
+    if (pflags[s_] & (FLAG_PARAREAL_KMAX | FLAG_WARN)) warn = true;
+  }
+  HIP_TRY(copy_sync(iters, Kh.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  // Q = sum_n q_n / T with q_n of each slice's latest fine run, iteration min(n, K) (FP64, device)
+  HIP_TRY(launch_para_qoi(qb, iters, kcap, M, S, T, q, p->stream));
   if (final_state) {
     std::vector<const double*> fp(S);
-    for (int s = 0; s < S; ++s) fp[s] = F(s, M);
-    TmpPtr<const double*> dfp;
-    HIP_TRY(tmp_alloc(dfp, S, p->stream));
-    HIP_TRY(copy_sync(dfp.get(), fp.data(), S * sizeof(double*), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(launch_to_interior(g, S, dfp.get(), final_state, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (int s_ = 0; s_ < S; ++s_) fp[s_] = F(Kh[s_], s_, M);
+    const double** dfp = nullptr;
+    HIP_TRY(mem.get(dfp, S));
+    HIP_TRY(copy_sync(dfp, fp.data(), S * sizeof(double*), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(launch_to_interior(g, S, dfp, final_state, p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (st) {
+    // executed work of the sequential algorithm with these K (entries that
+    // skipped ran nothing): initial chain (M-1) C, per iteration j <= K the
+    // fine slices j..M, per correction j < K the slices j+1..M-1
+    int64_t steps = 0;
+    for (int s_ = 0; s_ < S; ++s_) {
+      steps += (int64_t)(M - 1) * cs;
+      for (int j_ = 1; j_ <= Kh[s_]; ++j_) steps += (int64_t)(M - j_ + 1) * fs;
+      for (int j_ = 1; j_ < Kh[s_]; ++j_) steps += (int64_t)std::max(0, M - 1 - j_) * cs;
+    }
+    st->sample_steps = steps;
+    st->n_instances = (int64_t)insts.size();
+    st->total_ms = now_ms() - t_start;
   }
   last_flags() = pflags;
-  if (st) st->total_ms = now_ms() - t_start;
   if (warn) {
     last_error() = "Parareal reached k_max above the tolerance for some samples";
     return MQ_WARN_NOT_CONVERGED;

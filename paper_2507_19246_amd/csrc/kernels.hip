@@ -217,6 +217,118 @@ __device__ inline void block_sum(double (&v)[NV], double* red, int& slot) {
 }
 
 // ---------------------------------------------------------------------------
+// Parareal in one persistent launch: flags between queue entries
+// ---------------------------------------------------------------------------
+// Wait (thread 0, bounded) until *f is set, then make the writer's data visible
+// to the whole workgroup (the writer may have run on another XCD).  Returns
+// false after the time limit.
+// abort (nullable): a launch-wide flag; a wait that times out sets it, and every
+// wait that sees it gives up at once, so a missing flag costs one time limit
+// per launch, not one per entry.
+template <int NT>
+__device__ inline bool para_wait(const int* f, unsigned long long limit, int* s_ok, int* abort = nullptr) {
+  if (threadIdx.x == 0) {
+    const unsigned long long t0 = wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      if (wall_clock64() - t0 > limit ||
+          (abort && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        ok = 0;
+        if (abort) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool ok = *s_ok != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Publish everything the workgroup wrote, then set *f.
+__device__ inline void para_set(int* f) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Entry prologue of a queue entry (false at once for entries that are not part
+// of a one-launch Parareal run).  Returns true when a Parareal entry has
+// nothing to run: its sample stopped at an earlier iteration, or (coarse chain
+// of iteration j >= 1) the jumps of iteration j stop it now, or no correction
+// segment is left.  Such an entry sets every flag it owns.  A chain j >= 1
+// that continues has computed the jumps of Section II-C's stopping test
+// (largest ||F_n - U_n|| / ||F_n|| over n = j..M-1), written U_j = F_j and set
+// first_done; *flags gets FLAG_FAILED after a timed-out wait.
+template <int NT, int NWAVES>
+__device__ bool para_prologue(const Geom& g, const Inst& in, double* red, int& slot, int* s_ok, int* flags) {
+  // every branch below is taken by the workgroup as a whole (wave-uniform values)
+  if (__builtin_amdgcn_readfirstlane(in.para != nullptr ? 1 : 0) == 0) return false;  // not a Parareal entry
+  const ParaCtl* pc = in.para;
+  const int s = __builtin_amdgcn_readfirstlane(in.sample);
+  const int j = __builtin_amdgcn_readfirstlane(in.para_iter);
+  const int n_jump = __builtin_amdgcn_readfirstlane(in.n_jump);
+  const int n_chain = __builtin_amdgcn_readfirstlane(in.n_chain);
+  const bool chain = __builtin_amdgcn_readfirstlane(in.para_chain) != 0;
+  const int n = g.n, nd = n * n;
+  __shared__ int s_skip;
+  if (threadIdx.x == 0) {
+    const int K = __hip_atomic_load(pc->K + s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    s_skip = (K != 0 && K < j) ? 1 : 0;
+  }
+  __syncthreads();
+  int skip = __builtin_amdgcn_readfirstlane(s_skip);
+  __syncthreads();
+  if (!skip && chain && j >= 1) {
+    double Jmax = 0.0;
+    for (int k = 0; k < n_jump; ++k) {
+      if (!para_wait<NT>(in.jump_wait[k], PARA_WAIT_TICKS, s_ok, pc->abort)) *flags |= FLAG_FAILED;
+      const double* F = in.jump_f[k];
+      const double* U = in.jump_u[k];
+      double v[2] = {0.0, 0.0};
+      for (int idx = threadIdx.x; idx < nd; idx += NT) {
+        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        const double d = F[gi] - U[gi];
+        v[0] += d * d;
+        v[1] += F[gi] * F[gi];
+      }
+      block_sum<2, NWAVES>(v, red, slot);
+      Jmax = fmax(Jmax, v[1] > 0.0 ? sqrt(v[0] / v[1]) : sqrt(v[0]));
+    }
+    // the last slice's fine run has read U_{M-1}^(j-1) before the chain overwrites it
+    if (!para_wait<NT>(in.jump_wait[n_jump], PARA_WAIT_TICKS, s_ok, pc->abort)) *flags |= FLAG_FAILED;
+    const int stop = __builtin_amdgcn_readfirstlane(((pc->fixed_k == 0 && Jmax <= pc->tol) || j >= pc->kcap) ? 1 : 0);
+    if (threadIdx.x == 0) {
+      pc->J[(size_t)s * pc->kcap + (j - 1)] = Jmax;
+      if (stop) {
+        if (pc->fixed_k == 0 && Jmax > pc->tol) atomicOr(pc->flags + s, FLAG_PARAREAL_KMAX);
+        __hip_atomic_store(pc->K + s, j, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (stop) {
+      skip = 1;
+    } else {
+      for (int idx = threadIdx.x; idx < nd; idx += NT) {
+        const int gi = (idx / n + 1) * g.P + idx % n + 1;
+        in.u_first[gi] = in.f_first[gi];
+      }
+      para_set(in.first_done);
+      // no segment left (j = M - 1): nothing to run; done flag set by the caller
+      if (n_chain == 0) return true;
+    }
+  }
+  if (skip) {
+    if (in.first_done) para_set(in.first_done);
+    if (in.seg_done)
+      for (int k = 0; k < n_chain; ++k) para_set(in.seg_done[k]);
+  }
+  return skip != 0;
+}
+
+// ---------------------------------------------------------------------------
 // resident time-stepping kernel
 // ---------------------------------------------------------------------------
 // Workgroup = CW * NS threads; thread (c, s) owns interior column i = c and
@@ -638,8 +750,11 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   // recomputed in the iteration (a few scalar operations) instead of being kept
   // live across the whole loop, which exhausts the scalar register file.
   auto refresh = [&]() __attribute__((always_inline)) {
-    if constexpr (CW % 64 == 0) asm volatile("" : "+s"(j0));
-    else asm volatile("" : "+v"(j0));
+    // opaque to the optimiser, and back to a scalar register where the slice
+    // is wave-uniform (readfirstlane instead of an "s" constraint, which the
+    // backend cannot always honour once j0 is carried around the entry loop)
+    asm volatile("" : "+v"(j0));
+    if constexpr (CW % 64 == 0) j0 = __builtin_amdgcn_readfirstlane(j0);
     asm volatile("" : "+v"(l0), "+v"(s0));
   };
   const bool col_L = ci >= g.bx0 && ci < g.lx1;
@@ -726,9 +841,13 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       if (tid == 0) {
         const unsigned long long tw = wall_clock64();
         int ok = 1;
+        const unsigned long long lim = in.para ? PARA_WAIT_TICKS : DEP_WAIT_TICKS;
+        int* abort = in.para ? in.para->abort : nullptr;
         while (__hip_atomic_load(in.dep_wait, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-          if (wall_clock64() - tw > DEP_WAIT_TICKS) {
+          if (wall_clock64() - tw > lim ||
+              (abort && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             ok = 0;
+            if (abort) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
           __builtin_amdgcn_s_sleep(8);
@@ -738,6 +857,21 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (!s_depok) dep_flags = FLAG_FAILED;
+      __syncthreads();
+    }
+    // Parareal entry of a one-launch run: skip (sample stopped, or stopped by
+    // this chain's jumps) or run; a continuing chain has written U_j
+    // (called for every entry; the branch is made wave-uniform: it leaves the
+    // entry as a whole)
+    if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
+      if (tid == 0 && in.stat) {
+        in.stat[3] = dep_flags;
+        in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
+        in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+      }
+      if (in.dep_done) para_set(in.dep_done);
+      __syncthreads();
+      continue;
     }
     for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
 #pragma unroll 1
@@ -1240,6 +1374,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           }
         }
         __syncthreads();
+        if (in.seg_done) para_set(in.seg_done[seg]);
       }
     }
     if (in.a_out) {
@@ -1284,10 +1419,6 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     __syncthreads();
   }
 }
-
-struct ResCfg {
-  int cw, sh, ns, tp;
-};
 
 bool build_mg(const Geom& g, int lp, MGGeom* mg) {
   mg->nlev = 0;
@@ -1364,18 +1495,6 @@ static size_t resident_lds(const Geom& g, const ResCfg& c, const MGGeom* mg) {
 // tile 1: 16 rows per thread; tile 2 (meshes of 64..127 interior nodes per
 // side): 32 rows per thread in 512-thread workgroups, which leaves 256
 // registers per lane instead of 128.
-static bool pick_resident(const Geom& g, int tile, ResCfg* c) {
-  if (g.n <= 31) {
-    *c = {32, 16, 2, 32};
-  } else if (g.n <= 63) {
-    *c = {64, 16, 4, 64};
-  } else if (g.n <= 127) {
-    *c = tile == 2 ? ResCfg{128, 32, 4, 64} : ResCfg{128, 16, 8, 64};
-  } else {
-    return false;
-  }
-  return g.n <= c->sh * c->ns && g.RW <= c->tp;
-}
 
 int stream_threads(int tile);
 
@@ -1664,79 +1783,27 @@ hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double
 }
 
 // Interface jumps: for pair p, out2[2p] = ||F - U||^2, out2[2p+1] = ||F||^2 over interior nodes.
-__global__ void k_jumps(Geom g, const double* const* f, const double* const* u, double* out2) {
-  const int pidx = blockIdx.x;
-  const double* F = f[pidx];
-  const double* U = u[pidx];
-  const int nd = g.n * g.n;
-  double a = 0.0, b = 0.0;
-  for (int idx = threadIdx.x; idx < nd; idx += blockDim.x) {
-    const int i = idx % g.n, j = idx / g.n;
-    const int gi = (j + 1) * g.P + i + 1;
-    const double d = F[gi] - U[gi];
-    a += d * d;
-    b += F[gi] * F[gi];
-  }
-  __shared__ double sa[256], sb[256];
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  for (int m = 128; m >= 1; m >>= 1) {
-    if ((int)threadIdx.x < m) {
-      sa[threadIdx.x] += sa[threadIdx.x + m];
-      sb[threadIdx.x] += sb[threadIdx.x + m];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out2[2 * pidx] = sa[0];
-    out2[2 * pidx + 1] = sb[0];
-  }
-}
-
-hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f, const double* const* u,
-                        double* out2, hipStream_t st) {
-  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
-  if (n_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jumps, dim3(n_pairs), dim3(256), 0, st, g, f, u, out2);
-  return hipGetLastError();
-}
-
-// Per sample of a Parareal sweep: the largest relative interface jump
-// max_n sqrt(|F_n - U_n|^2 / |F_n|^2) over its `per` consecutive pairs of
-// out2 (absolute where |F_n| = 0), in interface order.
-__global__ void k_jump_max(const double* __restrict__ out2, int per, int n_samples, double* __restrict__ jmax) {
+// Parareal QoI per sample (one-launch run): Q = (sum_n q_n) / T over the M
+// slices in slice order, q_n from the slice's latest fine run, iteration
+// min(n, K) (FP64).  q: [S][kcap][M].
+__global__ void k_para_qoi(const double* __restrict__ qb, const int* __restrict__ K, int kcap, int M, int n_samples,
+                           double T, double* __restrict__ q) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_samples) return;
-  double J = 0.0;
-  for (int k = s * per; k < (s + 1) * per; ++k) {
-    const double a = out2[2 * k], b = out2[2 * k + 1];
-    J = fmax(J, b > 0.0 ? sqrt(a / b) : sqrt(a));
-  }
-  jmax[s] = J;
-}
-
-hipError_t launch_jump_max(const double* out2, int per, int n_samples, double* jmax, hipStream_t st) {
-  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
-  if (n_samples == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jump_max, dim3((n_samples + 255) / 256), dim3(256), 0, st, out2, per, n_samples, jmax);
-  return hipGetLastError();
-}
-
-// Parareal QoI per sample: Q = (sum_n q_n) / T over its M slice sums in slice
-// order (FP64).
-__global__ void k_slice_qoi(const double* __restrict__ qn, int M, int n_samples, double T, double* __restrict__ q) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_samples) return;
+  const int Ks = K[s];
   double acc = 0.0;
-  for (int n = 0; n < M; ++n) acc += qn[(size_t)s * M + n];
+  for (int n = 1; n <= M; ++n) {
+    const int jj = n < Ks ? n : Ks;
+    acc += qb[((size_t)s * kcap + (jj - 1)) * M + (n - 1)];
+  }
   q[s] = acc / T;
 }
 
-hipError_t launch_slice_qoi(const double* qn, int M, int n_samples, double T, double* q, hipStream_t st) {
+hipError_t launch_para_qoi(const double* qb, const int* K, int kcap, int M, int n_samples, double T, double* q,
+                           hipStream_t st) {
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   if (n_samples == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slice_qoi, dim3((n_samples + 255) / 256), dim3(256), 0, st, qn, M, n_samples, T, q);
+  hipLaunchKernelGGL(k_para_qoi, dim3((n_samples + 255) / 256), dim3(256), 0, st, qb, K, kcap, M, n_samples, T, q);
   return hipGetLastError();
 }
 
@@ -1793,6 +1860,8 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   __shared__ double red[2 * NWAVES * 4];
   __shared__ int s_inst;
   __shared__ int s_dmin;
+  __shared__ int s_depok;
+  __shared__ unsigned long long s_ph[9];  // thread 0's phase clocks, then its last mark
   const int tid = threadIdx.x;
   const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
   const size_t FS = (size_t)g.N * g.P;
@@ -1831,6 +1900,24 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
     const double* tab = in.tab;
     const double inv_dt = 1.0 / in.dt;
     const unsigned long long t_begin = wall_clock64();
+    // an entry of a one-launch Parareal run: wait (bounded) for its input, then
+    // skip (sample stopped, or stopped by this chain's jumps) or run
+    int dep_flags = 0;
+    if (in.dep_wait && !para_wait<NT>(in.dep_wait, in.para ? PARA_WAIT_TICKS : DEP_WAIT_TICKS, &s_depok,
+                                      in.para ? in.para->abort : nullptr))
+      dep_flags = FLAG_FAILED;
+    // (called for every entry; the branch is made wave-uniform: it leaves the
+    // entry as a whole)
+    if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
+      if (tid == 0 && in.stat) {
+        in.stat[3] = dep_flags;
+        in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
+        in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+      }
+      if (in.dep_done) para_set(in.dep_done);
+      __syncthreads();
+      continue;
+    }
     auto dscale = [&](int i, int j) -> double {
       if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
         const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
@@ -1886,12 +1973,26 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
     };
 
     double qsum = in.carry_in ? in.carry[2 * FS] : 0.0;
-    int it_total = 0, sw_total = 0, it_max_step = 0, flags = 0;
+    int it_total = 0, sw_total = 0, it_max_step = 0, flags = dep_flags;
+    // phase clocks of thread 0 in LDS (same phase indices as the resident
+    // kernel; kept out of the registers)
+    if (tid == 0) {
+      for (int q = 0; q < 8; ++q) s_ph[q] = 0;
+      s_ph[8] = wall_clock64();
+    }
+    auto tick = [&](int q) __attribute__((always_inline)) {
+      if (tid == 0) {
+        const unsigned long long t = wall_clock64();
+        if (q >= 0) s_ph[q] += t - s_ph[8];
+        s_ph[8] = t;
+      }
+    };
     const int n_seg = in.n_chain > 0 ? in.n_chain : 1;
     for (int seg = 0; seg < n_seg; ++seg) {
       const int kseg0 = in.k0 + seg * in.n_steps;
       for (int step = 0; step < in.n_steps; ++step) {
         const double Jt = in.src[kseg0 + step + 1];
+        tick(-1);
         double part[1] = {0.0};
         for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
           const NodeRef nr = node_ref(g, i, j);
@@ -1900,6 +2001,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
           part[0] += b * b;
         }
         block_sum<1, NWAVES>(part, red, slot);
+        tick(4);
         const double bb = part[0];
         int it_step = 0;
         if (bb == 0.0) {
@@ -1908,6 +2010,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
         } else {
           bool conv = false;
           for (int sweep = 0; sweep <= sv.max_sweeps; ++sweep) {
+            tick(-1);
             double rr[1] = {0.0};
             for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
               const NodeRef nr = node_ref(g, i, j);
@@ -1920,6 +2023,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
               if constexpr (MG) Vv[nr.gi] = VT(0);
             }
             block_sum<1, NWAVES>(rr, red, slot);
+            tick(5);
             if (!(rr[0] == rr[0]) || isinf(rr[0])) {
               flags |= FLAG_FAILED;
               break;
@@ -1969,6 +2073,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
               const bool exact1 = mg.nlev == 1 || sv.mg_levels == 1;
               double rho = 1.0, stop = 0.0;
               for (;;) {
+                tick(-1);
                 // z = B r: pre-smoothing from zero (z = om r) and t = r - A z
                 nodes2(
                     [&](int i, int j, const NodeRef& nr) {
@@ -1980,6 +2085,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                       Tm[nr.gi] = v.y;
                     });
                 __syncthreads();
+                tick(0);
                 {  // restriction to level 1
                   const int tx = tid & ((1 << L1.txs) - 1), ty = NT >> L1.txs;
                   if (tx < L1.n) {
@@ -1995,6 +2101,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                 const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
                                                     sv.mg_block_min);
                 __syncthreads();
+                tick(1);
                 nodes2(
                     [&](int i, int j, const NodeRef& nr) {
                       return V2{Zm[nr.gi] + prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr), VT(0)};
@@ -2014,6 +2121,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                       rz[1] += (double)(v.y * v.y);
                     });
                 block_sum<2, NWAVES>(rz, red, slot);
+                tick(2);
                 { VT* t_ = Zm; Zm = Tm; Tm = t_; }
                 double beta = 0.0;
                 if (it == 0) {
@@ -2049,6 +2157,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                       Rv[nr.gi] = v.y;
                     });
                 __syncthreads();
+                tick(3);
               }
             } else {
             double gd[2] = {0.0, 0.0};
@@ -2098,16 +2207,19 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
             }
             }
             it_step += it;
+            tick(-1);
             for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
               const NodeRef nr = node_ref(g, i, j);
               Xv[nr.gi] += (double)dnode(i, j, nr) * (double)Yv[nr.gi];
             }
             __syncthreads();
+            tick(6);
           }
           if (!conv) flags |= FLAG_NOT_CONVERGED;
         }
         it_total += it_step;
         it_max_step = it_step > it_max_step ? it_step : it_max_step;
+        tick(-1);
         double qq[1] = {0.0};
         for (int idx = tid; idx < lw * lh; idx += NT) {
           const NodeRef nr = node_ref(g, g.bx0 + idx % lw, g.by0 + idx / lw);
@@ -2123,6 +2235,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
           Xprev[gi] = d;
         }
         __syncthreads();
+        tick(7);
       }
       if (in.n_chain > 0) {
         const double* Fn = in.chain_f[seg];
@@ -2137,6 +2250,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
           Av[gi] = u;
         }
         __syncthreads();
+        if (in.seg_done) para_set(in.seg_done[seg]);
       }
     }
     if (in.a_out) {
@@ -2153,6 +2267,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
       }
       if (tid == 0) in.carry[2 * FS] = qsum;
     }
+    if (in.dep_done) para_set(in.dep_done);  // publishes a_out (and carry) first
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;
       if (in.stat) {
@@ -2165,6 +2280,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
         in.stat[5] = (int)(t_begin >> 32);
         in.stat[6] = (int)(t_end & 0xffffffffull);
         in.stat[7] = (int)(t_end >> 32);
+        for (int q = 0; q < 8; ++q) in.stat[8 + q] = (int)(s_ph[q] >> 4);  // units of 16 ticks
       }
       publish_done(in.host_done, qsum * in.q_scale, flags);
     }

@@ -38,15 +38,41 @@ struct Geom {
 // the sample's nonlinear curve coefficients k1', k2', k3' (and one pad).
 enum { T_MC = 0, T_ME, T_MN, T_MNE, T_KC, T_KE, T_KN, T_NPLANES };
 __host__ __device__ inline size_t tab_stride(const Geom& g) { return (size_t)T_NPLANES * g.RW * g.RH + 4; }
+// Resident workgroup shape: cw columns x ns slices of sh rows (cw * ns
+// threads, sh rows per thread), tp = table pitch in LDS.
+struct ResCfg {
+  int cw, sh, ns, tp;
+};
+// The resident shape for this mesh and tile (1: 16 rows per thread, 2: 32 rows
+// per thread in 512-thread workgroups where 64..127 interior nodes per side);
+// false where the resident path does not apply.
+__host__ __device__ inline bool pick_resident(const Geom& g, int tile, ResCfg* c) {
+  if (g.n <= 31) {
+    *c = {32, 16, 2, 32};
+  } else if (g.n <= 63) {
+    *c = {64, 16, 4, 64};
+  } else if (g.n <= 127) {
+    *c = tile == 2 ? ResCfg{128, 32, 4, 64} : ResCfg{128, 16, 8, 64};
+  } else {
+    return false;
+  }
+  return g.n <= c->sh * c->ns && g.RW <= c->tp;
+}
 // doubles of one thread-private [row][thread] plane of the resident kernel
 // (multigrid iterate, per-node D^{-1/2}): one element per (row, thread) of the
-// resident workgroup shapes for this mesh (16 x 64, 16 x 256, then 16 x 1024 =
-// 32 x 512 threads), and at least a full-grid plane.  On small meshes the
-// workgroup spans more (row, thread) pairs than the grid has nodes.
+// largest resident shape this mesh can take (either tile), and at least a
+// full-grid plane.  On small meshes the workgroup spans more (row, thread)
+// pairs than the grid has nodes.
 __host__ __device__ inline size_t res_plane_doubles(const Geom& g) {
-  const size_t fs = (size_t)g.N * g.P;
-  const size_t rows_x_threads = g.n <= 31 ? 1024 : g.n <= 63 ? 4096 : 16384;
-  return fs > rows_x_threads ? fs : rows_x_threads;
+  size_t need = (size_t)g.N * g.P;
+  for (int tile = 1; tile <= 2; ++tile) {
+    ResCfg c;
+    if (pick_resident(g, tile, &c)) {
+      const size_t rt = (size_t)c.sh * c.cw * c.ns;
+      if (rt > need) need = rt;
+    }
+  }
+  return need;
 }
 // doubles per slot of the time-stepping work buffer: state a, increment x,
 // right-hand side b (full-grid planes), the VT iterate plane (thread-private),
@@ -102,7 +128,37 @@ struct Inst {
   // Completion record in coherent pinned host memory (null: none), written
   // by the entry's last action so that the host sees Q as soon as it exists.
   struct HostDone* host_done;
+  // Parareal in one persistent launch (para null: none).  Every entry may wait
+  // (dep_wait) only on flags set by entries queued before it, so every wait ends.
+  const struct ParaCtl* para;
+  int para_iter;    // iteration j of this entry (0: the initial coarse pass)
+  int para_chain;   // 1: coarse chain of iteration j (j >= 1: decides, then corrects)
+  // chain j >= 1: the interfaces n = j..M-1 (fine end state F_n^(j), previous
+  // U_n^(j-1)) and the done flags of the fine slices n = j..M
+  const double* const* jump_f;
+  const double* const* jump_u;
+  const int* const* jump_wait;
+  int n_jump;       // M - j
+  double* u_first;        // U_j <- F_j^(j) before the correction chain
+  const double* f_first;
+  int* first_done;        // set once U_j is written
+  int* const* seg_done;   // per chain segment: set once its U_n is written
 };
+
+// Control record of one Parareal launch (device memory).
+struct ParaCtl {
+  int* K;        // [S]: iteration at which the sample stopped (0 while it runs)
+  double* J;     // [S][kcap]: largest relative interface jump of each iteration
+  int* flags;    // [S]: FLAG_PARAREAL_KMAX, FLAG_FAILED
+  int* abort;    // set by a wait that timed out: later waits give up at once
+  double tol;
+  int fixed_k, kcap;
+};
+
+// Longest wait of a Parareal entry for its input, 60 s of the device wall clock
+// (chains of a long run legitimately take seconds); past it the entry runs
+// flagged FLAG_FAILED.
+constexpr unsigned long long PARA_WAIT_TICKS = 6000000000ull;
 
 // One launch entry's completion as the host sees it: the kernel stores q and
 // flags, then sets done with a system-scope release store.
@@ -210,15 +266,13 @@ hipError_t launch_to_full(const Geom& g, int n, const double* in, double* const*
                           hipStream_t st);
 hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double* const* qf,
                               const double* const* qc, double* out, hipStream_t st);
-hipError_t launch_jumps(const Geom& g, int n_pairs, const double* const* f,
-                        const double* const* u, double* out2, hipStream_t st);
 // Device address of the allocation-free call's workspace on `device` (looked
 // up once per device with that device current; noalloc.hip).
 hipError_t noalloc_workspace(int device, char** ptr);
-// per sample: the largest relative jump over its `per` consecutive (|F-U|^2, |F|^2) pairs
-hipError_t launch_jump_max(const double* out2, int per, int n_samples, double* jmax, hipStream_t st);
-// per sample: Q = (sum of its M slice sums, in order) / T
-hipError_t launch_slice_qoi(const double* qn, int M, int n_samples, double T, double* q, hipStream_t st);
+// Parareal (one-launch run): Q per sample from the per-iteration slice sums
+// q [S][kcap][M] and the stopping iterations K [S] (device int32)
+hipError_t launch_para_qoi(const double* qb, const int* K, int kcap, int M, int n_samples, double T, double* q,
+                           hipStream_t st);
 // Row-sum lumping of the mass planes of n_samples tables (mass = MQ_MASS_LUMPED).
 hipError_t launch_lump_mass(const Geom& g, int n_samples, double* tables, hipStream_t st);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);

@@ -77,7 +77,8 @@ struct Req {
   int64_t t_submit = 0, t_start = 0;
   int slot = -1;
   int64_t n_total = 0, done_steps = 0;
-  int64_t iters = 0;
+  int64_t iters = 0, sweeps = 0;
+  int path = 0;
   int flags = 0;
   bool running = false;
   bool initialised = false;
@@ -176,6 +177,8 @@ void finish(mq_server* s, Req* r, int status, double q, const std::string& msg =
   res.q = q;
   res.status = status;
   res.inner_iters = (int32_t)std::min<int64_t>(r->iters, INT32_MAX);
+  res.sweeps = (int32_t)std::min<int64_t>(r->sweeps, INT32_MAX);
+  res.path = r->path;
   res.t_submit_ns = r->t_submit;
   res.t_start_ns = r->t_start;
   res.t_done_ns = now_ns();
@@ -305,6 +308,8 @@ void retire(mq_server* s, Class& c, Lane& L, hipError_t q) {
       const int* st = L.hstat.get() + i * STAT_N;
       r->done_steps += L.insts[i].n_steps;
       r->iters += st[0];
+      r->sweeps += st[1];
+      r->path = L.p->path;
       r->flags |= st[3];
     }
     if (r->done_steps >= r->n_total) {
@@ -474,6 +479,8 @@ void wide_worker(mq_server* s) {
         mq_run_stats rs{};
         rc = mlmc_level_run(p, &lv, 1, buf.get(), buf.get() + XI_SLOT, nullptr, nullptr, &rs);
         r->iters = rs.inner_iters;
+        r->sweeps = rs.sweeps;
+        r->path = MQ_PATH_WIDE;
         if (rc >= 0 && (hipMemcpyAsync(&q, buf.get() + XI_SLOT, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
                         hipStreamSynchronize(st) != hipSuccess))
           rc = MQ_ERR_DEVICE;
