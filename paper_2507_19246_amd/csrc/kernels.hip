@@ -1846,10 +1846,58 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
 // five table planes over the box region (scaled E, N, NE, D^{-1/2}, D^{1/2})
 // and, with multigrid, the
 // coarse-level vectors and Galerkin tables.
+// (rounded up to 64 elements: every slot, and every full-grid vector in it,
+// starts 16-byte aligned)
 __host__ __device__ inline size_t stream_slot_elems(const Geom& g, const MGGeom& mg, bool use_mg) {
   size_t e = 6 * (size_t)g.N * g.P + 5 * (size_t)g.RW * g.RH;
   if (use_mg) e += (size_t)mg.region_elems + (size_t)mg.ctab_elems;
-  return e;
+  return (e + 63) & ~(size_t)63;
+}
+
+// Four consecutive nodes of one row (float4 form of the streaming kernel's
+// fine passes, mixed precision).  The full-grid FP32 vectors are addressed 3
+// elements past their plane's start there, so that node (i, j) with i = 0 mod
+// 4 sits at a 16-byte boundary (needs a pitch P = N + 3, i.e. N = 1 mod 4; the
+// last accessed element, the top-right ring node, then stays inside the plane).
+typedef float f4v __attribute__((ext_vector_type(4)));
+struct F4x2 {
+  f4v a, b;
+};
+__device__ inline f4v ld4(const float* p) { return *reinterpret_cast<const f4v*>(p); }
+// store the first nv (1..4) components
+__device__ inline void st4(float* p, const f4v& v, int nv) {
+  if (nv == 4) {
+    *reinterpret_cast<f4v*>(p) = v;
+  } else {
+    p[0] = v[0];
+    if (nv > 1) p[1] = v[1];
+    if (nv > 2) p[2] = v[2];
+  }
+}
+// scaled 7-point stencil of four nodes (i0..i0+3, j): the float4 form of
+// stencil_scaled, same expression per node (gi = index of (i0, j))
+__device__ inline f4v stencil4(const Geom& g, const float* __restrict__ V, const float* tE, const float* tN,
+                               const float* tNE, int i0, int j, int gi) {
+  const int P = g.P;
+  const f4v c = ld4(V + gi), up = ld4(V + gi + P), dn = ld4(V + gi - P);
+  const float w = V[gi - 1], e = V[gi + 4], ne = V[gi + P + 4], sw = V[gi - P - 1];
+  const bool rowL = j >= g.by0 && j < g.ly1;
+  f4v out;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = i0 + k;
+    const float ck = c[k], ek = k < 3 ? c[k < 3 ? k + 1 : 0] : e, wk = k > 0 ? c[k > 0 ? k - 1 : 0] : w;
+    const float nk = up[k], sk = dn[k];
+    if (rowL && i >= g.bx0 && i < g.lx1) {
+      const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
+      const float nek = k < 3 ? up[k < 3 ? k + 1 : 0] : ne, swk = k > 0 ? dn[k > 0 ? k - 1 : 0] : sw;
+      out[k] = ck + tE[t] * ek + tE[t - 1] * wk + tN[t] * nk + tN[t - g.RW] * sk + tNE[t] * nek +
+               tNE[t - g.RW - 1] * swk;
+    } else {
+      out[k] = ck - 0.25f * ((ek + wk) + (nk + sk));
+    }
+  }
+  return out;
 }
 
 template <typename VT, int NT, bool MG>
@@ -1869,13 +1917,19 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   double* Xv = Av + FS;
   double* Bv = Xv + FS;
   double* Xprev = Bv + 2 * FS;
-  VT* Rv = vwork + (size_t)blockIdx.x * stream_slot_elems(g, mg, MG);
-  VT* Yv = Rv + FS;
-  VT* Pv = Yv + FS;
-  VT* Sv = Pv + FS;
-  VT* Wv = Sv + FS;
-  VT* Vv = Wv + FS;  // multigrid: q = A p
-  VT* tE = Vv + FS;
+  VT* const vslot = vwork + (size_t)blockIdx.x * stream_slot_elems(g, mg, MG);
+  // float4 form of the fine multigrid-CG passes (mixed precision, pitch N + 3):
+  // the six full-grid vectors are addressed 3 elements into their planes
+  constexpr bool QV = sizeof(VT) == 4 && MG;
+  const bool quad = QV && g.P == g.N + 3;
+  const int voff = quad ? 3 : 0;
+  VT* Rv = vslot + voff;
+  VT* Yv = vslot + FS + voff;
+  VT* Pv = vslot + 2 * FS + voff;
+  VT* Sv = vslot + 3 * FS + voff;
+  VT* Wv = vslot + 4 * FS + voff;
+  VT* Vv = vslot + 5 * FS + voff;  // multigrid: q = A p
+  VT* tE = vslot + 6 * FS;
   VT* tN = tE + RHW;
   VT* tNE = tN + RHW;
   VT* tD = tNE + RHW;
@@ -1886,6 +1940,12 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   int fs = 0;
   while ((1 << fs) < n && (2 << fs) <= NT) ++fs;
   const int ftx = tid & ((1 << fs) - 1), fty = NT >> fs, fj0 = tid >> fs;
+  // quad grid: 2^qs threads per row of n + 1 = 4 nq columns (the last quad holds
+  // the boundary column n, never stored)
+  const int nq = (n + 1) >> 2;
+  int qs = 0;
+  while ((1 << qs) < nq && (2 << qs) <= NT) ++qs;
+  const int qtx = tid & ((1 << qs) - 1), qty = NT >> qs, qj0 = tid >> qs;
   const double d_air = 1.0 / sqrt(4.0 * g.nu_air);
   const int lw = g.lx1 - g.bx0, lh = g.ly1 - g.by0;
   int slot = 0;
@@ -2064,6 +2124,28 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                   }
                 }
               };
+              // Four consecutive nodes per thread, one row at a time (float4 loads
+              // and stores).
+              auto quads2 = [&](auto&& ld, auto&& st) __attribute__((always_inline)) {
+                if (qtx >= nq) return;
+                const int i0 = qtx << 2;
+                const int nv = i0 + 4 <= n ? 4 : n - i0;
+                for (int j = qj0; j < n; j += qty) {
+                  const int ga = (j + 1) * g.P + i0 + 1;
+                  const F4x2 va = ld(i0, j, ga);
+                  st(ga, nv, va);
+                }
+              };
+              auto dinv4 = [&](int i0, int j) __attribute__((always_inline)) {  // D^{1/2} of four nodes
+                f4v d;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  const int i = i0 + k;
+                  const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+                  d[k] = box ? (float)tDi[(j - g.by0 + 1) * g.RW + (i - g.bx0 + 1)] : (float)(1.0 / d_air);
+                }
+                return d;
+              };
               VT* Zm = Sv;  // preconditioned residual
               VT* Tm = Wv;  // fine residual t / smoothing output (swapped with Zm)
               // coarse levels hold the unscaled operators: level 1 <-> scaled fine
@@ -2075,6 +2157,22 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
               for (;;) {
                 tick(-1);
                 // z = B r: pre-smoothing from zero (z = om r) and t = r - A z
+                if constexpr (QV) {
+                  if (quad) {
+                    const float* R4 = (const float*)Rv;
+                    quads2(
+                        [&](int i0, int j, int gi) {
+                          const f4v r = ld4(R4 + gi);
+                          const f4v ar = stencil4(g, R4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          return F4x2{(float)om * r, (r - (float)om * ar) * dinv4(i0, j)};
+                        },
+                        [&](int gi, int nv, const F4x2& v) {
+                          st4((float*)Zm + gi, v.a, nv);
+                          st4((float*)Tm + gi, v.b, nv);
+                        });
+                  }
+                }
+                if (!quad)
                 nodes2(
                     [&](int i, int j, const NodeRef& nr) {
                       const VT r = Rv[nr.gi];
@@ -2102,6 +2200,21 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                                                     sv.mg_block_min);
                 __syncthreads();
                 tick(1);
+                if constexpr (QV) {
+                  if (quad) {
+                    quads2(
+                        [&](int i0, int j, int gi) {
+                          f4v z = ld4((const float*)Zm + gi);
+                          const f4v di = dinv4(i0, j);
+#pragma unroll
+                          for (int k = 0; k < 4; ++k)
+                            if (i0 + k < n) z[k] = z[k] + (float)prolong_at(z1, L1.np, i0 + k, j) * di[k];
+                          return F4x2{z, z};
+                        },
+                        [&](int gi, int nv, const F4x2& v) { st4((float*)Zm + gi, v.a, nv); });
+                  }
+                }
+                if (!quad)
                 nodes2(
                     [&](int i, int j, const NodeRef& nr) {
                       return V2{Zm[nr.gi] + prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr), VT(0)};
@@ -2110,6 +2223,25 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                 __syncthreads();
                 // post-smoothing z <- z + om (r - A z); r.z and r.r of the new z
                 double rz[2] = {0.0, 0.0};
+                if constexpr (QV) {
+                  if (quad) {
+                    const float* Z4 = (const float*)Zm;
+                    quads2(
+                        [&](int i0, int j, int gi) {
+                          const f4v r = ld4((const float*)Rv + gi), z = ld4(Z4 + gi);
+                          const f4v az = stencil4(g, Z4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          return F4x2{z + (float)om * (r - az), r};
+                        },
+                        [&](int gi, int nv, const F4x2& v) {
+                          st4((float*)Tm + gi, v.a, nv);
+                          for (int k = 0; k < nv; ++k) {
+                            rz[0] += (double)(v.b[k] * v.a[k]);
+                            rz[1] += (double)(v.b[k] * v.b[k]);
+                          }
+                        });
+                  }
+                }
+                if (!quad)
                 nodes2(
                     [&](int, int, const NodeRef& nr) {
                       const VT r = Rv[nr.gi], z = Zm[nr.gi];
@@ -2137,6 +2269,23 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                 // p = z + beta p and q = A p = A z + beta q (one pass)
                 const VT b_ = vt<VT>(beta);
                 double pq[1] = {0.0};
+                if constexpr (QV) {
+                  if (quad) {
+                    const float* Z4 = (const float*)Zm;
+                    quads2(
+                        [&](int i0, int j, int gi) {
+                          const f4v az = stencil4(g, Z4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          return F4x2{ld4(Z4 + gi) + (float)b_ * ld4((const float*)Pv + gi),
+                                      az + (float)b_ * ld4((const float*)Vv + gi)};
+                        },
+                        [&](int gi, int nv, const F4x2& v) {
+                          st4((float*)Pv + gi, v.a, nv);
+                          st4((float*)Vv + gi, v.b, nv);
+                          for (int k = 0; k < nv; ++k) pq[0] += (double)(v.a[k] * v.b[k]);
+                        });
+                  }
+                }
+                if (!quad)
                 nodes2(
                     [&](int, int, const NodeRef& nr) {
                       return V2{Zm[nr.gi] + b_ * Pv[nr.gi], stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr) + b_ * Vv[nr.gi]};
@@ -2148,6 +2297,20 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                     });
                 block_sum<1, NWAVES>(pq, red, slot);
                 const VT a_ = vt<VT>(rho / pq[0]);
+                if constexpr (QV) {
+                  if (quad) {
+                    quads2(
+                        [&](int, int, int gi) {
+                          return F4x2{ld4((const float*)Yv + gi) + (float)a_ * ld4((const float*)Pv + gi),
+                                      ld4((const float*)Rv + gi) - (float)a_ * ld4((const float*)Vv + gi)};
+                        },
+                        [&](int gi, int nv, const F4x2& v) {
+                          st4((float*)Yv + gi, v.a, nv);
+                          st4((float*)Rv + gi, v.b, nv);
+                        });
+                  }
+                }
+                if (!quad)
                 nodes2(
                     [&](int, int, const NodeRef& nr) {
                       return V2{Yv[nr.gi] + a_ * Pv[nr.gi], Rv[nr.gi] - a_ * Vv[nr.gi]};

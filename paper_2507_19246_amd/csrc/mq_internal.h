@@ -79,8 +79,11 @@ __host__ __device__ inline size_t res_plane_doubles(const Geom& g) {
 // previous increment, Picard increment (full-grid), the per-node D^{-1/2}
 // plane (thread-private), then the instance's FP64 tables (planes + k1', k2',
 // k3')
+// (rounded up to 256 bytes, so that the streaming vectors after the slots
+// start 16-byte aligned)
 __host__ __device__ inline size_t ie_work_doubles(const Geom& g) {
-  return 5 * (size_t)g.N * g.P + 2 * res_plane_doubles(g) + (size_t)T_NPLANES * g.RW * g.RH + 3;
+  const size_t d = 5 * (size_t)g.N * g.P + 2 * res_plane_doubles(g) + (size_t)T_NPLANES * g.RW * g.RH + 3;
+  return (d + 31) & ~(size_t)31;
 }
 
 // Element data over the cells that touch the box: full-grid cells
