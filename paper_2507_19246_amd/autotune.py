@@ -77,14 +77,20 @@ def candidates(problem, precision: int) -> List[Dict]:
     return out
 
 
-# second stage: coarse-hierarchy variants (levels in use, coarsest sweeps)
-COARSE_VARIANTS = [(3, 4), (3, 6), (3, 8), (4, 2), (4, 4)]
+# second stage: coarse-hierarchy variants (levels in use, coarsest sweeps); the
+# deeper ones only where the hierarchy has more levels than that
+COARSE_VARIANTS = [(3, 4), (3, 6), (3, 8), (4, 2), (4, 4), (5, 2), (5, 4)]
 
 
-def coarse_candidates(best_knobs: Dict, resolved_precond: int) -> List[Dict]:
+def coarse_candidates(best_knobs: Dict, resolved_precond: int, n_nodes: int = 0) -> List[Dict]:
     if resolved_precond != L.MQ_PRECOND_MULTIGRID:
         return []
-    return [dict(best_knobs, mg_levels=lv, mg_coarse_sweeps=sw) for lv, sw in COARSE_VARIANTS]
+    n, depth = n_nodes - 2, 0
+    while n > 1:  # levels below the fine one: n -> (n - 1) / 2 down to one node
+        n = (n - 1) // 2
+        depth += 1
+    return [dict(best_knobs, mg_levels=lv, mg_coarse_sweeps=sw) for lv, sw in COARSE_VARIANTS
+            if n_nodes == 0 or lv < depth]
 
 
 def _load(path: str) -> Dict:
@@ -153,7 +159,7 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
     for knobs in [{}] + candidates(problem, precision):
         trial(knobs)
     best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
-    for knobs in coarse_candidates(best["knobs"], best["resolved"]["precond"]):
+    for knobs in coarse_candidates(best["knobs"], best["resolved"]["precond"], problem.n_nodes):
         trial(knobs)
     best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
     db = _load(path)
