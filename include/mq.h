@@ -355,10 +355,10 @@ int parareal_run(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, c
 /* MLMC with Parareal on the finest level (Section II-D): levels 0..L-1 and
  * the coupled coarse runs of level L are batched as in mlmc_multilevel_run,
  * while the fine values of level L come from Parareal (as parareal_run) with
- * the level L-2 discretisation as coarse propagator, both at once on the
- * device (the Parareal part runs on a second set-up of the same problem with
- * a stream of its own, created on the first call and kept with p; the batched
- * part's launch leaves N_L * M persistent slots to it, at most half).
+ * the level L-2 discretisation as coarse propagator, all in ONE persistent
+ * launch with two work queues: the Parareal entries and the level instances;
+ * N_L * M workgroups (at most half) start on the Parareal queue, the others on
+ * the levels, and a workgroup whose queue is empty moves to the other one.
  * n_slices = 0 picks M from Eq. (25) with the device's persistent slots as
  * cores: the largest power of two <= max(2, n_c,para) that divides the fine
  * and coarse step counts of level L (a given M must divide both).  q_coarse[L] is bitwise what
@@ -375,14 +375,14 @@ typedef struct mq_combined_desc {
 
 typedef struct mq_combined_stats {
   int32_t n_slices, coarse_steps_per_period, n_cores, n_c_para;
-  double ms_levels;    /* wall time of the batched part */
-  double ms_parareal;  /* wall time of level L's Parareal */
+  double ms_levels;    /* device time from the launch's start to the last level instance's end */
+  double ms_parareal;  /* device time from the launch's start to the last Parareal entry's end */
   double ms_total;
   int64_t para_fine_steps, para_coarse_steps;  /* sample-steps Parareal executed (all samples) */
   double mean_k;
   int32_t max_k;
-  int32_t level_slots;  /* persistent slots of the batched part: the device's n_cores less
-                           N_L * M (at most half) kept for the Parareal part */
+  int32_t level_slots;  /* workgroups that start on the level queue: the device's n_cores less
+                           N_L * M (at most half) that start on the Parareal queue */
 } mq_combined_stats;
 
 int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, const int32_t* n_samples,

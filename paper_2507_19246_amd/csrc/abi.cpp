@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -86,17 +87,19 @@ size_t max_slots(const mq_problem* p) {
 }
 
 int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block, double* work,
-                      size_t work_slots) {
+                      size_t work_slots, int n_first, int grid_first, bool para) {
   if (!work) {
     work = p->work.get();
     work_slots = p->work_slots;
   }
   size_t slots = std::min<size_t>((size_t)n, max_slots(p));
-  if (p->grid_cap > 0) slots = std::min<size_t>(slots, (size_t)p->grid_cap);
   slots = std::min(slots, work_slots);
   if (slots < 1) return fail(MQ_ERR_INVALID_ARG, "work buffer smaller than the launch");
-  HIP_TRY(launch_fill_zero_i(p->dcounter.get(), 1, p->stream));
-  const Solver sv = solver_of(p);
+  // one queue unless asked: every entry in queue 0, every workgroup starts there
+  HIP_TRY(launch_queue_init(p->dcounter.get(), n_first >= 0 ? n_first : n, grid_first >= 0 ? grid_first : INT_MAX,
+                            p->stream));
+  Solver sv = solver_of(p);
+  sv.para = para ? 1 : 0;
   // the slot layout of the work buffer is fixed by its allocation (work_slots);
   // the grid is the occupancy-limited slot count
   hipError_t le = launch_ie(p->hm.g, p->mg, sv, dinst, n, p->dcounter.get(), work, (int)work_slots,
@@ -170,6 +173,11 @@ struct RunOut {
   // host time (now_ms) of the call's start: when > 0, run_instances reports
   // latency as the time from it until a sample's Q is readable in host memory
   double t_submit_ms = 0;
+  // two work queues in one launch: entries [0, queue0) form the first queue,
+  // taken first by workgroups [0, grid0); -1: one queue
+  int queue0 = -1, grid0 = -1;
+  // device time from the launch's first start to the last end of each queue's entries
+  double done_ms[2] = {0, 0};
   std::vector<int> flags;  // FLAG_* bits per instance, appended by each run_instances call in its order
   double kernel_ms = 0;
   int grid = 0, block = 0;
@@ -299,7 +307,6 @@ int plan_split(mq_problem* p, const std::vector<Inst>& insts, Split& out, bool* 
   *used = false;
   const size_t n = insts.size();
   size_t slots = std::min(n, max_slots(p));
-  if (p->grid_cap > 0) slots = std::min(slots, (size_t)p->grid_cap);
   const int S = p->d.split_steps == 0 ? 32 : p->d.split_steps;
   if (p->d.split_steps < 0 || p->path != MQ_PATH_RESIDENT || p->d.material == MQ_MAT_NONLINEAR || n <= slots)
     return MQ_OK;
@@ -428,7 +435,8 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
     HIP_TRY(hipStreamSynchronize(p->stream));
     t_launch = now_ms();
   }
-  rc = launch_persistent(p, dinst, nr, &ro->grid, &ro->block, fwork, fixed ? slots : 0);
+  const bool para = std::any_of(run.begin(), run.end(), [](const Inst& in) { return in.para != nullptr; });
+  rc = launch_persistent(p, dinst, nr, &ro->grid, &ro->block, fwork, fixed ? slots : 0, ro->queue0, ro->grid0, para);
   if (rc) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -479,6 +487,10 @@ int run_instances(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, Run
   };
   uint64_t t_first = ~0ull;
   for (int i = 0; i < nr; ++i) t_first = std::min(t_first, stamp(i, 0));
+  for (int i = 0; i < nr; ++i) {
+    const int qq = (ro->queue0 >= 0 && i >= ro->queue0) ? 1 : 0;
+    ro->done_ms[qq] = std::max(ro->done_ms[qq], (double)(stamp(i, 1) - t_first) / p->wall_khz);
+  }
   {
     // per group (sample): host-visible completion after the call's start, or
     // device time after the first entry started
@@ -730,7 +742,7 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
     HIP_TRY(dev_alloc(p->dkl, p->hm.kl.size()));
     HIP_TRY(copy_sync(p->dkl.get(), p->hm.kl.data(), p->hm.kl.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   }
-  HIP_TRY(dev_alloc(p->dcounter, 1));
+  HIP_TRY(dev_alloc(p->dcounter, 4));  // work queue: two positions, split, first-queue workgroups
   HIP_TRY(dev_alloc(p->dflag, 1));
   HIP_TRY(noalloc_workspace(p->device, &p->scratch));
   (void)g;
@@ -740,8 +752,6 @@ int fem_setup(const mq_problem_desc* d, void* stream, mq_problem** out) {
 
 int mq_problem_destroy(mq_problem* p) {
   if (!p) return MQ_OK;
-  if (p->twin) mq_problem_destroy(p->twin);
-  if (p->twin_stream) (void)hipStreamDestroy(p->twin_stream);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   delete p;
@@ -1107,34 +1117,58 @@ int mlmc_multimesh_run(int32_t n_levels, mq_problem* const* problems, const mq_l
 // the sequential algorithm's (Eqs. (13)-(14)).  Fine end states alternate
 // between two buffers by the parity of j, because fine (j+1, n) can finish
 // before chain (j) has read F_n^(j).
-static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
-                            double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
-  last_flags().clear();
-  if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
-  if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "Parareal runs on the resident or streaming path");
-  if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
-  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+// Queue entries and buffers of a one-launch Parareal run (para_build), and
+// its results after the launch (para_finish).
+struct ParaRun {
+  CallMem mem;
+  int S = 0, M = 0, kcap = 0, fs = 0, cs = 0;
+  double T = 0;
+  double* Fb = nullptr;
+  double* qb = nullptr;
+  int* Kd = nullptr;
+  int* pfl = nullptr;
+  std::vector<Inst> insts;
+};
+
+static int para_validate(const mq_problem* p, const mq_parareal_desc* pd) {
   const int M = pd->n_slices, fs = pd->fine_steps_per_slice, cs = pd->coarse_steps_per_slice;
   if (M < 1 || fs < 1 || cs < 1 || pd->n_periods < 1 || pd->k_max < 1 || pd->fixed_k < 0 || !(pd->tol >= 0))
     return fail(MQ_ERR_INVALID_ARG, "invalid Parareal description");
   if ((int64_t)M * fs > (1 << 24) || (int64_t)M * cs > (1 << 24)) return fail(MQ_ERR_INVALID_ARG, "too many steps");
-  const double t_start = now_ms();
-  if (st) std::memset(st, 0, sizeof(*st));
-  int rc = check_finite(p, xi, (size_t)n_samples * p->n_xi);
-  if (rc) return rc;
+  if (p->path == MQ_PATH_WIDE) return fail(MQ_ERR_INVALID_ARG, "Parareal runs on the resident or streaming path");
+  return MQ_OK;
+}
+
+// Entries of Parareal (Section II-C, Eq. (12)) for S samples whose tables are
+// assembled in `tables` ([S][tab_stride]); appended to pr.insts (group and
+// sample = the sample index).  The launch's work queue holds, per sample,
+// the initial coarse chain, then per iteration j = 1..kcap the fine slices n =
+// j..M and the coarse chain of iteration j, which first takes the stopping
+// decision from the interface jumps of Section II-C and then corrects U_n =
+// F_n + (C_new - C_old), n = j+1..M-1.  Entries wait on flags in device memory:
+//   fine (j, n)   waits for U_{n-1}^(j-1): the chain of iteration j-1 (segment
+//                 n-1, or its first step U_{j-1} = F_{j-1} for n = j; the
+//                 initial chain for j = 1; U_0 needs no wait);
+//   chain (j)     waits for the chain of iteration j-1, then for the fine slices
+//                 n = j..M of iteration j, one by one, while it sums the jumps.
+// Every wait is for an entry queued before the waiting one, so every wait ends
+// (checked here before the launch); and the sweep of iteration j+1 overlaps
+// the correction chain of iteration j (fine (j+1, n) starts once the chain has
+// passed slice n-1).  A sample that stops at iteration K skips its later
+// entries; the executed work is exactly the sequential algorithm's (Eqs.
+// (13)-(14)).  Fine end states alternate between two buffers by the parity of
+// j, because fine (j+1, n) can finish before chain (j) has read F_n^(j).
+static int para_build(mq_problem* p, const mq_parareal_desc* pd, int S, const double* tables, ParaRun& pr) {
   const Geom& g = p->hm.g;
   const size_t FS = (size_t)g.N * g.P;
-  TmpPtr<double> tables;
-  rc = assemble(p, xi, n_samples, tables);
-  if (rc) return rc;
+  const int M = pd->n_slices, fs = pd->fine_steps_per_slice, cs = pd->coarse_steps_per_slice;
+  CallMem& mem = pr.mem;
+  mem.use_stream(p->stream);
   const double T = pd->n_periods / p->d.freq;
   const double dtf = T / ((double)M * fs), dtc = T / ((double)M * cs);
   auto sf = source_table(p->d, dtf, M * fs);
   auto sc = source_table(p->d, dtc, M * cs);
-  const int S = n_samples;
   const int kcap = std::min(pd->fixed_k > 0 ? pd->fixed_k : pd->k_max, M);
-  CallMem mem;
-  mem.use_stream(p->stream);
   double *dsf, *dsc, *Ub, *Fb, *Cb, *qb, *Jb;
   int *segd, *fdone, *chd, *Kd, *pfl, *abortf;
   ParaCtl* dctl;
@@ -1196,7 +1230,7 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
   std::vector<Arr> arrs;
   auto base = [&](int s_) {
     Inst in{};
-    in.tab = tables.get() + (size_t)s_ * tab_stride(g);
+    in.tab = tables + (size_t)s_ * tab_stride(g);
     in.sample = s_;
     in.group = s_;
     in.para = dctl;
@@ -1338,16 +1372,40 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
       in.jump_wait = (const int* const*)(dptrs + a.jw);
     }
   }
-  RunOut ro;
-  rc = run_instances(p, insts, st, &ro, nullptr);
-  if (rc) return rc;
-  std::vector<int> Kh(S), ph(S);
-  HIP_TRY(hipMemcpyAsync(Kh.data(), Kd, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipMemcpyAsync(ph.data(), pfl, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  pr.S = S;
+  pr.M = M;
+  pr.kcap = kcap;
+  pr.fs = fs;
+  pr.cs = cs;
+  pr.T = T;
+  pr.Fb = Fb;
+  pr.qb = qb;
+  pr.Kd = Kd;
+  pr.pfl = pfl;
+  pr.insts = std::move(insts);
+  return MQ_OK;
+}
+
+// After the launch: per-sample K, flags (entry_flags: FLAG_* per entry of
+// pr.insts, in order), Q (device), K (device iters), final states (nullable),
+// executed sample-steps.  Returns MQ_WARN_NOT_CONVERGED when a sample
+// reached k_max above tol or an entry hit a solver cap.
+static int para_finish(mq_problem* p, ParaRun& pr, const int* entry_flags, double* q, int32_t* iters,
+                       double* final_state, std::vector<int32_t>& pflags, std::vector<int>& Kh, int64_t* steps_out) {
+  const Geom& g = p->hm.g;
+  const size_t FS = (size_t)g.N * g.P;
+  const int S = pr.S, M = pr.M, kcap = pr.kcap, fs = pr.fs, cs = pr.cs;
+  const double T = pr.T;
+  double* const Fb = pr.Fb;
+  auto F = [&](int j_, int s_, int n_) { return Fb + (((size_t)(j_ & 1) * S + s_) * M + (n_ - 1)) * FS; };
+  Kh.assign(S, 0);
+  std::vector<int> ph(S);
+  HIP_TRY(hipMemcpyAsync(Kh.data(), pr.Kd, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(ph.data(), pr.pfl, S * sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   bool warn = false;
-  std::vector<int32_t> pflags(S, 0);
-  for (size_t e = 0; e < insts.size(); ++e) pflags[insts[e].sample] |= ro.flags[e];
+  pflags.assign(S, 0);
+  for (size_t e = 0; e < pr.insts.size(); ++e) pflags[pr.insts[e].sample] |= entry_flags[e];
   for (int s_ = 0; s_ < S; ++s_) {
     pflags[s_] |= ph[s_];
     if (Kh[s_] < 1 || Kh[s_] > kcap) {  // no decision reached (a timed-out wait)
@@ -1358,33 +1416,65 @@ static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n
   }
   HIP_TRY(copy_sync(iters, Kh.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   // Q = sum_n q_n / T with q_n of each slice's latest fine run, iteration min(n, K) (FP64, device)
-  HIP_TRY(launch_para_qoi(qb, iters, kcap, M, S, T, q, p->stream));
+  HIP_TRY(launch_para_qoi(pr.qb, iters, kcap, M, S, T, q, p->stream));
   if (final_state) {
     std::vector<const double*> fp(S);
     for (int s_ = 0; s_ < S; ++s_) fp[s_] = F(Kh[s_], s_, M);
     const double** dfp = nullptr;
-    HIP_TRY(mem.get(dfp, S));
+    HIP_TRY(pr.mem.get(dfp, S));
     HIP_TRY(copy_sync(dfp, fp.data(), S * sizeof(double*), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(launch_to_interior(g, S, dfp, final_state, p->stream));
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
+  // executed work of the sequential algorithm with these K (entries that
+  // skipped ran nothing): initial chain (M-1) C, per iteration j <= K the fine
+  // slices j..M, per correction j < K the slices j+1..M-1
+  int64_t steps = 0;
+  for (int s_ = 0; s_ < S; ++s_) {
+    steps += (int64_t)(M - 1) * cs;
+    for (int j_ = 1; j_ <= Kh[s_]; ++j_) steps += (int64_t)(M - j_ + 1) * fs;
+    for (int j_ = 1; j_ < Kh[s_]; ++j_) steps += (int64_t)std::max(0, M - 1 - j_) * cs;
+  }
+  if (steps_out) *steps_out = steps;
+  return warn ? MQ_WARN_NOT_CONVERGED : MQ_OK;
+}
+
+// Parareal for n_samples samples in one persistent launch (para_build).
+static int parareal_run_dev(mq_problem* p, const mq_parareal_desc* pd, int32_t n_samples, const double* xi,
+                            double* q, int32_t* iters, double* final_state, mq_run_stats* st) {
+  last_flags().clear();
+  if (!p || !pd) return fail(MQ_ERR_INVALID_ARG, "null argument");
+  if (!xi || !q || !iters) return fail(MQ_ERR_INVALID_ARG, "xi, q and iters are required");
+  if (n_samples < 1) return fail(MQ_ERR_INVALID_ARG, "n_samples must be >= 1");
+  int rc = para_validate(p, pd);
+  if (rc) return rc;
+  if (p->d.material == MQ_MAT_NONLINEAR) return fail(MQ_ERR_INVALID_ARG, "Parareal takes linear materials");
+  const double t_start = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  rc = check_finite(p, xi, (size_t)n_samples * p->n_xi);
+  if (rc) return rc;
+  TmpPtr<double> tables;
+  rc = assemble(p, xi, n_samples, tables);
+  if (rc) return rc;
+  ParaRun pr;
+  rc = para_build(p, pd, n_samples, tables.get(), pr);
+  if (rc) return rc;
+  RunOut ro;
+  rc = run_instances(p, pr.insts, st, &ro, nullptr);
+  if (rc) return rc;
+  std::vector<int32_t> pflags;
+  std::vector<int> Kh;
+  int64_t steps = 0;
+  const int rf = para_finish(p, pr, ro.flags.data(), q, iters, final_state, pflags, Kh, &steps);
+  if (rf < 0) return rf;
   if (st) {
-    // executed work of the sequential algorithm with these K (entries that
-    // skipped ran nothing): initial chain (M-1) C, per iteration j <= K the
-    // fine slices j..M, per correction j < K the slices j+1..M-1
-    int64_t steps = 0;
-    for (int s_ = 0; s_ < S; ++s_) {
-      steps += (int64_t)(M - 1) * cs;
-      for (int j_ = 1; j_ <= Kh[s_]; ++j_) steps += (int64_t)(M - j_ + 1) * fs;
-      for (int j_ = 1; j_ < Kh[s_]; ++j_) steps += (int64_t)std::max(0, M - 1 - j_) * cs;
-    }
     st->sample_steps = steps;
-    st->n_instances = (int64_t)insts.size();
+    st->n_instances = (int64_t)pr.insts.size();
     st->total_ms = now_ms() - t_start;
   }
   last_flags() = pflags;
-  if (warn) {
-    last_error() = "Parareal reached k_max above the tolerance for some samples";
+  if (rf == MQ_WARN_NOT_CONVERGED) {
+    last_error() = "Parareal reached k_max above the tolerance (or a solver cap) for some samples";
     return MQ_WARN_NOT_CONVERGED;
   }
   return ro.status;
@@ -1428,27 +1518,6 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
   if (M < 2 || fine_total % M || coarse_total % M)
     return fail(MQ_ERR_INVALID_ARG, "the slices (>= 2) must divide the fine and coarse step counts of level L");
   const int kmax = cd->k_max > 0 ? cd->k_max : M;
-  if (!p->twin) {
-    hipStream_t ts = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking));
-    mq_problem* tw = nullptr;
-    const int rc = fem_setup(&p->d, (void*)ts, &tw);
-    if (rc) {
-      (void)hipStreamDestroy(ts);
-      return rc;
-    }
-    p->twin = tw;
-    p->twin_stream = ts;
-  }
-  // the Parareal part starts from the same a_0 as the batched part
-  if (p->a0) {
-    const size_t FS = (size_t)p->hm.g.N * p->hm.g.P;
-    if (!p->twin->a0) HIP_TRY(dev_alloc(p->twin->a0, FS));
-    HIP_TRY(copy_sync(p->twin->a0.get(), p->a0.get(), FS * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-  } else if (p->twin->a0) {
-    HIP_TRY(hipStreamSynchronize(p->twin_stream));
-    p->twin->a0.reset();
-  }
   const double t0 = now_ms();
   if (st) std::memset(st, 0, sizeof(*st));
   // batched part: levels 0..L-1 and the coupled coarse runs of level L
@@ -1470,44 +1539,32 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     for (auto& i : c) keyed.push_back({i.n_steps, i});
   }
   std::stable_sort(keyed.begin(), keyed.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  std::vector<Inst> all;
-  for (auto& k : keyed) all.push_back(k.second);
-  // size both work buffers before the two parts overlap (growing one frees memory)
-  int rc = ensure_work(p, std::min(all.size(), max_slots(p)));
-  if (rc) return rc;
-  rc = ensure_work(p->twin, std::min<size_t>((size_t)n_samples[L] * M, max_slots(p->twin)));
-  if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(p->twin_stream));
-  // Eq. (25) on the device: the batched part leaves N_L * M slots (at most half
-  // of them) to the Parareal part, so both run at once
-  const int level_slots = n_c - std::min(n_samples[L] * M, n_c / 2);
-  struct CapGuard {
-    mq_problem* p;
-    ~CapGuard() { p->grid_cap = 0; }
-  } cap_guard{p};
-  p->grid_cap = level_slots;
-  mq_run_stats sa{}, sb{};
-  RunOut ro;
-  int rca = MQ_OK;
-  std::string erra;
-  double ms_a = 0;
-  std::thread ta([&] {
-    (void)hipSetDevice(p->device);
-    const double ta0 = now_ms();
-    rca = run_instances(p, all, &sa, &ro, nullptr);
-    if (rca < 0) erra = last_error();
-    ms_a = now_ms() - ta0;
-  });
-  const double tb0 = now_ms();
+  // level L's fine values by Parareal (Section II-D), on the tables of its samples
   const mq_parareal_desc pd{nper, M, (int32_t)(fine_total / M), (int32_t)(coarse_total / M), kmax, 0, cd->tol};
-  const int rcb = parareal_run_dev(p->twin, &pd, n_samples[L], xi[L], q_fine[L], para_iters, nullptr, &sb);
-  const std::string errb = rcb < 0 ? last_error() : std::string();
-  const double ms_b = now_ms() - tb0;
-  ta.join();
-  if (rca < 0) return fail(rca, erra);
-  if (rcb < 0) return fail(rcb, errb);
-  std::vector<int32_t> K(n_samples[L]);
-  HIP_TRY(copy_sync(K.data(), para_iters, K.size() * sizeof(int32_t), hipMemcpyDeviceToHost, p->twin_stream));
+  int rc = para_validate(p, &pd);
+  if (rc) return rc;
+  ParaRun pr;
+  rc = para_build(p, &pd, n_samples[L], lbs[L].tables, pr);
+  if (rc) return rc;
+  // ONE persistent launch: the Parareal entries form the first work queue, the
+  // level instances (longest first) the second.  Eq. (25) on the device: N_L * M
+  // workgroups (at most half) start on the Parareal queue, the others on the
+  // levels; a workgroup whose queue is empty moves to the other one.
+  const int n_para = (int)pr.insts.size();
+  std::vector<Inst> all = pr.insts;
+  for (auto& k : keyed) all.push_back(k.second);
+  const int level_slots = n_c - std::min(n_samples[L] * M, n_c / 2);
+  RunOut ro;
+  ro.queue0 = n_para;
+  ro.grid0 = n_c - level_slots;
+  rc = run_instances(p, all, st, &ro, nullptr);
+  if (rc) return rc;
+  std::vector<int32_t> pflags;
+  std::vector<int> Kh;
+  int64_t para_steps = 0;
+  const int rcb = para_finish(p, pr, ro.flags.data(), q_fine[L], para_iters, nullptr, pflags, Kh, &para_steps);
+  if (rcb < 0) return rcb;
+  const std::vector<int>& K = Kh;
   // executed work: fine slices j..M in iteration j; coarse chains over M - j slices
   // before iteration j + 1 while the sample is still iterating (the first one is the
   // initial prediction)
@@ -1523,20 +1580,11 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     ksum += k;
   }
   if (st) {
-    for (const mq_run_stats* s : {&sa, &sb}) {
-      st->n_instances += s->n_instances;
-      st->sample_steps += s->sample_steps;
-      st->inner_iters += s->inner_iters;
-      st->sweeps += s->sweeps;
-      st->max_inner_per_step = std::max(st->max_inner_per_step, s->max_inner_per_step);
-      st->n_not_converged += s->n_not_converged;
-      st->n_failed += s->n_failed;
-      st->n_pieces += s->n_pieces;
-      st->kernel_ms += s->kernel_ms;
-    }
-    st->path = sa.path;
-    st->grid = sa.grid;
-    st->block = sa.block;
+    // executed work: the level instances ran whole; the Parareal entries ran
+    // the sequential algorithm's work for these K
+    int64_t level_steps = 0;
+    for (auto& k : keyed) level_steps += k.second.n_steps;
+    st->sample_steps = level_steps + para_steps;
     st->total_ms = now_ms() - t0;
   }
   if (cs) {
@@ -1545,8 +1593,8 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     cs->coarse_steps_per_period = cspp;
     cs->n_cores = n_c;
     cs->n_c_para = n_c_para;
-    cs->ms_levels = ms_a;
-    cs->ms_parareal = ms_b;
+    cs->ms_levels = ro.done_ms[1];    // device time to the last level instance's end
+    cs->ms_parareal = ro.done_ms[0];  // ... and to the last Parareal entry's end
     cs->ms_total = now_ms() - t0;
     cs->para_fine_steps = fsteps;
     cs->para_coarse_steps = csteps;
@@ -1554,7 +1602,7 @@ int mlmc_combined_run(mq_problem* p, int32_t n_levels, const mq_level_desc* lv, 
     cs->max_k = kmx;
     cs->level_slots = level_slots;
   }
-  if (rcb == MQ_WARN_NOT_CONVERGED) last_error() = errb.empty() ? "Parareal reached k_max above the tolerance" : errb;
+  if (rcb == MQ_WARN_NOT_CONVERGED) last_error() = "Parareal reached k_max above the tolerance for some samples";
   return std::max(ro.status, rcb);
 }
 

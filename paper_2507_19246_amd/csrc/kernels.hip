@@ -217,6 +217,43 @@ __device__ inline void block_sum(double (&v)[NV], double* red, int& slot) {
 }
 
 // ---------------------------------------------------------------------------
+// Persistent work queue: two queues in one launch
+// ---------------------------------------------------------------------------
+// counter[0], counter[1]: next position in queue 0 (entries [0, counter[2]))
+// and queue 1 (entries [counter[2], n_inst)); workgroups below counter[3]
+// start on queue 0, the others on queue 1, and each moves to the other queue
+// once its own is empty.  Called by thread 0; returns n_inst when both queues
+// are empty.  Within a queue, entries are handed out in order.
+__device__ inline int queue_next(int* counter, int n_inst, int& q, int& moved) {
+  const int n0 = counter[2];
+  for (;;) {
+    const int base = q == 0 ? 0 : n0, end = q == 0 ? n0 : n_inst;
+    if (base < end) {
+      const int k = atomicAdd(counter + q, 1);
+      if (base + k < end) return base + k;
+    }
+    if (moved) return n_inst;
+    moved = 1;
+    q ^= 1;
+  }
+}
+
+__global__ void k_queue_init(int* counter, int n_first, int grid_first) {
+  if (threadIdx.x == 0) {
+    counter[0] = 0;
+    counter[1] = 0;
+    counter[2] = n_first;
+    counter[3] = grid_first;
+  }
+}
+
+hipError_t launch_queue_init(int* counter, int n_first, int grid_first, hipStream_t st) {
+  (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
+  hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(64), 0, st, counter, n_first, grid_first);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Parareal in one persistent launch: flags between queue entries
 // ---------------------------------------------------------------------------
 // Wait (thread 0, bounded) until *f is set, then make the writer's data visible
@@ -696,7 +733,7 @@ __device__ void build_galerkin(const MGGeom& mg, VT* ctab, const VT* tE, const V
 // LDS pitches are compile-time constants (LP = CW + 2 for the grid, TP for
 // the tables) so that every per-node LDS offset folds into the instruction's
 // immediate offset instead of occupying a register.
-template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL>
+template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL, bool PARA>
 __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solver sv,
                                                         const Inst* __restrict__ insts, int n_inst,
                                                         int* counter, double* work,
@@ -751,8 +788,9 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   // live across the whole loop, which exhausts the scalar register file.
   auto refresh = [&]() __attribute__((always_inline)) {
     // opaque to the optimiser, and back to a scalar register where the slice
-    // is wave-uniform (readfirstlane instead of an "s" constraint, which the
-    // backend cannot always honour once j0 is carried around the entry loop)
+    // is wave-uniform (readfirstlane rather than an "s" asm constraint, which
+    // the backend cannot honour once the Parareal entry prologue is present,
+    // and which spills more here)
     asm volatile("" : "+v"(j0));
     if constexpr (CW % 64 == 0) j0 = __builtin_amdgcn_readfirstlane(j0);
     asm volatile("" : "+v"(l0), "+v"(s0));
@@ -773,8 +811,9 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     return col_box && j >= g.by0 && j < g.by1;
   };
 
+  int q_cur = (int)blockIdx.x < counter[3] ? 0 : 1, q_moved = 0;  // work queue of this workgroup (thread 0)
   for (;;) {
-    if (tid == 0) s_inst = atomicAdd(counter, 1);
+    if (tid == 0) s_inst = queue_next(counter, n_inst, q_cur, q_moved);
     __syncthreads();
     const int id = s_inst;
     __syncthreads();
@@ -841,8 +880,9 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
       if (tid == 0) {
         const unsigned long long tw = wall_clock64();
         int ok = 1;
-        const unsigned long long lim = in.para ? PARA_WAIT_TICKS : DEP_WAIT_TICKS;
-        int* abort = in.para ? in.para->abort : nullptr;
+        const unsigned long long lim = PARA ? PARA_WAIT_TICKS : DEP_WAIT_TICKS;
+        int* abort = nullptr;
+        if constexpr (PARA) abort = in.para ? in.para->abort : nullptr;
         while (__hip_atomic_load(in.dep_wait, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
           if (wall_clock64() - tw > lim ||
               (abort && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
@@ -861,17 +901,18 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
     }
     // Parareal entry of a one-launch run: skip (sample stopped, or stopped by
     // this chain's jumps) or run; a continuing chain has written U_j
-    // (called for every entry; the branch is made wave-uniform: it leaves the
-    // entry as a whole)
-    if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
-      if (tid == 0 && in.stat) {
-        in.stat[3] = dep_flags;
-        in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
-        in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+    // (the branch is made wave-uniform: it leaves the entry as a whole)
+    if constexpr (PARA) {
+      if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
+        if (tid == 0 && in.stat) {
+          in.stat[3] = dep_flags;
+          in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
+          in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+        }
+        if (in.dep_done) para_set(in.dep_done);
+        __syncthreads();
+        continue;
       }
-      if (in.dep_done) para_set(in.dep_done);
-      __syncthreads();
-      continue;
     }
     for (int t = tid; t < (n + 2) * LP; t += NT) rl[t] = VT(0);
 #pragma unroll 1
@@ -1374,7 +1415,8 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
           }
         }
         __syncthreads();
-        if (in.seg_done) para_set(in.seg_done[seg]);
+        if constexpr (PARA)
+          if (in.seg_done) para_set(in.seg_done[seg]);
       }
     }
     if (in.a_out) {
@@ -1528,7 +1570,7 @@ int resident_supported(const Geom& g, const MGGeom* mg, int precision, int lds_l
   return b <= (size_t)lds_limit ? 1 : 0;
 }
 
-template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL>
+template <typename VT, int CW, int SH, int NS, int TP, bool MG, bool NL, bool PARA>
 static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts,
                              int n_inst, int* counter, double* work, int max_grid, const double* S,
                              const uint8_t* cond, const CellRegion& cr,
@@ -1538,7 +1580,7 @@ static hipError_t launch_res(const Geom& g, const MGGeom& mg, const Solver& sv, 
   // the thread-private [row][thread] planes of the work slot must hold SH * NT elements
   if ((size_t)SH * NT > res_plane_doubles(g)) return hipErrorInvalidValue;
   const size_t lds = resident_lds<VT>(g, ResCfg{CW, SH, NS, TP}, MG ? &mg : nullptr);
-  auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG, NL>;
+  auto kern = k_ie_resident<VT, CW, SH, NS, TP, MG, NL, PARA>;
   hipError_t e0 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e0 != hipSuccess) return e0;
   const int grid = max_grid < n_inst ? max_grid : n_inst;
@@ -1556,10 +1598,23 @@ static hipError_t dispatch_res(const Geom& g, const MGGeom& mg, const Solver& sv
                                int* grid_out, int* block_out, hipStream_t st) {
   ResCfg c;
   if (!pick_resident(g, sv.tile, &c)) return hipErrorInvalidValue;
-  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
-  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
-  if (c.sh == 32) return launch_res<VT, 128, 32, 4, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
-  return launch_res<VT, 128, 16, 8, 64, MG, NL>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  if (sv.para) {  // Parareal entries (linear materials only)
+    if constexpr (NL) {
+      return hipErrorInvalidValue;
+    } else {
+#define MQ_RES(CW_, SH_, NS_, TP_) \
+  launch_res<VT, CW_, SH_, NS_, TP_, MG, NL, true>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st)
+      if (c.cw == 32) return MQ_RES(32, 16, 2, 32);
+      if (c.cw == 64) return MQ_RES(64, 16, 4, 64);
+      if (c.sh == 32) return MQ_RES(128, 32, 4, 64);
+      return MQ_RES(128, 16, 8, 64);
+#undef MQ_RES
+    }
+  }
+  if (c.cw == 32) return launch_res<VT, 32, 16, 2, 32, MG, NL, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  if (c.cw == 64) return launch_res<VT, 64, 16, 4, 64, MG, NL, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  if (c.sh == 32) return launch_res<VT, 128, 32, 4, 64, MG, NL, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
+  return launch_res<VT, 128, 16, 8, 64, MG, NL, false>(g, mg, sv, insts, n_inst, counter, work, max_grid, S, cond, cr, grid_out, block_out, st);
 }
 
 template <typename VT, bool MG>
@@ -1568,10 +1623,10 @@ static int occupancy_res(const Geom& g, const MGGeom* mg, const ResCfg& c) {
   const int nt = c.cw * c.ns;
   const size_t lds = resident_lds<VT>(g, c, MG ? mg : nullptr);
   hipError_t e;
-  if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG, false>, nt, lds);
-  else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG, false>, nt, lds);
-  else if (c.sh == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 32, 4, 64, MG, false>, nt, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG, false>, nt, lds);
+  if (c.cw == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 32, 16, 2, 32, MG, false, false>, nt, lds);
+  else if (c.cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 64, 16, 4, 64, MG, false, false>, nt, lds);
+  else if (c.sh == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 32, 4, 64, MG, false, false>, nt, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ie_resident<VT, 128, 16, 8, 64, MG, false, false>, nt, lds);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
@@ -1900,7 +1955,7 @@ __device__ inline f4v stencil4(const Geom& g, const float* __restrict__ V, const
   return out;
 }
 
-template <typename VT, int NT, bool MG>
+template <typename VT, int NT, bool MG, bool PARA>
 __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver sv, const Inst* __restrict__ insts,
                                                   int n_inst, int* counter, double* work,
                                                   const double* __restrict__ S, VT* vwork) {
@@ -1950,8 +2005,9 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   const int lw = g.lx1 - g.bx0, lh = g.ly1 - g.by0;
   int slot = 0;
 
+  int q_cur = (int)blockIdx.x < counter[3] ? 0 : 1, q_moved = 0;  // work queue of this workgroup (thread 0)
   for (;;) {
-    if (tid == 0) s_inst = atomicAdd(counter, 1);
+    if (tid == 0) s_inst = queue_next(counter, n_inst, q_cur, q_moved);
     __syncthreads();
     const int id = s_inst;
     __syncthreads();
@@ -1963,20 +2019,20 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
     // an entry of a one-launch Parareal run: wait (bounded) for its input, then
     // skip (sample stopped, or stopped by this chain's jumps) or run
     int dep_flags = 0;
-    if (in.dep_wait && !para_wait<NT>(in.dep_wait, in.para ? PARA_WAIT_TICKS : DEP_WAIT_TICKS, &s_depok,
-                                      in.para ? in.para->abort : nullptr))
-      dep_flags = FLAG_FAILED;
-    // (called for every entry; the branch is made wave-uniform: it leaves the
-    // entry as a whole)
-    if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
-      if (tid == 0 && in.stat) {
-        in.stat[3] = dep_flags;
-        in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
-        in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+    if constexpr (PARA) {
+      if (in.dep_wait && !para_wait<NT>(in.dep_wait, PARA_WAIT_TICKS, &s_depok, in.para ? in.para->abort : nullptr))
+        dep_flags = FLAG_FAILED;
+      // (the branch is made wave-uniform: it leaves the entry as a whole)
+      if (__builtin_amdgcn_readfirstlane(para_prologue<NT, NWAVES>(g, in, red, slot, &s_depok, &dep_flags) ? 1 : 0)) {
+        if (tid == 0 && in.stat) {
+          in.stat[3] = dep_flags;
+          in.stat[4] = in.stat[6] = (int)(t_begin & 0xffffffffull);
+          in.stat[5] = in.stat[7] = (int)(t_begin >> 32);
+        }
+        if (in.dep_done) para_set(in.dep_done);
+        __syncthreads();
+        continue;
       }
-      if (in.dep_done) para_set(in.dep_done);
-      __syncthreads();
-      continue;
     }
     auto dscale = [&](int i, int j) -> double {
       if (i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1) {
@@ -2413,7 +2469,8 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
           Av[gi] = u;
         }
         __syncthreads();
-        if (in.seg_done) para_set(in.seg_done[seg]);
+        if constexpr (PARA)
+          if (in.seg_done) para_set(in.seg_done[seg]);
       }
     }
     if (in.a_out) {
@@ -2430,7 +2487,8 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
       }
       if (tid == 0) in.carry[2 * FS] = qsum;
     }
-    if (in.dep_done) para_set(in.dep_done);  // publishes a_out (and carry) first
+    if constexpr (PARA)
+      if (in.dep_done) para_set(in.dep_done);  // publishes a_out (and carry) first
     if (tid == 0) {
       if (in.q_out) *in.q_out = qsum * in.q_scale;
       if (in.stat) {
@@ -2457,7 +2515,7 @@ size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
   return stream_slot_elems(g, mg ? *mg : MGGeom{}, mg && mg->nlev > 0);
 }
 
-template <int NT>
+template <int NT, bool PARA>
 static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
                                   int* counter, double* work, int n_slots, int grid, const double* S, hipStream_t st) {
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
@@ -2465,18 +2523,18 @@ static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver
   const bool usemg = sv.precond == 1 && mg.nlev > 0;
   if (sv.precision == MQ_PREC_FP64) {
     if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<double, NT, true>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+      hipLaunchKernelGGL((k_ie_stream<double, NT, true, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
                          counter, work, S, vbase);
     else
-      hipLaunchKernelGGL((k_ie_stream<double, NT, false>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
-                         counter, work, S, vbase);
+      hipLaunchKernelGGL((k_ie_stream<double, NT, false, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts,
+                         n_inst, counter, work, S, vbase);
   } else {
     float* fb = reinterpret_cast<float*>(vbase);
     if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<float, NT, true>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+      hipLaunchKernelGGL((k_ie_stream<float, NT, true, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
                          counter, work, S, fb);
     else
-      hipLaunchKernelGGL((k_ie_stream<float, NT, false>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+      hipLaunchKernelGGL((k_ie_stream<float, NT, false, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
                          counter, work, S, fb);
   }
   return hipGetLastError();
@@ -2494,8 +2552,13 @@ hipError_t launch_ie_stream(const Geom& g, const MGGeom& mg, const Solver& sv, c
   const int nt = stream_threads(sv.tile);
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = nt;
-  if (nt == 512) return launch_stream_nt<512>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
-  return launch_stream_nt<STREAM_NT>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
+  // Parareal entries take the instantiation with the entry prologue
+  if (sv.para) {
+    if (nt == 512) return launch_stream_nt<512, true>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
+    return launch_stream_nt<STREAM_NT, true>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
+  }
+  if (nt == 512) return launch_stream_nt<512, false>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
+  return launch_stream_nt<STREAM_NT, false>(g, mg, sv, insts, n_inst, counter, work, n_slots, grid, S, st);
 }
 
 }  // namespace mq

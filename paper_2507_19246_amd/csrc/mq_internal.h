@@ -207,6 +207,7 @@ struct Solver {
   int mg_levels;   // coarse levels in use (0: all)
   int mg_coarse_sweeps;  // damped-Jacobi sweeps at the coarsest level in use
   int mg_block_min;      // coarse levels with at least this many nodes per side use the whole workgroup
+  int para;              // 1: the launch holds one-launch Parareal entries (kernels with the entry prologue)
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4, FLAG_PARAREAL_KMAX = 8 };
@@ -269,6 +270,10 @@ hipError_t launch_to_full(const Geom& g, int n, const double* in, double* const*
                           hipStream_t st);
 hipError_t launch_level_stats(int n_levels, const int* n_per_level, const double* const* qf,
                               const double* const* qc, double* out, hipStream_t st);
+// Work queue of the next persistent launch (counter: 4 ints): entries [0,
+// n_first) form queue 0, the rest queue 1; workgroups below grid_first start
+// on queue 0.
+hipError_t launch_queue_init(int* counter, int n_first, int grid_first, hipStream_t st);
 // Device address of the allocation-free call's workspace on `device` (looked
 // up once per device with that device current; noalloc.hip).
 hipError_t noalloc_workspace(int device, char** ptr);

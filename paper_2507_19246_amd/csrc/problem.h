@@ -149,9 +149,6 @@ struct mq_problem {
   // wide path: called on the host between time steps (may block to let other
   // work have the device); empty: none
   std::function<void()> wide_yield;
-  // upper bound on the persistent grid (0: the device's slots); set while a
-  // combined run keeps slots free for its Parareal part
-  int grid_cap = 0;
   // start state a_0 of later runs on the full grid (zero boundary ring), set by
   // mq_set_initial_state; empty: a_0 = 0
   mq::DevPtr<double> a0;
@@ -162,9 +159,6 @@ struct mq_problem {
   // this device's fixed workspace of the allocation-free entry point
   // (MQ_NOALLOC_WORKSPACE_BYTES, shared by every handle on the device)
   char* scratch = nullptr;
-  // second set-up of the same problem on a stream of its own (combined runs)
-  mq_problem* twin = nullptr;
-  hipStream_t twin_stream = nullptr;
 };
 
 namespace mq {
@@ -182,8 +176,11 @@ std::vector<double> source_table(const mq_problem_desc& d, double dt, int n_tota
 // `dinst` on p->stream without waiting.  The work buffer must already hold
 // min(n, max_slots(p)) slots.
 // work (nullable): use these work_slots slots instead of the handle's work buffer.
+// n_first >= 0: entries [0, n_first) form a second work queue that workgroups
+// below grid_first take first (see the kernels' queue_next).
+// para: the entries include one-launch Parareal entries.
 int launch_persistent(mq_problem* p, const Inst* dinst, int n, int* grid, int* block, double* work = nullptr,
-                      size_t work_slots = 0);
+                      size_t work_slots = 0, int n_first = -1, int grid_first = -1, bool para = false);
 // Wide path (wide.cpp): run the instances one after the other over the whole device.
 // flags (nullable): receives one entry of FLAG_* bits per instance, in insts order
 int run_wide(mq_problem* p, std::vector<Inst>& insts, mq_run_stats* st, int* status, std::vector<int>* flags);
