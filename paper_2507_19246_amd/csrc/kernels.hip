@@ -464,6 +464,34 @@ __device__ inline VT capp(const CLev<VT>& L, const VT* v, int i, int j, VT* idg)
   return L.air * (c - VT(0.25) * ((e + w) + (nn + s)));
 }
 
+// A lane's value from the lane to its left / right in the wave (DPP wave
+// shifts; 0 in lane 0 / lane 63).  Callers read them only where that lane is
+// active.
+__device__ inline float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// The same with every load issued unconditionally (levels in global memory):
+// a node outside the table region reads the region's first box position and
+// keeps the air stencil, so the loads of a pass are not serialised behind the
+// region test.  Same expression per node as capp.
+template <typename VT>
+__device__ inline VT capp_gm(const CLev<VT>& L, const VT* v, int i, int j, VT* idg) {
+  const int np = L.np, p = (j + 1) * np + i + 1;
+  const VT c = v[p], e = v[p + 1], w = v[p - 1], nn = v[p + np], s = v[p - np], ne = v[p + np + 1],
+           sw = v[p - np - 1];
+  const bool in = clev_inL(L, i, j);
+  const int t = in ? (j - L.by0 + 1) * L.RW + (i - L.bx0 + 1) : L.RW + 1;
+  const VT tc = L.C[t], te = L.E[t], tw = L.E[t - 1], tn = L.N[t], ts = L.N[t - L.RW], tne = L.NE[t],
+           tsw = L.NE[t - L.RW - 1], ti = L.ID[t];
+  *idg = in ? ti : L.air_id;
+  return in ? tc * c + te * e + tw * w + tn * nn + ts * s + tne * ne + tsw * sw
+            : L.air * (c - VT(0.25) * ((e + w) + (nn + s)));
+}
+
 template <typename VT>
 __device__ inline VT clev_id(const CLev<VT>& L, int i, int j) {
   return clev_inL(L, i, j) ? L.ID[(j - L.by0 + 1) * L.RW + (i - L.bx0 + 1)] : L.air_id;
@@ -498,22 +526,53 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Level passes; (me, nthr) are the participating threads.
-template <typename VT>
+// Level passes; (me, nthr) are the participating threads.  GM: the level
+// lives in global memory; the stencil passes then take two rows per step,
+// both rows' loads ahead of either row's store (no node of a pass reads what
+// another node of it writes), to double the loads in flight.
+template <typename VT, bool GM = false>
 __device__ inline void c_resid(const CLev<VT>& L, int me, int nthr) {  // T = R - A Z
   const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
   if (tx >= L.n) return;
+  if constexpr (GM) {
+    for (int j = me >> L.txs; j < L.n; j += 2 * ty) {
+      const int j2 = j + ty < L.n ? j + ty : j;
+      VT d;
+      const int p = (j + 1) * L.np + tx + 1, p2 = (j2 + 1) * L.np + tx + 1;
+      const VT a = L.R[p] - capp_gm(L, L.Z, tx, j, &d);
+      const VT b = L.R[p2] - capp_gm(L, L.Z, tx, j2, &d);
+      L.T[p] = a;
+      if (j + ty < L.n) L.T[p2] = b;
+    }
+    return;
+  }
   for (int j = me >> L.txs; j < L.n; j += ty) {
     VT d;
     const int p = (j + 1) * L.np + tx + 1;
     L.T[p] = L.R[p] - capp(L, L.Z, tx, j, &d);
   }
 }
-template <typename VT>
+template <typename VT, bool GM = false>
 __device__ inline void c_restrict(const CLev<VT>& F, const CLev<VT>& Cc, VT om, bool exact, int me,
                                   int nthr) {  // Cc.R = P^T F.T, Cc.Z = om ID R (ID R at the coarsest)
   const int tx = me & ((1 << Cc.txs) - 1), ty = nthr >> Cc.txs;
   if (tx >= Cc.n) return;
+  if constexpr (GM) {
+    const VT f = exact ? VT(1) : om;
+    for (int j = me >> Cc.txs; j < Cc.n; j += 2 * ty) {
+      const int j2 = j + ty < Cc.n ? j + ty : j;
+      const VT r = restrict_at(F.T, F.np, tx, j), r2 = restrict_at(F.T, F.np, tx, j2);
+      const VT d = clev_id(Cc, tx, j), d2 = clev_id(Cc, tx, j2);
+      const int p = (j + 1) * Cc.np + tx + 1, p2 = (j2 + 1) * Cc.np + tx + 1;
+      Cc.R[p] = r;
+      Cc.Z[p] = f * d * r;
+      if (j + ty < Cc.n) {
+        Cc.R[p2] = r2;
+        Cc.Z[p2] = f * d2 * r2;
+      }
+    }
+    return;
+  }
   for (int j = me >> Cc.txs; j < Cc.n; j += ty) {
     const VT r = restrict_at(F.T, F.np, tx, j);
     const int p = (j + 1) * Cc.np + tx + 1;
@@ -521,16 +580,38 @@ __device__ inline void c_restrict(const CLev<VT>& F, const CLev<VT>& Cc, VT om, 
     Cc.Z[p] = (exact ? VT(1) : om) * clev_id(Cc, tx, j) * r;
   }
 }
-template <typename VT>
+template <typename VT, bool GM = false>
 __device__ inline void c_prolong(const CLev<VT>& L, const VT* zc, int cp, int me, int nthr) {
   const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
   if (tx >= L.n) return;
+  if constexpr (GM) {
+    for (int j = me >> L.txs; j < L.n; j += 2 * ty) {
+      const int j2 = j + ty < L.n ? j + ty : j;
+      const int p = (j + 1) * L.np + tx + 1, p2 = (j2 + 1) * L.np + tx + 1;
+      const VT a = L.Z[p] + prolong_at(zc, cp, tx, j), b = L.Z[p2] + prolong_at(zc, cp, tx, j2);
+      L.Z[p] = a;
+      if (j + ty < L.n) L.Z[p2] = b;
+    }
+    return;
+  }
   for (int j = me >> L.txs; j < L.n; j += ty) L.Z[(j + 1) * L.np + tx + 1] += prolong_at(zc, cp, tx, j);
 }
-template <typename VT>
+template <typename VT, bool GM = false>
 __device__ inline void c_post(const CLev<VT>& L, VT om, int me, int nthr) {  // T = Z + om ID (R - A Z)
   const int tx = me & ((1 << L.txs) - 1), ty = nthr >> L.txs;
   if (tx >= L.n) return;
+  if constexpr (GM) {
+    for (int j = me >> L.txs; j < L.n; j += 2 * ty) {
+      const int j2 = j + ty < L.n ? j + ty : j;
+      VT id, id2;
+      const int p = (j + 1) * L.np + tx + 1, p2 = (j2 + 1) * L.np + tx + 1;
+      const VT az = capp_gm(L, L.Z, tx, j, &id), az2 = capp_gm(L, L.Z, tx, j2, &id2);
+      const VT a = L.Z[p] + om * id * (L.R[p] - az), b = L.Z[p2] + om * id2 * (L.R[p2] - az2);
+      L.T[p] = a;
+      if (j + ty < L.n) L.T[p2] = b;
+    }
+    return;
+  }
   for (int j = me >> L.txs; j < L.n; j += ty) {
     VT id;
     const int p = (j + 1) * L.np + tx + 1;
@@ -555,10 +636,10 @@ __device__ inline void c_zero_halo(const CLev<VT>& L, int me, int nthr) {
 
 // Damped-Jacobi sweeps Z <- Z + om ID (R - A Z) at the coarsest level in
 // use; returns the vector that holds the result (Z and T alternate).
-template <typename VT, class SYNC>
+template <typename VT, bool GM, class SYNC>
 __device__ __attribute__((always_inline)) inline const VT* c_coarsest(CLev<VT> C, VT om, int sweeps, int me, int nthr, SYNC sync) {
   for (int s = 0; s < sweeps; ++s) {
-    c_post(C, om, me, nthr);
+    c_post<VT, GM>(C, om, me, nthr);
     sync();
     VT* t = C.Z;
     C.Z = C.T;
@@ -573,7 +654,7 @@ __device__ __attribute__((always_inline)) inline const VT* c_coarsest(CLev<VT> C
 // level L is the single-node level).  Levels with n >= block_min use the whole
 // workgroup, smaller ones run on wave 0 alone.  Returns level 1's corrected
 // vector.
-template <typename VT, int NT>
+template <typename VT, int NT, bool GM = false>
 __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
                                          VT air = VT(1), int lmax = 0, int csweeps = 0, int block_min = 15) {
   const int L = (lmax > 0 && lmax < mg.nlev) ? lmax : mg.nlev;
@@ -586,30 +667,30 @@ __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MG
   for (int l = 1; l <= lb && l < L; ++l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
     const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
-    c_resid(F, tid, NT);
+    c_resid<VT, GM>(F, tid, NT);
     __syncthreads();
-    c_restrict(F, Cc, om, l + 1 == L, tid, NT);
+    c_restrict<VT, GM>(F, Cc, om, l + 1 == L, tid, NT);
     __syncthreads();
   }
-  if (lb == L) zL = c_coarsest(clev<VT>(mg, L, region, ctab, NT, air), om, csweeps, tid, NT, bsync);
+  if (lb == L) zL = c_coarsest<VT, GM>(clev<VT>(mg, L, region, ctab, NT, air), om, csweeps, tid, NT, bsync);
   // wave levels
   if (lb < L) {
     if (tid < 64) {
       for (int l = lb + 1; l < L; ++l) {
         const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
         const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
-        c_resid(F, tid, 64);
+        c_resid<VT, GM>(F, tid, 64);
         wave_sync();
-        c_restrict(F, Cc, om, l + 1 == L, tid, 64);
+        c_restrict<VT, GM>(F, Cc, om, l + 1 == L, tid, 64);
         wave_sync();
       }
-      zL = c_coarsest(clev<VT>(mg, L, region, ctab, 64, air), om, csweeps, tid, 64, wave_sync);
+      zL = c_coarsest<VT, GM>(clev<VT>(mg, L, region, ctab, 64, air), om, csweeps, tid, 64, wave_sync);
       for (int l = L - 1; l > lb; --l) {
         const CLev<VT> F = clev<VT>(mg, l, region, ctab, 64, air);
         const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, 64, air);
-        c_prolong(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, 64);
+        c_prolong<VT, GM>(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, 64);
         wave_sync();
-        c_post(F, om, tid, 64);
+        c_post<VT, GM>(F, om, tid, 64);
         wave_sync();
       }
     } else {
@@ -623,9 +704,9 @@ __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MG
   for (int l = (lb < L ? lb : L - 1); l >= 1; --l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
     const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
-    c_prolong(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, NT);
+    c_prolong<VT, GM>(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, NT);
     __syncthreads();
-    c_post(F, om, tid, NT);
+    c_post<VT, GM>(F, om, tid, NT);
     __syncthreads();
   }
   return L == 1 ? zL : clev<VT>(mg, 1, region, ctab, NT, air).T;
@@ -1897,14 +1978,36 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
          tNE[t - g.RW - 1] * R[gi - P - 1];
 }
 
+// Quad tables of the streaming kernel's float4 passes: the scaled E, N and NE
+// coefficients and D^{1/2} of the table region, laid out so that the four
+// nodes of a quad (first column i0 = 0 mod 4) are one aligned float4.  Columns
+// qx0 .. qx0 + qw - 1 (qx0 = 4 floor(bx0 / 4) - 4, qw = 0 mod 4) cover every
+// quad that meets the lookup columns [bx0, lx1) plus the column left of it;
+// rows by0 - 2 .. ly1 - 1 (row r = j - by0 + 2) put two rows of air below the
+// lookup rows.  Positions outside the table region hold the air values (-1/4,
+// -1/4, 0; D^{1/2} of air off the box), so a quad outside the lookup region
+// reads the fixed air position (row 1, column qx0 + 4) instead of branching
+// per node.
+struct QTab {
+  int qx0, qw, rows;
+};
+__host__ __device__ inline QTab qtab_geom(const Geom& g) {
+  QTab q;
+  q.qx0 = ((g.bx0 >> 2) << 2) - 4;
+  const int hi = g.lx1 > g.bx0 ? (((g.lx1 - 1) >> 2) << 2) + 4 : q.qx0 + 8;
+  q.qw = hi - q.qx0 < 8 ? 8 : hi - q.qx0;
+  q.rows = g.RH + 1;
+  return q;
+}
+
 // Per-slot VT workspace of the streaming kernel: six full-grid vectors, the
-// five table planes over the box region (scaled E, N, NE, D^{-1/2}, D^{1/2})
-// and, with multigrid, the
-// coarse-level vectors and Galerkin tables.
-// (rounded up to 64 elements: every slot, and every full-grid vector in it,
-// starts 16-byte aligned)
+// four quad-table planes, the five table planes over the box region (scaled
+// E, N, NE, D^{-1/2}, D^{1/2}) and, with multigrid, the coarse-level vectors
+// and Galerkin tables.  (Rounded up to 64 elements: every slot, every
+// full-grid vector and every quad plane in it starts 16-byte aligned.)
 __host__ __device__ inline size_t stream_slot_elems(const Geom& g, const MGGeom& mg, bool use_mg) {
-  size_t e = 6 * (size_t)g.N * g.P + 5 * (size_t)g.RW * g.RH;
+  const QTab q = qtab_geom(g);
+  size_t e = 6 * (size_t)g.N * g.P + 4 * (size_t)q.rows * q.qw + 5 * (size_t)g.RW * g.RH;
   if (use_mg) e += (size_t)mg.region_elems + (size_t)mg.ctab_elems;
   return (e + 63) & ~(size_t)63;
 }
@@ -1929,28 +2032,67 @@ __device__ inline void st4(float* p, const f4v& v, int nv) {
     if (nv > 2) p[2] = v[2];
   }
 }
-// scaled 7-point stencil of four nodes (i0..i0+3, j): the float4 form of
-// stencil_scaled, same expression per node (gi = index of (i0, j))
-__device__ inline f4v stencil4(const Geom& g, const float* __restrict__ V, const float* tE, const float* tN,
-                               const float* tNE, int i0, int j, int gi) {
+// Quad-table base of the quad (i0, j) inside the lookup region, else -1.
+__device__ inline int qbase(const Geom& g, const QTab& q, int i0, int j) {
+  const bool in = j >= g.by0 && j < g.ly1 && i0 + 3 >= g.bx0 && i0 < g.lx1;
+  return in ? (j - g.by0 + 2) * q.qw + (i0 - q.qx0) : -1;
+}
+// Where a quad's left and right neighbour quads are: quads of one row sit in
+// consecutive lanes, so the nodes just across a quad's edges are the
+// neighbouring lanes' values, except at the row's ends (the zero boundary
+// ring on the left; on the right only the boundary node, never stored, reads
+// past it) and where a row continues in the next wave (then loaded).
+struct QLane {
+  bool lzero, lload, rload;
+};
+__device__ inline QLane qlane(int qtx, int nq) {
+  const int lane = threadIdx.x & 63;
+  return QLane{qtx == 0, lane == 0 && qtx > 0, lane == 63 && qtx + 1 < nq};
+}
+// scaled 7-point stencil of four nodes (i0..i0+3, j), the float4 form of
+// stencil_scaled (gi = index of (i0, j)): three row loads, the coefficients
+// from the quad tables inside the lookup region (air values elsewhere), the
+// values across the quad's edges from the adjacent lanes.  Same expression
+// per node as stencil_scaled inside the lookup region.
+__device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, const float* __restrict__ V,
+                               const float* qE, const float* qN, const float* qNE, int i0, int j, int gi) {
   const int P = g.P;
   const f4v c = ld4(V + gi), up = ld4(V + gi + P), dn = ld4(V + gi - P);
-  const float w = V[gi - 1], e = V[gi + 4], ne = V[gi + P + 4], sw = V[gi - P - 1];
-  const bool rowL = j >= g.by0 && j < g.ly1;
+  const int b = qbase(g, q, i0, j);
+  f4v E, N, Nb, NE, NEb;
+  if (b >= 0) {
+    E = ld4(qE + b);
+    N = ld4(qN + b);
+    Nb = ld4(qN + b - q.qw);
+    NE = ld4(qNE + b);
+    NEb = ld4(qNE + b - q.qw);
+  } else {
+    E = N = Nb = f4v{-0.25f, -0.25f, -0.25f, -0.25f};
+    NE = NEb = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  float w = from_left(c[3]), sw = from_left(dn[3]), Ew = from_left(E[3]), NEbw = from_left(NEb[3]);
+  float e = from_right(c[0]), ne = from_right(up[0]);
+  if (ql.lzero) {
+    w = sw = NEbw = 0.0f;
+    Ew = -0.25f;
+  }
+  if (ql.lload) {
+    w = V[gi - 1];
+    sw = V[gi - P - 1];
+    Ew = b >= 0 ? qE[b - 1] : -0.25f;
+    NEbw = b >= 0 ? qNE[b - q.qw - 1] : 0.0f;
+  }
+  if (ql.rload) {
+    e = V[gi + 4];
+    ne = V[gi + P + 4];
+  }
   f4v out;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int i = i0 + k;
-    const float ck = c[k], ek = k < 3 ? c[k < 3 ? k + 1 : 0] : e, wk = k > 0 ? c[k > 0 ? k - 1 : 0] : w;
-    const float nk = up[k], sk = dn[k];
-    if (rowL && i >= g.bx0 && i < g.lx1) {
-      const int t = (j - g.by0 + 1) * g.RW + (i - g.bx0 + 1);
-      const float nek = k < 3 ? up[k < 3 ? k + 1 : 0] : ne, swk = k > 0 ? dn[k > 0 ? k - 1 : 0] : sw;
-      out[k] = ck + tE[t] * ek + tE[t - 1] * wk + tN[t] * nk + tN[t - g.RW] * sk + tNE[t] * nek +
-               tNE[t - g.RW - 1] * swk;
-    } else {
-      out[k] = ck - 0.25f * ((ek + wk) + (nk + sk));
-    }
+    const float ek = k < 3 ? c[k < 3 ? k + 1 : 0] : e, wk = k > 0 ? c[k > 0 ? k - 1 : 0] : w;
+    const float nek = k < 3 ? up[k < 3 ? k + 1 : 0] : ne, swk = k > 0 ? dn[k > 0 ? k - 1 : 0] : sw;
+    const float cw = k > 0 ? E[k > 0 ? k - 1 : 0] : Ew, csw = k > 0 ? NEb[k > 0 ? k - 1 : 0] : NEbw;
+    out[k] = c[k] + E[k] * ek + cw * wk + N[k] * up[k] + Nb[k] * dn[k] + NE[k] * nek + csw * swk;
   }
   return out;
 }
@@ -1984,7 +2126,13 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   VT* Sv = vslot + 3 * FS + voff;
   VT* Wv = vslot + 4 * FS + voff;
   VT* Vv = vslot + 5 * FS + voff;  // multigrid: q = A p
-  VT* tE = vslot + 6 * FS;
+  const QTab qg = qtab_geom(g);
+  const int QE = qg.rows * qg.qw;
+  float* const qE = (float*)(vslot + 6 * FS);  // quad tables (float form only)
+  float* const qN = qE + QE;
+  float* const qNE = qN + QE;
+  float* const qDi = qNE + QE;
+  VT* tE = vslot + 6 * FS + 4 * (size_t)QE;
   VT* tN = tE + RHW;
   VT* tNE = tN + RHW;
   VT* tD = tNE + RHW;
@@ -2077,6 +2225,21 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
       };
       build_galerkin<VT>(mg, ctab, tE, tN, tNE, dn, true, d_air, g.RW, tid, NT);
       for (int l = 1; l <= mg.nlev; ++l) c_zero_halo(clev<VT>(mg, l, mgreg, ctab, NT), tid, NT);
+      if constexpr (QV) {
+        if (quad) {
+          for (int p = tid; p < QE; p += NT) {
+            const int i = qg.qx0 + p % qg.qw, j = g.by0 - 2 + p / qg.qw;
+            const int ci = i - g.bx0 + 1, cj = j - g.by0 + 1;
+            const bool in = ci >= 0 && ci < g.RW && cj >= 0 && cj < g.RH;
+            const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
+            const int t = in ? cj * g.RW + ci : 0;
+            qE[p] = in ? (float)tE[t] : -0.25f;
+            qN[p] = in ? (float)tN[t] : -0.25f;
+            qNE[p] = in ? (float)tNE[t] : 0.0f;
+            qDi[p] = box ? (float)tDi[t] : (float)(1.0 / d_air);
+          }
+        }
+      }
       __syncthreads();
     }
     auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
@@ -2181,7 +2344,9 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                 }
               };
               // Four consecutive nodes per thread, one row at a time (float4 loads
-              // and stores).
+              // and stores).  (Two rows per step, loads first, measured no faster:
+              // the passes are bound by memory instructions issued, not by loads
+              // in flight.)
               auto quads2 = [&](auto&& ld, auto&& st) __attribute__((always_inline)) {
                 if (qtx >= nq) return;
                 const int i0 = qtx << 2;
@@ -2192,16 +2357,12 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                   st(ga, nv, va);
                 }
               };
+              const float di_air = (float)(1.0 / d_air);
               auto dinv4 = [&](int i0, int j) __attribute__((always_inline)) {  // D^{1/2} of four nodes
-                f4v d;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                  const int i = i0 + k;
-                  const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
-                  d[k] = box ? (float)tDi[(j - g.by0 + 1) * g.RW + (i - g.bx0 + 1)] : (float)(1.0 / d_air);
-                }
-                return d;
+                const int b = qbase(g, qg, i0, j);
+                return b >= 0 ? ld4(qDi + b) : f4v{di_air, di_air, di_air, di_air};
               };
+              const QLane ql = qlane(qtx, nq);
               VT* Zm = Sv;  // preconditioned residual
               VT* Tm = Wv;  // fine residual t / smoothing output (swapped with Zm)
               // coarse levels hold the unscaled operators: level 1 <-> scaled fine
@@ -2219,7 +2380,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                     quads2(
                         [&](int i0, int j, int gi) {
                           const f4v r = ld4(R4 + gi);
-                          const f4v ar = stencil4(g, R4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          const f4v ar = stencil4(g, qg, ql, R4, qE, qN, qNE, i0, j, gi);
                           return F4x2{(float)om * r, (r - (float)om * ar) * dinv4(i0, j)};
                         },
                         [&](int gi, int nv, const F4x2& v) {
@@ -2240,19 +2401,26 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                     });
                 __syncthreads();
                 tick(0);
-                {  // restriction to level 1
+                {  // restriction to level 1 (two rows per step, loads first)
                   const int tx = tid & ((1 << L1.txs) - 1), ty = NT >> L1.txs;
+                  const VT f1 = exact1 ? VT(1) : om;
                   if (tx < L1.n) {
-                    for (int j = tid >> L1.txs; j < L1.n; j += ty) {
-                      const VT rc = restrict_at(Tm, g.P, tx, j);
-                      const int q = (j + 1) * L1.np + tx + 1;
+                    for (int j = tid >> L1.txs; j < L1.n; j += 2 * ty) {
+                      const int j2 = j + ty < L1.n ? j + ty : j;
+                      const VT rc = restrict_at(Tm, g.P, tx, j), rc2 = restrict_at(Tm, g.P, tx, j2);
+                      const VT d = clev_id(L1, tx, j), d2 = clev_id(L1, tx, j2);
+                      const int q = (j + 1) * L1.np + tx + 1, q2 = (j2 + 1) * L1.np + tx + 1;
                       L1.R[q] = rc;
-                      L1.Z[q] = (exact1 ? VT(1) : om) * clev_id(L1, tx, j) * rc;
+                      L1.Z[q] = f1 * d * rc;
+                      if (j + ty < L1.n) {
+                        L1.R[q2] = rc2;
+                        L1.Z[q2] = f1 * d2 * rc2;
+                      }
                     }
                   }
                 }
                 __syncthreads();
-                const VT* z1 = coarse_cycle<VT, NT>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
+                const VT* z1 = coarse_cycle<VT, NT, true>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
                                                     sv.mg_block_min);
                 __syncthreads();
                 tick(1);
@@ -2285,14 +2453,17 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                     quads2(
                         [&](int i0, int j, int gi) {
                           const f4v r = ld4((const float*)Rv + gi), z = ld4(Z4 + gi);
-                          const f4v az = stencil4(g, Z4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          const f4v az = stencil4(g, qg, ql, Z4, qE, qN, qNE, i0, j, gi);
                           return F4x2{z + (float)om * (r - az), r};
                         },
                         [&](int gi, int nv, const F4x2& v) {
                           st4((float*)Tm + gi, v.a, nv);
-                          for (int k = 0; k < nv; ++k) {
-                            rz[0] += (double)(v.b[k] * v.a[k]);
-                            rz[1] += (double)(v.b[k] * v.b[k]);
+#pragma unroll
+                          for (int k = 0; k < 4; ++k) {
+                            if (k < nv) {
+                              rz[0] += (double)(v.b[k] * v.a[k]);
+                              rz[1] += (double)(v.b[k] * v.b[k]);
+                            }
                           }
                         });
                   }
@@ -2330,14 +2501,16 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                     const float* Z4 = (const float*)Zm;
                     quads2(
                         [&](int i0, int j, int gi) {
-                          const f4v az = stencil4(g, Z4, (const float*)tE, (const float*)tN, (const float*)tNE, i0, j, gi);
+                          const f4v az = stencil4(g, qg, ql, Z4, qE, qN, qNE, i0, j, gi);
                           return F4x2{ld4(Z4 + gi) + (float)b_ * ld4((const float*)Pv + gi),
                                       az + (float)b_ * ld4((const float*)Vv + gi)};
                         },
                         [&](int gi, int nv, const F4x2& v) {
                           st4((float*)Pv + gi, v.a, nv);
                           st4((float*)Vv + gi, v.b, nv);
-                          for (int k = 0; k < nv; ++k) pq[0] += (double)(v.a[k] * v.b[k]);
+#pragma unroll
+                          for (int k = 0; k < 4; ++k)
+                            if (k < nv) pq[0] += (double)(v.a[k] * v.b[k]);
                         });
                   }
                 }
@@ -2823,7 +2996,7 @@ __global__ __launch_bounds__(WIDE_BX) void k_w_cpass(MGGeom mg, WidePtrs w, int 
 template <typename VT>
 __global__ __launch_bounds__(1024) void k_w_ctail(MGGeom sub, WidePtrs w, VT om, VT air) {
   if (w.sc->done) return;
-  (void)coarse_cycle<VT, 1024>(sub, (VT*)w.mgreg, (const VT*)w.ctab, om, threadIdx.x, air);
+  (void)coarse_cycle<VT, 1024, true>(sub, (VT*)w.mgreg, (const VT*)w.ctab, om, threadIdx.x, air);
 }
 
 // Z += D^{1/2} P z_1
