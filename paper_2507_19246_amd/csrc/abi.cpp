@@ -58,6 +58,7 @@ Solver solver_of(const mq_problem* p) {
   sv.mg_levels = p->d.mg_levels;
   sv.mg_coarse_sweeps = p->d.mg_coarse_sweeps;
   sv.mg_block_min = p->d.mg_block_min > 0 ? p->d.mg_block_min : 15;
+  sv.lds_limit = p->lds_limit;
   return sv;
 }
 

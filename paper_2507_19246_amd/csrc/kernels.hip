@@ -184,6 +184,27 @@ __device__ inline double A_apply(const Geom& g, const double* __restrict__ tab, 
   return M_apply(g, tab, v, nr) * inv_dt + K_apply(g, tab, v, nr);
 }
 
+// A_apply with every load issued at once (a node outside the lookup region
+// reads the region's first box position and keeps the air stencil): the
+// loads of a pass are not serialised behind the region test.  Same
+// expression per node as A_apply.
+__device__ inline double A_apply_u(const Geom& g, const double* __restrict__ tab, const double* v,
+                                   const NodeRef& nr, double inv_dt) {
+  const int P = g.P, gi = nr.gi, RW = g.RW, RHW = g.RW * g.RH;
+  const double c = v[gi], e = v[gi + 1], w = v[gi - 1], n = v[gi + P], s = v[gi - P], ne = v[gi + P + 1],
+               sw = v[gi - P - 1];
+  const int t = nr.inL ? nr.t : RW + 1;
+  const double kc = tab[T_KC * RHW + t], ke = tab[T_KE * RHW + t], kw = tab[T_KE * RHW + t - 1],
+               kn = tab[T_KN * RHW + t], ks = tab[T_KN * RHW + t - RW];
+  const double mc = tab[T_MC * RHW + t], me = tab[T_ME * RHW + t], mw = tab[T_ME * RHW + t - 1],
+               mn = tab[T_MN * RHW + t], ms = tab[T_MN * RHW + t - RW], mne = tab[T_MNE * RHW + t],
+               msw = tab[T_MNE * RHW + t - RW - 1];
+  const double air = g.nu_air * (4.0 * c - (e + w) - (n + s));
+  const double m = mc * c + me * e + mw * w + mn * n + ms * s + mne * ne + msw * sw;
+  const double k = kc * c + ke * e + kw * w + kn * n + ks * s;
+  return nr.inL ? m * inv_dt + k : air;
+}
+
 // ---------------------------------------------------------------------------
 // deterministic reductions (wave64 butterfly, then waves in order)
 // ---------------------------------------------------------------------------
@@ -656,15 +677,16 @@ __device__ __attribute__((always_inline)) inline const VT* c_coarsest(CLev<VT> C
 // vector.
 template <typename VT, int NT, bool GM = false>
 __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MGGeom& mg, VT* region, const VT* ctab, VT om, int tid,
-                                         VT air = VT(1), int lmax = 0, int csweeps = 0, int block_min = 15) {
+                                         VT air = VT(1), int lmax = 0, int csweeps = 0, int block_min = 15,
+                                         int l0 = 1) {
   const int L = (lmax > 0 && lmax < mg.nlev) ? lmax : mg.nlev;
   auto is_block = [&](int l) { return NT == 64 || mg.lv[l].n >= block_min; };
   auto bsync = [] { __syncthreads(); };
-  int lb = 0;  // last block level
+  int lb = l0 - 1;  // last block level
   while (lb + 1 <= L && is_block(lb + 1)) ++lb;
   const VT* zL = nullptr;
   // block levels: descent
-  for (int l = 1; l <= lb && l < L; ++l) {
+  for (int l = l0; l <= lb && l < L; ++l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
     const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
     c_resid<VT, GM>(F, tid, NT);
@@ -701,7 +723,7 @@ __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MG
     __syncthreads();
   }
   // block levels: ascent
-  for (int l = (lb < L ? lb : L - 1); l >= 1; --l) {
+  for (int l = (lb < L ? lb : L - 1); l >= l0; --l) {
     const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
     const CLev<VT> Cc = clev<VT>(mg, l + 1, region, ctab, NT, air);
     c_prolong<VT, GM>(F, l + 1 == L ? zL : Cc.T, Cc.np, tid, NT);
@@ -709,7 +731,55 @@ __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MG
     c_post<VT, GM>(F, om, tid, NT);
     __syncthreads();
   }
-  return L == 1 ? zL : clev<VT>(mg, 1, region, ctab, NT, air).T;
+  return L == l0 ? zL : clev<VT>(mg, l0, region, ctab, NT, air).T;
+}
+
+// Coarse levels in use (mg_levels caps them).
+__host__ __device__ inline int stream_levels_used(const MGGeom& mg, const Solver& sv) {
+  return (sv.mg_levels > 0 && sv.mg_levels < mg.nlev) ? sv.mg_levels : mg.nlev;
+}
+// Elements of levels la..lz's vectors / tables (contiguous in the layout).
+__host__ __device__ inline int lds_vec_elems(const MGGeom& mg, int la, int lz) {
+  const MGLevel& z = mg.lv[lz];
+  return z.vec_off + 3 * (z.n + 2) * (z.n + 2) - mg.lv[la].vec_off;
+}
+__host__ __device__ inline int lds_tab_elems(const MGGeom& mg, int la, int lz) {
+  const MGLevel& z = mg.lv[lz];
+  return z.tab_off + 5 * z.RW * z.RH - mg.lv[la].tab_off;
+}
+
+// The same cycle with levels lds_lev..L in LDS (lds_reg: their vectors,
+// lds_tab: their tables, in the global layout's order) and levels
+// 1..lds_lev-1 in global memory (whole-workgroup levels); returns level 1's
+// corrected vector.  Same arithmetic as coarse_cycle.
+template <typename VT, int NT>
+__device__ __attribute__((always_inline)) inline const VT* coarse_cycle_lds(const MGGeom& mg, VT* region, const VT* ctab,
+                                                                          VT* lds_reg, const VT* lds_tab, int lds_lev,
+                                                                          VT om, int tid, VT air, int lmax, int csweeps,
+                                                                          int block_min) {
+  const int L = (lmax > 0 && lmax < mg.nlev) ? lmax : mg.nlev;
+  VT* const lreg = lds_reg - mg.lv[lds_lev].vec_off;  // level l's vectors at lreg + vec_off(l)
+  const VT* const ltab = lds_tab - mg.lv[lds_lev].tab_off;
+  for (int l = 1; l < lds_lev; ++l) {
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
+    c_resid<VT, true>(F, tid, NT);
+    __syncthreads();
+    if (l + 1 < lds_lev) c_restrict<VT, true>(F, clev<VT>(mg, l + 1, region, ctab, NT, air), om, l + 1 == L, tid, NT);
+    else c_restrict<VT, true>(F, clev<VT>(mg, l + 1, lreg, ltab, NT, air), om, l + 1 == L, tid, NT);
+    __syncthreads();
+  }
+  const VT* zl = coarse_cycle<VT, NT, false>(mg, lreg, ltab, om, tid, air, lmax, csweeps, block_min, lds_lev);
+  __syncthreads();
+  for (int l = lds_lev - 1; l >= 1; --l) {
+    const CLev<VT> F = clev<VT>(mg, l, region, ctab, NT, air);
+    const int cp = mg.lv[l + 1].n + 2;
+    if (l + 1 == lds_lev) c_prolong<VT, true>(F, zl, cp, tid, NT);
+    else c_prolong<VT, true>(F, clev<VT>(mg, l + 1, region, ctab, NT, air).T, cp, tid, NT);
+    __syncthreads();
+    c_post<VT, true>(F, om, tid, NT);
+    __syncthreads();
+  }
+  return clev<VT>(mg, 1, region, ctab, NT, air).T;
 }
 
 // Galerkin coarse entries A_c(c, c + D) = (P e_c)^T A_f (P e_{c+D}) for
@@ -2097,7 +2167,9 @@ __device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, co
   return out;
 }
 
-template <typename VT, int NT, bool MG, bool PARA>
+// LC: coarse levels sv.lds_lev.. in LDS (launched with their bytes of dynamic
+// LDS); otherwise every coarse level in global memory.
+template <typename VT, int NT, bool MG, bool PARA, bool LC = false>
 __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver sv, const Inst* __restrict__ insts,
                                                   int n_inst, int* counter, double* work,
                                                   const double* __restrict__ S, VT* vwork) {
@@ -2107,6 +2179,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
   __shared__ int s_dmin;
   __shared__ int s_depok;
   __shared__ unsigned long long s_ph[9];  // thread 0's phase clocks, then its last mark
+  extern __shared__ double smem_d[];      // multigrid: coarse levels lds_lev.. (vectors, then tables)
   const int tid = threadIdx.x;
   const int n = g.n, nd = n * n, RHW = g.RW * g.RH;
   const size_t FS = (size_t)g.N * g.P;
@@ -2213,6 +2286,10 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
       Av[gi] = in.a_init ? in.a_init[gi] : 0.0;
       Xv[gi] = in.carry_in ? in.carry[gi] : 0.0;
       Xprev[gi] = in.carry_in ? in.carry[FS + gi] : 0.0;
+      if (quad) {
+        Pv[gi] = VT(0);
+        Vv[gi] = VT(0);
+      }
     }
     __syncthreads();
     const double dmin = (double)__int_as_float(s_dmin) * 0.999;
@@ -2241,10 +2318,21 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
         }
       }
       __syncthreads();
+      if constexpr (LC) {  // coarse levels lds_lev..: tables into LDS, zero halos
+        const int la = sv.lds_lev, lz = stream_levels_used(mg, sv);
+        const int nvec = lds_vec_elems(mg, la, lz), ntab = lds_tab_elems(mg, la, lz);
+        VT* const lreg = reinterpret_cast<VT*>(smem_d);
+        VT* const ltab = lreg + nvec;
+        for (int q = tid; q < ntab; q += NT) ltab[q] = ctab[mg.lv[la].tab_off + q];
+        for (int l = la; l <= lz; ++l)
+          c_zero_halo(clev<VT>(mg, l, lreg - mg.lv[la].vec_off, ltab - mg.lv[la].tab_off, NT), tid, NT);
+        __syncthreads();
+      }
     }
-    auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {
+    auto dnode = [&](int i, int j, const NodeRef& nr) -> VT {  // (load issued unconditionally)
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
-      return box ? tD[nr.t] : (VT)d_air;
+      const VT d = tD[box ? nr.t : g.RW + 1];
+      return box ? d : (VT)d_air;
     };
     auto dnode_inv = [&](int i, int j, const NodeRef& nr) -> VT {  // D^{1/2}
       const bool box = i >= g.bx0 && i < g.bx1 && j >= g.by0 && j < g.by1;
@@ -2293,13 +2381,18 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
             double rr[1] = {0.0};
             for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
               const NodeRef nr = node_ref(g, i, j);
-              const double res = Bv[nr.gi] - A_apply(g, tab, Xv, nr, inv_dt);
+              const double res = Bv[nr.gi] - A_apply_u(g, tab, Xv, nr, inv_dt);
               rr[0] += res * res;
               Rv[nr.gi] = (VT)(res * (double)dnode(i, j, nr));
               Yv[nr.gi] = VT(0);
-              Pv[nr.gi] = VT(0);
-              Sv[nr.gi] = VT(0);
-              if constexpr (MG) Vv[nr.gi] = VT(0);
+              // (the float4 passes write S before reading it and read P and V
+              // only times beta = 0 in the first iteration: finite from the
+              // instance's start on, so they need no clearing per sweep)
+              if (!quad) {
+                Pv[nr.gi] = VT(0);
+                Sv[nr.gi] = VT(0);
+                if constexpr (MG) Vv[nr.gi] = VT(0);
+              }
             }
             block_sum<1, NWAVES>(rr, red, slot);
             tick(5);
@@ -2420,8 +2513,16 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                   }
                 }
                 __syncthreads();
-                const VT* z1 = coarse_cycle<VT, NT, true>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
-                                                    sv.mg_block_min);
+                const VT* z1;
+                if constexpr (LC)
+                  z1 = coarse_cycle_lds<VT, NT>(mg, mgreg, ctab, reinterpret_cast<VT*>(smem_d),
+                                                reinterpret_cast<VT*>(smem_d) +
+                                                    lds_vec_elems(mg, sv.lds_lev, stream_levels_used(mg, sv)),
+                                                sv.lds_lev, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
+                                                sv.mg_block_min);
+                else
+                  z1 = coarse_cycle<VT, NT, true>(mg, mgreg, ctab, om, tid, air, sv.mg_levels, sv.mg_coarse_sweeps,
+                                                  sv.mg_block_min);
                 __syncthreads();
                 tick(1);
                 if constexpr (QV) {
@@ -2688,26 +2789,60 @@ size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
   return stream_slot_elems(g, mg ? *mg : MGGeom{}, mg && mg->nlev > 0);
 }
 
+// First coarse level the streaming kernel keeps in LDS: the largest tail of
+// the levels in use that fits `budget` bytes, starting at level 2 or deeper,
+// every level above it a whole-workgroup level (0: none fits).
+static int stream_lds_level(const MGGeom& mg, const Solver& sv, size_t vt, size_t budget, size_t* bytes) {
+  *bytes = 0;
+  const int lz = stream_levels_used(mg, sv);
+  for (int la = 2; la <= lz; ++la) {
+    if (mg.lv[la - 1].n < sv.mg_block_min) return 0;
+    const size_t b = (size_t)(lds_vec_elems(mg, la, lz) + lds_tab_elems(mg, la, lz)) * vt;
+    if (b <= budget) {
+      *bytes = b;
+      return la;
+    }
+  }
+  return 0;
+}
+
 template <int NT, bool PARA>
-static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver& sv, const Inst* insts, int n_inst,
+static hipError_t launch_stream_nt(const Geom& g, const MGGeom& mg, const Solver& sv0, const Inst* insts, int n_inst,
                                   int* counter, double* work, int n_slots, int grid, const double* S, hipStream_t st) {
   (void)hipGetLastError();  // clear errors of earlier calls: report this launch's only
   double* vbase = work + (size_t)n_slots * ie_work_doubles(g);
-  const bool usemg = sv.precond == 1 && mg.nlev > 0;
+  const bool usemg = sv0.precond == 1 && mg.nlev > 0;
+  Solver sv = sv0;
+  size_t lds = 0;
+  sv.lds_lev = 0;
+  if (usemg && sv.precision != MQ_PREC_FP64) {
+    // the kernel's own LDS takes under 2 KB; two 512-thread workgroups share a compute unit
+    const size_t cap = (size_t)(NT == 512 ? sv.lds_limit / 2 : sv.lds_limit);
+    if (cap > 4096) sv.lds_lev = stream_lds_level(mg, sv, sizeof(float), cap - 4096, &lds);
+  }
+  auto setup = [&](const void* kern) -> hipError_t {
+    if (lds == 0) return hipSuccess;
+    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  };
   if (sv.precision == MQ_PREC_FP64) {
     if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<double, NT, true, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+      hipLaunchKernelGGL((k_ie_stream<double, NT, true, PARA>), dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst,
                          counter, work, S, vbase);
     else
-      hipLaunchKernelGGL((k_ie_stream<double, NT, false, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts,
+      hipLaunchKernelGGL((k_ie_stream<double, NT, false, PARA>), dim3(grid), dim3(NT), lds, st, g, mg, sv, insts,
                          n_inst, counter, work, S, vbase);
   } else {
     float* fb = reinterpret_cast<float*>(vbase);
-    if (usemg)
-      hipLaunchKernelGGL((k_ie_stream<float, NT, true, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+    if (usemg && sv.lds_lev > 0) {
+      const hipError_t e = setup((const void*)k_ie_stream<float, NT, true, PARA, true>);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ie_stream<float, NT, true, PARA, true>), dim3(grid), dim3(NT), lds, st, g, mg, sv, insts,
+                         n_inst, counter, work, S, fb);
+    } else if (usemg)
+      hipLaunchKernelGGL((k_ie_stream<float, NT, true, PARA>), dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst,
                          counter, work, S, fb);
     else
-      hipLaunchKernelGGL((k_ie_stream<float, NT, false, PARA>), dim3(grid), dim3(NT), 0, st, g, mg, sv, insts, n_inst,
+      hipLaunchKernelGGL((k_ie_stream<float, NT, false, PARA>), dim3(grid), dim3(NT), lds, st, g, mg, sv, insts, n_inst,
                          counter, work, S, fb);
   }
   return hipGetLastError();

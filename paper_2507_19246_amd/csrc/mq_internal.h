@@ -208,6 +208,8 @@ struct Solver {
   int mg_coarse_sweeps;  // damped-Jacobi sweeps at the coarsest level in use
   int mg_block_min;      // coarse levels with at least this many nodes per side use the whole workgroup
   int para;              // 1: the launch holds one-launch Parareal entries (kernels with the entry prologue)
+  int lds_limit = 0;     // LDS bytes one workgroup may use
+  int lds_lev = 0;       // streaming multigrid: first coarse level held in LDS (0: none; set by the launcher)
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4, FLAG_PARAREAL_KMAX = 8 };
