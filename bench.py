@@ -308,7 +308,9 @@ def bench_parareal(args, mq, L, W, np, torch):
         "q_max_rel_diff_parareal_vs_serial": None if sts is None else float(np.max(np.abs(qp - qsr) / np.abs(qsr))),
         "cg_iters_per_executed_step": inner / executed,
         "roofline": _hbm_roofline("k_ie_stream<float,%d,multigrid>" % stats[-1]["block"], bytes_launches, avg_kern_s,
-                                  measured_traffic("ie_stream_parareal_257_hbm_counters.md", "traffic_bytes_per_run"),
+                                  # (the committed counters are of the 1-step coarse propagator run)
+                                  measured_traffic("ie_stream_parareal_257_hbm_counters.md", "traffic_bytes_per_run")
+                                  if pr.coarse_steps_per_slice == 1 else None,
                                   f"{STREAM_MG_BYTES_PER_DOF_ITER} B per DoF-iteration + "
                                   f"{STREAM_OUTER_BYTES_PER_DOF_STEP} B per DoF-step, summed over the "
                                   "launches of one parareal_run"),

@@ -1189,7 +1189,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
             for (int k = 0; k < SH; ++k) {
               if (ACT(k)) {
                 const NodeRef nr = NREF(k);
-                const double res = Bv[nr.gi] - A_apply(g, tab, Xv, nr, inv_dt);
+                const double res = Bv[nr.gi] - A_apply_u(g, tab, Xv, nr, inv_dt);
                 rr[0] += res * res;
                 rl[l0 + k * LP] = vt<VT>(res * DN(k));
               }
