@@ -734,20 +734,6 @@ __device__ __attribute__((always_inline)) inline const VT* coarse_cycle(const MG
   return L == l0 ? zL : clev<VT>(mg, l0, region, ctab, NT, air).T;
 }
 
-// Coarse levels in use (mg_levels caps them).
-__host__ __device__ inline int stream_levels_used(const MGGeom& mg, const Solver& sv) {
-  return (sv.mg_levels > 0 && sv.mg_levels < mg.nlev) ? sv.mg_levels : mg.nlev;
-}
-// Elements of levels la..lz's vectors / tables (contiguous in the layout).
-__host__ __device__ inline int lds_vec_elems(const MGGeom& mg, int la, int lz) {
-  const MGLevel& z = mg.lv[lz];
-  return z.vec_off + 3 * (z.n + 2) * (z.n + 2) - mg.lv[la].vec_off;
-}
-__host__ __device__ inline int lds_tab_elems(const MGGeom& mg, int la, int lz) {
-  const MGLevel& z = mg.lv[lz];
-  return z.tab_off + 5 * z.RW * z.RH - mg.lv[la].tab_off;
-}
-
 // The same cycle with levels lds_lev..L in LDS (lds_reg: their vectors,
 // lds_tab: their tables, in the global layout's order) and levels
 // 1..lds_lev-1 in global memory (whole-workgroup levels); returns level 1's
@@ -1613,66 +1599,6 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
   }
 }
 
-bool build_mg(const Geom& g, int lp, MGGeom* mg) {
-  mg->nlev = 0;
-  mg->region_elems = 0;
-  mg->ctab_elems = 0;
-  const int n = g.n;
-  if (n < 3 || ((n + 1) & n) != 0) return false;  // n = 2^k - 1
-  MGLevel& f = mg->lv[0];
-  f.n = n;
-  f.bx0 = g.bx0;
-  f.bx1 = g.bx1;
-  f.by0 = g.by0;
-  f.by1 = g.by1;
-  f.lx1 = g.lx1;
-  f.ly1 = g.ly1;
-  f.RW = g.RW;
-  f.RH = g.RH;
-  f.tab_off = 0;
-  f.vec_off = 0;
-  int l = 0, vec = 0, tab = 0;
-  while (mg->lv[l].n > 1) {
-    if (l + 1 >= MG_MAX_LEVELS) return false;
-    const MGLevel& F = mg->lv[l];
-    const int nc = (F.n - 1) / 2;
-    MGLevel c{};
-    c.n = nc;
-    // coarse node ic owns non-air entries iff the fine rows 2ic..2ic+2 meet
-    // the fine lookup region [bx0, lx1)
-    auto range = [&](int f0, int f1, int* c0, int* c1) {
-      *c0 = nc;
-      *c1 = 0;
-      if (f1 <= f0) {
-        *c0 = *c1 = 0;
-        return;
-      }
-      for (int ic = 0; ic < nc; ++ic)
-        if (2 * ic + 2 >= f0 && 2 * ic <= f1 - 1) {
-          if (ic < *c0) *c0 = ic;
-          *c1 = ic + 1;
-        }
-      if (*c1 <= *c0) *c0 = *c1 = 0;
-    };
-    range(F.bx0, F.lx1, &c.bx0, &c.bx1);
-    range(F.by0, F.ly1, &c.by0, &c.by1);
-    if (c.bx1 == c.bx0 || c.by1 == c.by0) c.bx0 = c.bx1 = c.by0 = c.by1 = 0;
-    c.lx1 = c.bx1 > c.bx0 ? std::min(nc, c.bx1 + 1) : c.bx0;
-    c.ly1 = c.by1 > c.by0 ? std::min(nc, c.by1 + 1) : c.by0;
-    c.RW = (c.bx1 - c.bx0) + 2;
-    c.RH = (c.by1 - c.by0) + 2;
-    c.tab_off = tab;
-    tab += 5 * c.RW * c.RH;
-    c.vec_off = vec;
-    vec += 3 * (nc + 2) * (nc + 2);
-    mg->lv[++l] = c;
-  }
-  mg->nlev = l;
-  mg->region_elems = std::max((n + 2) * lp, vec);
-  mg->ctab_elems = tab;
-  return true;
-}
-
 template <typename VT>
 static size_t resident_lds(const Geom& g, const ResCfg& c, const MGGeom* mg) {
   const int nw = c.cw * c.ns / 64;
@@ -2048,28 +1974,6 @@ __device__ inline VT stencil_scaled(const Geom& g, const VT* __restrict__ R, con
          tNE[t - g.RW - 1] * R[gi - P - 1];
 }
 
-// Quad tables of the streaming kernel's float4 passes: the scaled E, N and NE
-// coefficients and D^{1/2} of the table region, laid out so that the four
-// nodes of a quad (first column i0 = 0 mod 4) are one aligned float4.  Columns
-// qx0 .. qx0 + qw - 1 (qx0 = 4 floor(bx0 / 4) - 4, qw = 0 mod 4) cover every
-// quad that meets the lookup columns [bx0, lx1) plus the column left of it;
-// rows by0 - 2 .. ly1 - 1 (row r = j - by0 + 2) put two rows of air below the
-// lookup rows.  Positions outside the table region hold the air values (-1/4,
-// -1/4, 0; D^{1/2} of air off the box), so a quad outside the lookup region
-// reads the fixed air position (row 1, column qx0 + 4) instead of branching
-// per node.
-struct QTab {
-  int qx0, qw, rows;
-};
-__host__ __device__ inline QTab qtab_geom(const Geom& g) {
-  QTab q;
-  q.qx0 = ((g.bx0 >> 2) << 2) - 4;
-  const int hi = g.lx1 > g.bx0 ? (((g.lx1 - 1) >> 2) << 2) + 4 : q.qx0 + 8;
-  q.qw = hi - q.qx0 < 8 ? 8 : hi - q.qx0;
-  q.rows = g.RH + 1;
-  return q;
-}
-
 // Per-slot VT workspace of the streaming kernel: six full-grid vectors, the
 // four quad-table planes, the five table planes over the box region (scaled
 // E, N, NE, D^{-1/2}, D^{1/2}) and, with multigrid, the coarse-level vectors
@@ -2101,11 +2005,6 @@ __device__ inline void st4(float* p, const f4v& v, int nv) {
     if (nv > 1) p[1] = v[1];
     if (nv > 2) p[2] = v[2];
   }
-}
-// Quad-table base of the quad (i0, j) inside the lookup region, else -1.
-__device__ inline int qbase(const Geom& g, const QTab& q, int i0, int j) {
-  const bool in = j >= g.by0 && j < g.ly1 && i0 + 3 >= g.bx0 && i0 < g.lx1;
-  return in ? (j - g.by0 + 2) * q.qw + (i0 - q.qx0) : -1;
 }
 // Where a quad's left and right neighbour quads are: quads of one row sit in
 // consecutive lanes, so the nodes just across a quad's edges are the
@@ -2787,23 +2686,6 @@ constexpr int STREAM_NT = 1024;
 
 size_t stream_vwork_elems(const Geom& g, const MGGeom* mg) {
   return stream_slot_elems(g, mg ? *mg : MGGeom{}, mg && mg->nlev > 0);
-}
-
-// First coarse level the streaming kernel keeps in LDS: the largest tail of
-// the levels in use that fits `budget` bytes, starting at level 2 or deeper,
-// every level above it a whole-workgroup level (0: none fits).
-static int stream_lds_level(const MGGeom& mg, const Solver& sv, size_t vt, size_t budget, size_t* bytes) {
-  *bytes = 0;
-  const int lz = stream_levels_used(mg, sv);
-  for (int la = 2; la <= lz; ++la) {
-    if (mg.lv[la - 1].n < sv.mg_block_min) return 0;
-    const size_t b = (size_t)(lds_vec_elems(mg, la, lz) + lds_tab_elems(mg, la, lz)) * vt;
-    if (b <= budget) {
-      *bytes = b;
-      return la;
-    }
-  }
-  return 0;
 }
 
 template <int NT, bool PARA>

@@ -193,6 +193,33 @@ struct MGGeom {
 };
 bool build_mg(const Geom& g, int lp, MGGeom* mg);
 
+// Quad tables of the streaming kernel's float4 passes: the scaled E, N and NE
+// coefficients and D^{1/2} of the table region, laid out so that the four
+// nodes of a quad (first column i0 = 0 mod 4) are one aligned float4.  Columns
+// qx0 .. qx0 + qw - 1 (qx0 = 4 floor(bx0 / 4) - 4, qw = 0 mod 4) cover every
+// quad that meets the lookup columns [bx0, lx1) plus the column left of it;
+// rows by0 - 2 .. ly1 - 1 (row r = j - by0 + 2; row 0 is not read).
+// Positions outside the table region hold the air values (-1/4, -1/4, 0;
+// D^{1/2} of air off the box).  A quad outside the lookup region reads no
+// table (air constants).
+struct QTab {
+  int qx0, qw, rows;
+};
+__host__ __device__ inline QTab qtab_geom(const Geom& g) {
+  QTab q;
+  q.qx0 = ((g.bx0 >> 2) << 2) - 4;
+  const int hi = g.lx1 > g.bx0 ? (((g.lx1 - 1) >> 2) << 2) + 4 : q.qx0 + 8;
+  q.qw = hi - q.qx0 < 8 ? 8 : hi - q.qx0;
+  q.rows = g.RH + 1;
+  return q;
+}
+
+// Quad-table base of the quad (i0, j) inside the lookup region, else -1.
+__host__ __device__ inline int qbase(const Geom& g, const QTab& q, int i0, int j) {
+  const bool in = j >= g.by0 && j < g.ly1 && i0 + 3 >= g.bx0 && i0 < g.lx1;
+  return in ? (j - g.by0 + 2) * q.qw + (i0 - q.qx0) : -1;
+}
+
 struct Solver {
   int precond;     // 0 = Jacobi scaling only, 1 = multigrid V(1,1) (resident path)
   double mg_omega; // damped-Jacobi weight of the multigrid smoother
@@ -213,6 +240,37 @@ struct Solver {
 };
 
 enum { FLAG_NOT_CONVERGED = 1, FLAG_FAILED = 2, FLAG_PICARD_CAP = 4, FLAG_PARAREAL_KMAX = 8 };
+// Coarse levels in use (mg_levels caps them).
+__host__ __device__ inline int stream_levels_used(const MGGeom& mg, const Solver& sv) {
+  return (sv.mg_levels > 0 && sv.mg_levels < mg.nlev) ? sv.mg_levels : mg.nlev;
+}
+// Elements of levels la..lz's vectors / tables (contiguous in the layout).
+__host__ __device__ inline int lds_vec_elems(const MGGeom& mg, int la, int lz) {
+  const MGLevel& z = mg.lv[lz];
+  return z.vec_off + 3 * (z.n + 2) * (z.n + 2) - mg.lv[la].vec_off;
+}
+__host__ __device__ inline int lds_tab_elems(const MGGeom& mg, int la, int lz) {
+  const MGLevel& z = mg.lv[lz];
+  return z.tab_off + 5 * z.RW * z.RH - mg.lv[la].tab_off;
+}
+
+// First coarse level the streaming kernel keeps in LDS: the largest tail of
+// the levels in use that fits `budget` bytes, starting at level 2 or deeper,
+// every level above it a whole-workgroup level (0: none fits).
+inline int stream_lds_level(const MGGeom& mg, const Solver& sv, size_t vt, size_t budget, size_t* bytes) {
+  *bytes = 0;
+  const int lz = stream_levels_used(mg, sv);
+  for (int la = 2; la <= lz; ++la) {
+    if (mg.lv[la - 1].n < sv.mg_block_min) return 0;
+    const size_t b = (size_t)(lds_vec_elems(mg, la, lz) + lds_tab_elems(mg, la, lz)) * vt;
+    if (b <= budget) {
+      *bytes = b;
+      return la;
+    }
+  }
+  return 0;
+}
+
 // bits that make a call return MQ_WARN_NOT_CONVERGED
 constexpr int FLAG_WARN = FLAG_NOT_CONVERGED | FLAG_FAILED | FLAG_PICARD_CAP;
 enum { STAT_N = 17 };

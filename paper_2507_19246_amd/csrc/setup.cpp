@@ -203,4 +203,64 @@ HostMesh build_host_mesh(const mq_problem_desc& d) {
   return hm;
 }
 
+bool build_mg(const Geom& g, int lp, MGGeom* mg) {
+  mg->nlev = 0;
+  mg->region_elems = 0;
+  mg->ctab_elems = 0;
+  const int n = g.n;
+  if (n < 3 || ((n + 1) & n) != 0) return false;  // n = 2^k - 1
+  MGLevel& f = mg->lv[0];
+  f.n = n;
+  f.bx0 = g.bx0;
+  f.bx1 = g.bx1;
+  f.by0 = g.by0;
+  f.by1 = g.by1;
+  f.lx1 = g.lx1;
+  f.ly1 = g.ly1;
+  f.RW = g.RW;
+  f.RH = g.RH;
+  f.tab_off = 0;
+  f.vec_off = 0;
+  int l = 0, vec = 0, tab = 0;
+  while (mg->lv[l].n > 1) {
+    if (l + 1 >= MG_MAX_LEVELS) return false;
+    const MGLevel& F = mg->lv[l];
+    const int nc = (F.n - 1) / 2;
+    MGLevel c{};
+    c.n = nc;
+    // coarse node ic owns non-air entries iff the fine rows 2ic..2ic+2 meet
+    // the fine lookup region [bx0, lx1)
+    auto range = [&](int f0, int f1, int* c0, int* c1) {
+      *c0 = nc;
+      *c1 = 0;
+      if (f1 <= f0) {
+        *c0 = *c1 = 0;
+        return;
+      }
+      for (int ic = 0; ic < nc; ++ic)
+        if (2 * ic + 2 >= f0 && 2 * ic <= f1 - 1) {
+          if (ic < *c0) *c0 = ic;
+          *c1 = ic + 1;
+        }
+      if (*c1 <= *c0) *c0 = *c1 = 0;
+    };
+    range(F.bx0, F.lx1, &c.bx0, &c.bx1);
+    range(F.by0, F.ly1, &c.by0, &c.by1);
+    if (c.bx1 == c.bx0 || c.by1 == c.by0) c.bx0 = c.bx1 = c.by0 = c.by1 = 0;
+    c.lx1 = c.bx1 > c.bx0 ? std::min(nc, c.bx1 + 1) : c.bx0;
+    c.ly1 = c.by1 > c.by0 ? std::min(nc, c.by1 + 1) : c.by0;
+    c.RW = (c.bx1 - c.bx0) + 2;
+    c.RH = (c.by1 - c.by0) + 2;
+    c.tab_off = tab;
+    tab += 5 * c.RW * c.RH;
+    c.vec_off = vec;
+    vec += 3 * (nc + 2) * (nc + 2);
+    mg->lv[++l] = c;
+  }
+  mg->nlev = l;
+  mg->region_elems = std::max((n + 2) * lp, vec);
+  mg->ctab_elems = tab;
+  return true;
+}
+
 }  // namespace mq
