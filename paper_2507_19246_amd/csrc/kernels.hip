@@ -184,25 +184,64 @@ __device__ inline double A_apply(const Geom& g, const double* __restrict__ tab, 
   return M_apply(g, tab, v, nr) * inv_dt + K_apply(g, tab, v, nr);
 }
 
-// A_apply with every load issued at once (a node outside the lookup region
-// reads the region's first box position and keeps the air stencil): the
-// loads of a pass are not serialised behind the region test.  Same
-// expression per node as A_apply.
+// A_apply, M_apply and K_apply with the table loads grouped: a node inside
+// the lookup region issues all its table loads before any use, and a wave
+// with no such node issues none.  Same expression per node as A_apply,
+// M_apply and K_apply.
+struct Tab7 {
+  double kc, ke, kw, kn, ks, mc, me, mw, mn, ms, mne, msw;
+};
+__device__ inline Tab7 tab_load(const Geom& g, const double* __restrict__ tab, const NodeRef& nr, bool want_m,
+                                bool want_k) {
+  Tab7 T{};
+  if (nr.inL) {
+    const int RW = g.RW, RHW = g.RW * g.RH, t = nr.t;
+    if (want_k) {
+      T.kc = tab[T_KC * RHW + t];
+      T.ke = tab[T_KE * RHW + t];
+      T.kw = tab[T_KE * RHW + t - 1];
+      T.kn = tab[T_KN * RHW + t];
+      T.ks = tab[T_KN * RHW + t - RW];
+    }
+    if (want_m) {
+      T.mc = tab[T_MC * RHW + t];
+      T.me = tab[T_ME * RHW + t];
+      T.mw = tab[T_ME * RHW + t - 1];
+      T.mn = tab[T_MN * RHW + t];
+      T.ms = tab[T_MN * RHW + t - RW];
+      T.mne = tab[T_MNE * RHW + t];
+      T.msw = tab[T_MNE * RHW + t - RW - 1];
+    }
+  }
+  return T;
+}
 __device__ inline double A_apply_u(const Geom& g, const double* __restrict__ tab, const double* v,
                                    const NodeRef& nr, double inv_dt) {
-  const int P = g.P, gi = nr.gi, RW = g.RW, RHW = g.RW * g.RH;
+  const int P = g.P, gi = nr.gi;
   const double c = v[gi], e = v[gi + 1], w = v[gi - 1], n = v[gi + P], s = v[gi - P], ne = v[gi + P + 1],
                sw = v[gi - P - 1];
-  const int t = nr.inL ? nr.t : RW + 1;
-  const double kc = tab[T_KC * RHW + t], ke = tab[T_KE * RHW + t], kw = tab[T_KE * RHW + t - 1],
-               kn = tab[T_KN * RHW + t], ks = tab[T_KN * RHW + t - RW];
-  const double mc = tab[T_MC * RHW + t], me = tab[T_ME * RHW + t], mw = tab[T_ME * RHW + t - 1],
-               mn = tab[T_MN * RHW + t], ms = tab[T_MN * RHW + t - RW], mne = tab[T_MNE * RHW + t],
-               msw = tab[T_MNE * RHW + t - RW - 1];
+  const Tab7 T = tab_load(g, tab, nr, true, true);
   const double air = g.nu_air * (4.0 * c - (e + w) - (n + s));
-  const double m = mc * c + me * e + mw * w + mn * n + ms * s + mne * ne + msw * sw;
-  const double k = kc * c + ke * e + kw * w + kn * n + ks * s;
+  const double m = T.mc * c + T.me * e + T.mw * w + T.mn * n + T.ms * s + T.mne * ne + T.msw * sw;
+  const double k = T.kc * c + T.ke * e + T.kw * w + T.kn * n + T.ks * s;
   return nr.inL ? m * inv_dt + k : air;
+}
+__device__ inline double K_apply_u(const Geom& g, const double* __restrict__ tab, const double* v,
+                                   const NodeRef& nr) {
+  const int P = g.P, gi = nr.gi;
+  const double c = v[gi], e = v[gi + 1], w = v[gi - 1], n = v[gi + P], s = v[gi - P];
+  const Tab7 T = tab_load(g, tab, nr, false, true);
+  const double air = g.nu_air * (4.0 * c - (e + w) - (n + s));
+  return nr.inL ? T.kc * c + T.ke * e + T.kw * w + T.kn * n + T.ks * s : air;
+}
+// (M v)_node inside the lookup region (callers add it only there)
+__device__ inline double M_apply_u(const Geom& g, const double* __restrict__ tab, const double* v,
+                                   const NodeRef& nr) {
+  const int P = g.P, gi = nr.gi;
+  const double c = v[gi], e = v[gi + 1], w = v[gi - 1], n = v[gi + P], s = v[gi - P], ne = v[gi + P + 1],
+               sw = v[gi - P - 1];
+  const Tab7 T = tab_load(g, tab, nr, true, false);
+  return T.mc * c + T.me * e + T.mw * w + T.mn * n + T.ms * s + T.mne * ne + T.msw * sw;
 }
 
 // ---------------------------------------------------------------------------
@@ -1151,7 +1190,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         for (int k = 0; k < SH; ++k) {
           if (ACT(k)) {
             const NodeRef nr = NREF(k);
-            const double b = Jt * S[nr.gi] - K_apply(g, tab, Av, nr);
+            const double b = Jt * S[nr.gi] - K_apply_u(g, tab, Av, nr);
             Bv[nr.gi] = b;
             part[0] += b * b;
           }
@@ -1516,7 +1555,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
 #pragma unroll 1
         for (int k = 0; k < SH; ++k) {
           const NodeRef nr = NREF(k);
-          if (ACT(k) && nr.inL) qq[0] += Xv[nr.gi] * M_apply(g, tab, Xv, nr);
+          if (ACT(k) && nr.inL) qq[0] += Xv[nr.gi] * M_apply_u(g, tab, Xv, nr);
         }
         block_sum<1, NWAVES>(qq, red, slot);
         qsum += qq[0] * inv_dt;
@@ -1529,7 +1568,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
             Av[gi] += d;
             Xv[gi] = 2.0 * d - Pv[gi];
             Pv[gi] = d;
-            Qv[gi] = 0.0;
+            if constexpr (NL) Qv[gi] = 0.0;  // (linear: never written, zero from the start)
           }
         }
         __syncthreads();
@@ -2262,7 +2301,7 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
         double part[1] = {0.0};
         for (int j = fj0; j < n; j += fty) for (int i = ftx; i < n; i += (1 << fs)) {
           const NodeRef nr = node_ref(g, i, j);
-          const double b = Jt * S[nr.gi] - K_apply(g, tab, Av, nr);
+          const double b = Jt * S[nr.gi] - K_apply_u(g, tab, Av, nr);
           Bv[nr.gi] = b;
           part[0] += b * b;
         }
