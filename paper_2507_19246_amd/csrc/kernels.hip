@@ -2057,15 +2057,16 @@ __device__ inline QLane qlane(int qtx, int nq) {
   const int lane = threadIdx.x & 63;
   return QLane{qtx == 0, lane == 0 && qtx > 0, lane == 63 && qtx + 1 < nq};
 }
-// scaled 7-point stencil of four nodes (i0..i0+3, j), the float4 form of
-// stencil_scaled (gi = index of (i0, j)): three row loads, the coefficients
-// from the quad tables inside the lookup region (air values elsewhere), the
-// values across the quad's edges from the adjacent lanes.  Same expression
-// per node as stencil_scaled inside the lookup region.
-__device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, const float* __restrict__ V,
-                               const float* qE, const float* qN, const float* qNE, int i0, int j, int gi) {
-  const int P = g.P;
-  const f4v c = ld4(V + gi), up = ld4(V + gi + P), dn = ld4(V + gi - P);
+// scaled 7-point stencil of four nodes (i0..i0+3, j) from their rows c (row
+// j), up (j + 1), dn (j - 1) and the four values across the quad's edges (w =
+// (i0-1, j), e = (i0+4, j), ne = (i0+4, j+1), sw = (i0-1, j-1)): the
+// coefficients from the quad tables inside the lookup region (air values
+// elsewhere), the W and SW coefficients at the quad's left edge from the
+// adjacent lane.  Same expression per node as stencil_scaled inside the
+// lookup region.
+__device__ inline f4v stencil4_rows(const Geom& g, const QTab& q, const QLane& ql, const f4v& c, const f4v& up,
+                                    const f4v& dn, float w, float e, float ne, float sw, const float* qE,
+                                    const float* qN, const float* qNE, int i0, int j) {
   const int b = qbase(g, q, i0, j);
   f4v E, N, Nb, NE, NEb;
   if (b >= 0) {
@@ -2078,21 +2079,14 @@ __device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, co
     E = N = Nb = f4v{-0.25f, -0.25f, -0.25f, -0.25f};
     NE = NEb = f4v{0.0f, 0.0f, 0.0f, 0.0f};
   }
-  float w = from_left(c[3]), sw = from_left(dn[3]), Ew = from_left(E[3]), NEbw = from_left(NEb[3]);
-  float e = from_right(c[0]), ne = from_right(up[0]);
+  float Ew = from_left(E[3]), NEbw = from_left(NEb[3]);
   if (ql.lzero) {
-    w = sw = NEbw = 0.0f;
+    NEbw = 0.0f;
     Ew = -0.25f;
   }
   if (ql.lload) {
-    w = V[gi - 1];
-    sw = V[gi - P - 1];
     Ew = b >= 0 ? qE[b - 1] : -0.25f;
     NEbw = b >= 0 ? qNE[b - q.qw - 1] : 0.0f;
-  }
-  if (ql.rload) {
-    e = V[gi + 4];
-    ne = V[gi + P + 4];
   }
   f4v out;
 #pragma unroll
@@ -2103,6 +2097,25 @@ __device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, co
     out[k] = c[k] + E[k] * ek + cw * wk + N[k] * up[k] + Nb[k] * dn[k] + NE[k] * nek + csw * swk;
   }
   return out;
+}
+// The same stencil of the vector V (gi = index of (i0, j)): three row loads,
+// the values across the quad's edges from the adjacent lanes (the zero ring
+// at a row's ends; loaded where a row continues in the next wave).
+__device__ inline f4v stencil4(const Geom& g, const QTab& q, const QLane& ql, const float* __restrict__ V,
+                               const float* qE, const float* qN, const float* qNE, int i0, int j, int gi) {
+  const int P = g.P;
+  const f4v c = ld4(V + gi), up = ld4(V + gi + P), dn = ld4(V + gi - P);
+  float w = from_left(c[3]), sw = from_left(dn[3]), e = from_right(c[0]), ne = from_right(up[0]);
+  if (ql.lzero) w = sw = 0.0f;
+  if (ql.lload) {
+    w = V[gi - 1];
+    sw = V[gi - P - 1];
+  }
+  if (ql.rload) {
+    e = V[gi + 4];
+    ne = V[gi + P + 4];
+  }
+  return stencil4_rows(g, q, ql, c, up, dn, w, e, ne, sw, qE, qN, qNE, i0, j);
 }
 
 // LC: coarse levels sv.lds_lev.. in LDS (launched with their bytes of dynamic
@@ -2463,37 +2476,78 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                                                   sv.mg_block_min);
                 __syncthreads();
                 tick(1);
-                if constexpr (QV) {
-                  if (quad) {
-                    quads2(
-                        [&](int i0, int j, int gi) {
-                          f4v z = ld4((const float*)Zm + gi);
-                          const f4v di = dinv4(i0, j);
-#pragma unroll
-                          for (int k = 0; k < 4; ++k)
-                            if (i0 + k < n) z[k] = z[k] + (float)prolong_at(z1, L1.np, i0 + k, j) * di[k];
-                          return F4x2{z, z};
-                        },
-                        [&](int gi, int nv, const F4x2& v) { st4((float*)Zm + gi, v.a, nv); });
-                  }
-                }
-                if (!quad)
-                nodes2(
-                    [&](int i, int j, const NodeRef& nr) {
-                      return V2{Zm[nr.gi] + prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr), VT(0)};
-                    },
-                    [&](const NodeRef& nr, const V2& v) { Zm[nr.gi] = v.x; });
-                __syncthreads();
-                // post-smoothing z <- z + om (r - A z); r.z and r.r of the new z
+                // prolongation z <- z + P z_1 D^{1/2} and post-smoothing z <- z + om (r - A z);
+                // r.z and r.r of the new z
                 double rz[2] = {0.0, 0.0};
                 if constexpr (QV) {
                   if (quad) {
+                    // One pass: each quad forms the prolonged z of its four nodes on
+                    // rows j - 1, j, j + 1 (the coarse values it needs: columns 2q - 1
+                    // .. 2q + 1 of coarse rows m - 1 .. m + 1, m = j / 2, the left one
+                    // from the adjacent lane) and takes the values across its edges
+                    // from the adjacent lanes; the same values, computed in the same
+                    // way, that a separate prolongation pass would store.
                     const float* Z4 = (const float*)Zm;
+                    const float* zc1 = (const float*)z1;
+                    const int cp = L1.np, nc = L1.n;
+                    struct CRow {
+                      float c0, c1, cm;  // coarse columns 2q, 2q + 1, 2q - 1 of one coarse row
+                    };
+                    auto crow = [&](int i0, int mr) __attribute__((always_inline)) {
+                      const float* b = zc1 + (mr + 1) * cp + (i0 >> 1) + 1;
+                      CRow r{b[0], b[1], 0.0f};
+                      r.cm = from_left(r.c1);
+                      if (ql.lzero) r.cm = 0.0f;
+                      if (ql.lload) r.cm = b[-1];
+                      return r;
+                    };
+                    // P z_1 on a fine row: odd rows from coarse row jr / 2 (a), even rows
+                    // from coarse rows jr / 2 (a) and jr / 2 - 1 (b)
+                    auto p_odd = [](const CRow& a) __attribute__((always_inline)) {
+                      return f4v{0.5f * (a.cm + a.c0), a.c0, 0.5f * (a.c0 + a.c1), a.c1};
+                    };
+                    auto p_even = [](const CRow& a, const CRow& b) __attribute__((always_inline)) {
+                      return f4v{0.5f * (b.cm + a.c0), 0.5f * (b.c0 + a.c0), 0.5f * (b.c0 + a.c1),
+                                 0.5f * (b.c1 + a.c1)};
+                    };
+                    auto zrow = [&](int i0, int jr, int gr, const f4v& pv) __attribute__((always_inline)) {
+                      if (jr < 0 || jr >= n) return f4v{0.0f, 0.0f, 0.0f, 0.0f};  // boundary ring
+                      f4v z = ld4(Z4 + gr);
+                      const f4v di = dinv4(i0, jr);
+#pragma unroll
+                      for (int k = 0; k < 4; ++k)
+                        if (i0 + k < n) z[k] = z[k] + pv[k] * di[k];
+                      return z;
+                    };
+                    // one node's prolonged z (the lanes at a wave's ends of rows that
+                    // continue in the next wave)
+                    auto zone = [&](int i, int jr) -> float {
+                      if (i < 0 || i >= n || jr < 0 || jr >= n) return 0.0f;
+                      const NodeRef nr = node_ref(g, i, jr);
+                      return Z4[nr.gi] + (float)prolong_at(z1, cp, i, jr) * (float)dnode_inv(i, jr, nr);
+                    };
                     quads2(
                         [&](int i0, int j, int gi) {
-                          const f4v r = ld4((const float*)Rv + gi), z = ld4(Z4 + gi);
-                          const f4v az = stencil4(g, qg, ql, Z4, qE, qN, qNE, i0, j, gi);
-                          return F4x2{z + (float)om * (r - az), r};
+                          const int m = j >> 1;
+                          const CRow a = crow(i0, m), b = crow(i0, m - 1), c = crow(i0, m + 1 <= nc ? m + 1 : nc);
+                          const bool odd = j & 1;
+                          const f4v zc = zrow(i0, j, gi, odd ? p_odd(a) : p_even(a, b));
+                          const f4v zu = zrow(i0, j + 1, gi + g.P, odd ? p_even(c, a) : p_odd(a));
+                          const f4v zd = zrow(i0, j - 1, gi - g.P, odd ? p_even(a, b) : p_odd(b));
+                          float w = from_left(zc[3]), sw = from_left(zd[3]), e = from_right(zc[0]),
+                                ne = from_right(zu[0]);
+                          if (ql.lzero) w = sw = 0.0f;
+                          if (ql.lload) {
+                            w = zone(i0 - 1, j);
+                            sw = zone(i0 - 1, j - 1);
+                          }
+                          if (ql.rload) {
+                            e = zone(i0 + 4, j);
+                            ne = zone(i0 + 4, j + 1);
+                          }
+                          const f4v az = stencil4_rows(g, qg, ql, zc, zu, zd, w, e, ne, sw, qE, qN, qNE, i0, j);
+                          const f4v r = ld4((const float*)Rv + gi);
+                          return F4x2{zc + (float)om * (r - az), r};
                         },
                         [&](int gi, int nv, const F4x2& v) {
                           st4((float*)Tm + gi, v.a, nv);
@@ -2507,17 +2561,24 @@ __global__ __launch_bounds__(NT, 4) void k_ie_stream(Geom g, MGGeom mg, Solver s
                         });
                   }
                 }
-                if (!quad)
-                nodes2(
-                    [&](int, int, const NodeRef& nr) {
-                      const VT r = Rv[nr.gi], z = Zm[nr.gi];
-                      return V2{z + om * (r - stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr)), r};
-                    },
-                    [&](const NodeRef& nr, const V2& v) {
-                      Tm[nr.gi] = v.x;
-                      rz[0] += (double)(v.y * v.x);
-                      rz[1] += (double)(v.y * v.y);
-                    });
+                if (!quad) {
+                  nodes2(
+                      [&](int i, int j, const NodeRef& nr) {
+                        return V2{Zm[nr.gi] + prolong_at(z1, L1.np, i, j) * dnode_inv(i, j, nr), VT(0)};
+                      },
+                      [&](const NodeRef& nr, const V2& v) { Zm[nr.gi] = v.x; });
+                  __syncthreads();
+                  nodes2(
+                      [&](int, int, const NodeRef& nr) {
+                        const VT r = Rv[nr.gi], z = Zm[nr.gi];
+                        return V2{z + om * (r - stencil_scaled<VT>(g, Zm, tE, tN, tNE, nr)), r};
+                      },
+                      [&](const NodeRef& nr, const V2& v) {
+                        Tm[nr.gi] = v.x;
+                        rz[0] += (double)(v.y * v.x);
+                        rz[1] += (double)(v.y * v.y);
+                      });
+                }
                 block_sum<2, NWAVES>(rz, red, slot);
                 tick(2);
                 { VT* t_ = Zm; Zm = Tm; Tm = t_; }

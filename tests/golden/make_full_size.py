@@ -55,6 +55,21 @@ def _c3(sample):
     return {"level": 0, "sample": sample, "q": float(q), "picard_iters": int(counts.sum()), "flagged": bool(flagged)}
 
 
+def _c3_top(sample):
+    """A sample of the finest level of the nonlinear workload: fine and coupled coarse run."""
+    import workloads as W
+    from oracle import picard
+    w = W.nonlinear_mlmc4_129()
+    level = len(w.levels) - 1
+    lv = w.levels[level]
+    xi = W.level_xi(w, level, first=sample, n=1)[0]
+    qf, _, cf, ff = picard.solve_sample(w.problem, xi, lv.steps_per_period, lv.n_periods, return_counts=True)
+    qc, _, cc, fc = picard.solve_sample(w.problem, xi, lv.coarse_steps_per_period, lv.n_periods, return_counts=True)
+    return {"level": level, "sample": sample, "q_fine": float(qf), "q_coarse": float(qc),
+            "picard_iters_fine": int(cf.sum()), "picard_iters_coarse": int(cc.sum()),
+            "flagged": bool(ff or fc)}
+
+
 def _c4(index):
     import workloads as W
     from oracle import timestep
@@ -78,8 +93,10 @@ def main():
         f2 = [ex.submit(_c2, 0)]
         f3 = [ex.submit(_c3, s) for s in (0, 1)]
         f4 = [ex.submit(_c4, big.rid)]
+        f5 = [ex.submit(_c3_top, 0)]
         out = {"mlmc3_129": [f.result() for f in f1], "parareal_257": [f.result() for f in f2],
-               "nonlinear_129": [f.result() for f in f3], "serving": [f.result() for f in f4]}
+               "nonlinear_129": [f.result() for f in f3], "serving": [f.result() for f in f4],
+               "nonlinear_129_top": [f.result() for f in f5]}
     out["generator"] = "tests/golden/make_full_size.py (oracle only)"
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)

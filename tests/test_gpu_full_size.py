@@ -107,6 +107,28 @@ def test_full_size_nonlinear_129(golden):
     prob.close()
 
 
+def test_full_size_nonlinear_129_finest_level(golden):
+    """The finest level of the nonlinear MLMC workload (512 fine and 256 coupled
+    coarse Picard steps): Q of both runs of its first sample against the oracle."""
+    import paper_2507_19246_amd as mq
+    from paper_2507_19246_amd import _lib as L, autotune
+    w = W.nonlinear_mlmc4_129()
+    level = len(w.levels) - 1
+    lv = w.levels[level]
+    xi = W.level_xi(w, level, n=1)
+    prob, knobs = autotune.tuned_problem(w.problem, L.MQ_PREC_MIXED)
+    qf, qc, _, rc, st = mq.mlmc_level_run(prob, lv.steps_per_period, lv.coarse_steps_per_period, lv.n_periods, xi)
+    assert rc == 0
+    g = golden["nonlinear_129_top"][0]
+    assert g["level"] == level and g["sample"] == 0 and not g["flagged"]
+    ef, ec = rel(float(qf[0]), g["q_fine"]), rel(float(qc[0]), g["q_coarse"])
+    say("nonlinear finest level: err fine", ef, "coarse", ec, "picard", st["picard_iters"])
+    assert ef <= TOL and ec <= TOL
+    ref_its = g["picard_iters_fine"] + g["picard_iters_coarse"]
+    assert abs(st["picard_iters"] - ref_its) <= (lv.steps_per_period + lv.coarse_steps_per_period) * lv.n_periods // 2
+    prob.close()
+
+
 def test_full_size_serving_513(golden):
     """A 513x513 request of the serving stream through the server."""
     import time
