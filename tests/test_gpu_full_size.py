@@ -154,6 +154,28 @@ def test_full_size_serving_513(golden):
     assert e <= TOL
 
 
+def test_full_size_513_streaming_batch(golden):
+    """The stored 513x513 request run four times in one batched launch of the
+    streaming kernel (the coarse levels from level 3 on in LDS): every copy
+    equal, and equal to the oracle's value."""
+    import paper_2507_19246_amd as mq
+    from paper_2507_19246_amd import _lib as L, autotune
+    g = golden["serving"][0]
+    r = W.serving_stream(4096)[g["index"]]
+    prob = W.Problem(513, W.Material(kind=W.MAT_KL))
+    p, knobs = autotune.tuned_problem(prob, L.MQ_PREC_MIXED, path=L.MQ_PATH_STREAMING)
+    assert p.path == L.MQ_PATH_STREAMING
+    xi = np.repeat(np.asarray(r.xi, dtype=np.float64)[None, :], 4, axis=0)
+    q, _, _, rc, st = mq.mlmc_level_run(p, r.steps_per_period, 0, r.n_periods, xi)
+    assert rc == 0 and st["path"] == L.MQ_PATH_STREAMING and st["n_instances"] == 4
+    qs = q.cpu().numpy()
+    e = rel(float(qs[0]), g["q"])
+    say("513x513 streaming batch: err", e, "iters/step", st["inner_iters"] / st["sample_steps"])
+    assert np.all(qs == qs[0])
+    assert e <= TOL
+    p.close()
+
+
 def test_tuned_knobs_are_found():
     """The committed autotuner cache has this device's entries for the bench
     workloads, so every bench line runs its tuned configuration."""
