@@ -72,14 +72,6 @@ PAPER_CONTEXT = {
                 "Distributed.jl) with GetDP/Gmsh; no GPU; precision not stated",
     "source": "Sec. III (results), Sec. IV (conclusions), Table II",
 }
-# streaming multigrid CG, algorithmic HBM bytes per fine DoF and iteration (FP32
-# vectors, each vector element read/written once per pass): pre-smoothing and
-# residual 12, restriction 6, prolongation 9, post-smoothing 12, p/q update 20,
-# y/r update 24, coarse levels (1/4 + 1/16 + ...) x 40 = 13
-STREAM_MG_BYTES_PER_DOF_ITER = 96
-# outer FP64 work per fine DoF and time step (right-hand side 24, two
-# refinement residuals 2 x 36, two increment updates 2 x 20, state update 48, QoI)
-STREAM_OUTER_BYTES_PER_DOF_STEP = 220
 
 
 def _kernel_source_hash() -> str:
@@ -291,7 +283,8 @@ def bench_parareal(args, mq, L, W, np, torch):
     executed = stats[-1]["sample_steps"]
     avg_kern_s = sum(s["kernel_ms"] for s in stats) / len(stats) / 1e3
     inner = stats[-1]["inner_iters"]
-    bytes_launches = nd * (inner * STREAM_MG_BYTES_PER_DOF_ITER + executed * STREAM_OUTER_BYTES_PER_DOF_STEP)
+    resid = stats[-1]["sweeps"] + executed  # FP64 residual passes: one per sweep plus the converged check
+    bytes_launches = nd * (ALG_BYTES_CG_ITER_FP32 * inner + ALG_BYTES_FP64_RESIDUAL * resid + ALG_BYTES_STEP * executed)
     res = _contract("sample-steps/s", useful * args.steps / elapsed, elapsed, args, {
         "workload": w.name, "mesh": "257x257", "n_dof": nd, "samples": int(xi.shape[0]),
         "fine_steps": n_f, "slices": pr.n_slices, "coarse_steps_per_slice": pr.coarse_steps_per_slice,
@@ -311,9 +304,10 @@ def bench_parareal(args, mq, L, W, np, torch):
                                   # (the committed counters are of the 1-step coarse propagator run)
                                   measured_traffic("ie_stream_parareal_257_hbm_counters.md", "traffic_bytes_per_run")
                                   if pr.coarse_steps_per_slice == 1 else None,
-                                  f"{STREAM_MG_BYTES_PER_DOF_ITER} B per DoF-iteration + "
-                                  f"{STREAM_OUTER_BYTES_PER_DOF_STEP} B per DoF-step, summed over the "
-                                  "launches of one parareal_run"),
+                                  f"{ALG_BYTES_CG_ITER_FP32} B per DoF and CG iteration + "
+                                  f"{ALG_BYTES_FP64_RESIDUAL} B per DoF and FP64 residual + "
+                                  f"{ALG_BYTES_STEP} B per DoF and executed step; units of the launch: "
+                                  f"{inner} CG iterations, {resid} residuals, {executed} steps over {nd} DoF"),
     })
     if not args.no_cpu_baseline and sts is not None:
         tasks = [(w.problem, xi_np[s], spp, pr.n_periods) for s in range(2)]
