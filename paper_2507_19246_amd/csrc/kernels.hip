@@ -1559,7 +1559,7 @@ __global__ __launch_bounds__(CW* NS) void k_ie_resident(Geom g, MGGeom mg, Solve
         }
         block_sum<1, NWAVES>(qq, red, slot);
         qsum += qq[0] * inv_dt;
-#pragma unroll 1
+#pragma unroll 4
         for (int k = 0; k < SH; ++k) {
           if (ACT(k)) {
             // a += d; next start 2 d_k - d_{k-1} (linear extrapolation)
