@@ -534,9 +534,9 @@ __device__ inline float from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-// The same with every load issued unconditionally (levels in global memory):
-// a node outside the table region reads the region's first box position and
-// keeps the air stencil, so the loads of a pass are not serialised behind the
+// The same for levels in global memory: a node inside the table region
+// issues all its table loads together before any use (a wave with no such
+// node issues none), so the loads of a pass are not serialised behind the
 // region test.  Same expression per node as capp.
 template <typename VT>
 __device__ inline VT capp_gm(const CLev<VT>& L, const VT* v, int i, int j, VT* idg) {
@@ -544,9 +544,18 @@ __device__ inline VT capp_gm(const CLev<VT>& L, const VT* v, int i, int j, VT* i
   const VT c = v[p], e = v[p + 1], w = v[p - 1], nn = v[p + np], s = v[p - np], ne = v[p + np + 1],
            sw = v[p - np - 1];
   const bool in = clev_inL(L, i, j);
-  const int t = in ? (j - L.by0 + 1) * L.RW + (i - L.bx0 + 1) : L.RW + 1;
-  const VT tc = L.C[t], te = L.E[t], tw = L.E[t - 1], tn = L.N[t], ts = L.N[t - L.RW], tne = L.NE[t],
-           tsw = L.NE[t - L.RW - 1], ti = L.ID[t];
+  VT tc = VT(0), te = VT(0), tw = VT(0), tn = VT(0), ts = VT(0), tne = VT(0), tsw = VT(0), ti = VT(0);
+  if (in) {
+    const int t = (j - L.by0 + 1) * L.RW + (i - L.bx0 + 1);
+    tc = L.C[t];
+    te = L.E[t];
+    tw = L.E[t - 1];
+    tn = L.N[t];
+    ts = L.N[t - L.RW];
+    tne = L.NE[t];
+    tsw = L.NE[t - L.RW - 1];
+    ti = L.ID[t];
+  }
   *idg = in ? ti : L.air_id;
   return in ? tc * c + te * e + tw * w + tn * nn + ts * s + tne * ne + tsw * sw
             : L.air * (c - VT(0.25) * ((e + w) + (nn + s)));
