@@ -12,7 +12,8 @@ candidate of:
 
 then, for the best multigrid candidate, the depth of the coarse hierarchy
 (``mg_levels``) and the damped-Jacobi sweeps at its coarsest level
-(``mg_coarse_sweeps``), and keeps the fastest candidate whose QoIs agree with the default
+(``mg_coarse_sweeps``), then the smoother weight and the inner tolerance again
+with that hierarchy, and keeps the fastest candidate whose QoIs agree with the default
 configuration's within the precision's tolerance (1e-6 mixed, 1e-10 FP64).
 The outer tolerance, and so the accuracy of every result, is never tuned.
 
@@ -32,6 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
 
 QOI_AGREEMENT = {L.MQ_PREC_MIXED: 1e-6, L.MQ_PREC_FP64: 1e-10}
+# a candidate replaces the defaults only when it is this much faster
+NOISE_MARGIN = 1.02
 
 
 def cache_path() -> str:
@@ -91,6 +94,20 @@ def coarse_candidates(best_knobs: Dict, resolved_precond: int, n_nodes: int = 0)
         depth += 1
     return [dict(best_knobs, mg_levels=lv, mg_coarse_sweeps=sw) for lv, sw in COARSE_VARIANTS
             if n_nodes == 0 or lv < depth]
+
+
+def refine_candidates(best_knobs: Dict, resolved_precond: int, precision: int) -> List[Dict]:
+    """Third stage: smoother weight x inner tolerance around a chosen coarse
+    hierarchy (multigrid with an explicit hierarchy only)."""
+    if resolved_precond != L.MQ_PRECOND_MULTIGRID or "mg_levels" not in best_knobs:
+        return []
+    rtols = [1e-5, 3e-6, 1e-6] if precision == L.MQ_PREC_MIXED else [1e-10]
+    out = []
+    for om, rt in itertools.product([0.7, 0.8, 0.9], rtols):
+        k = dict(best_knobs, mg_omega=om, inner_rtol=rt)
+        if k != best_knobs:
+            out.append(k)
+    return out
 
 
 def _load(path: str) -> Dict:
@@ -162,6 +179,14 @@ def autotune(problem, precision: int, steps_per_period: int = 32, n_periods: int
     for knobs in coarse_candidates(best["knobs"], best["resolved"]["precond"], problem.n_nodes):
         trial(knobs)
     best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
+    # third stage: the smoother weight and the inner tolerance again, with the
+    # chosen coarse hierarchy (the first stage timed them with the default one,
+    # and the best weight depends on how many coarsest sweeps follow)
+    for knobs in refine_candidates(best["knobs"], best["resolved"]["precond"], precision):
+        trial(knobs)
+    best = max((t for t in trials if t["agree"]), key=lambda t: t["rate"])
+    if best["rate"] < NOISE_MARGIN * trials[0]["rate"]:
+        best = trials[0]  # within the timing noise of the defaults: keep them
     db = _load(path)
     db[key] = {"knobs": best["knobs"], "rate": best["rate"], "default_rate": trials[0]["rate"],
                "resolved": best["resolved"], "trials": len(trials),
